@@ -1,0 +1,569 @@
+/*
+ * npx_oracle.c -- FP64 CPU oracle of the NeoPhysIx per-frame step.
+ *
+ * TEST INFRASTRUCTURE ONLY (see npx_oracle.h). Plain loops in the order the
+ * step is defined; no blocking, fusion or reordering. Where the paper is
+ * silent, the reading used is named in the comment of the part it fixes.
+ *
+ * The step, n -> n+1 at t = n dt, for one robot treated as a single rigid body
+ * made of mass points (Sec. III-A, III-B):
+ *   S0  controller: commanded joint angles (the user's move() of Fig. 1)
+ *   S1  point-cloud collision against the height-map look-up table (Sec. III-A)
+ *   S2  normal penalty force per contact point, summed to force and torque
+ *       (the paper gives no normal response; reading: Hunt-Crossley penalty)
+ *   S3  joint-angle determination: joints are set kinematically, the robot
+ *       stays one rigid body and its world CoG is kept (Sec. III-B)
+ *   S4  trial integration (semi-implicit Euler) to the predicted points P*
+ *   S5  friction set: points in contact at both t and t+1 (Sec. III-C, eq. 3)
+ *   S6  least-squares displacement + rotation of the contact points, the
+ *       linearised rigid map (eqs. 1-2) solved through the normal equations
+ *       (eqs. 4-6), in the ground plane, about the predicted CoG
+ *   S7  cap by the maximum static friction mu F_N (Sec. III-C)
+ *   S8  move the robot back by the (capped) fitted motion, with the matching
+ *       velocity change, and commit
+ *   S9  telemetry and health flags (not physics)
+ */
+#include "npx_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+int orc_version(void) { return 1; }
+
+/* ------------------------------------------------------------------------- */
+/* small dense linear algebra, row-major 3x3                                  */
+/* ------------------------------------------------------------------------- */
+
+static void m3_mul(const double* A, const double* B, double* C) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += A[3 * i + k] * B[3 * k + j];
+      C[3 * i + j] = s;
+    }
+}
+
+static void m3_vec(const double* A, const double* x, double* y) {
+  for (int i = 0; i < 3; ++i) y[i] = A[3 * i] * x[0] + A[3 * i + 1] * x[1] + A[3 * i + 2] * x[2];
+}
+
+static void m3_transpose(const double* A, double* T) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) T[3 * j + i] = A[3 * i + j];
+}
+
+static void cross3(const double* a, const double* b, double* c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static double det3(const double* A) {
+  return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+         A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+
+/* Gaussian elimination with partial pivoting on a copy of A. Returns 0 when a
+ * pivot vanishes. */
+static int solve3(const double* A_in, const double* b_in, double* x) {
+  double A[9], b[3];
+  memcpy(A, A_in, sizeof A);
+  memcpy(b, b_in, sizeof b);
+  for (int col = 0; col < 3; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < 3; ++r)
+      if (fabs(A[3 * r + col]) > fabs(A[3 * piv + col])) piv = r;
+    if (A[3 * piv + col] == 0.0) return 0;
+    if (piv != col) {
+      for (int k = 0; k < 3; ++k) {
+        double t = A[3 * col + k];
+        A[3 * col + k] = A[3 * piv + k];
+        A[3 * piv + k] = t;
+      }
+      double t = b[col];
+      b[col] = b[piv];
+      b[piv] = t;
+    }
+    for (int r = col + 1; r < 3; ++r) {
+      double f = A[3 * r + col] / A[3 * col + col];
+      for (int k = col; k < 3; ++k) A[3 * r + k] -= f * A[3 * col + k];
+      b[r] -= f * b[col];
+    }
+  }
+  for (int r = 2; r >= 0; --r) {
+    double s = b[r];
+    for (int k = r + 1; k < 3; ++k) s -= A[3 * r + k] * x[k];
+    x[r] = s / A[3 * r + r];
+  }
+  return 1;
+}
+
+/* Rotation matrix of a unit quaternion (w, x, y, z). */
+static void quat_to_mat(const double* Q, double* R) {
+  double w = Q[0], x = Q[1], y = Q[2], z = Q[3];
+  R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+  R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+  R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+}
+
+/* Hamilton product a (x) b. */
+static void quat_mul(const double* a, const double* b, double* o) {
+  double w = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+  double x = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+  double y = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+  double z = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+  o[0] = w; o[1] = x; o[2] = y; o[3] = z;
+}
+
+static void quat_normalize(double* Q) {
+  double n = sqrt(Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2] + Q[3] * Q[3]);
+  for (int i = 0; i < 4; ++i) Q[i] /= n;
+}
+
+/* Unit quaternion of the rotation vector th (angle |th| about th/|th|). */
+static void quat_exp(const double* th, double* o) {
+  double a = sqrt(th[0] * th[0] + th[1] * th[1] + th[2] * th[2]);
+  if (a < 1e-12) {
+    o[0] = 1.0; o[1] = 0.5 * th[0]; o[2] = 0.5 * th[1]; o[3] = 0.5 * th[2];
+    return;
+  }
+  double s = sin(0.5 * a) / a;
+  o[0] = cos(0.5 * a); o[1] = s * th[0]; o[2] = s * th[1]; o[3] = s * th[2];
+}
+
+/* Rotation by angle th about the unit axis a (Rodrigues' formula). */
+static void axis_angle(const double* a, double th, double* R) {
+  double c = cos(th), s = sin(th), C = 1.0 - c;
+  double x = a[0], y = a[1], z = a[2];
+  R[0] = c + x * x * C;     R[1] = x * y * C - z * s; R[2] = x * z * C + y * s;
+  R[3] = y * x * C + z * s; R[4] = c + y * y * C;     R[5] = y * z * C - x * s;
+  R[6] = z * x * C - y * s; R[7] = z * y * C + x * s; R[8] = c + z * z * C;
+}
+
+/* ------------------------------------------------------------------------- */
+/* forward kinematics and mass properties (Sec. III-A mass points, III-B)     */
+/* ------------------------------------------------------------------------- */
+
+/* Link l moves with its parent and turns by q[l-1] about its hinge, whose
+ * anchor and axis are given in the construction frame (createJoint, Sec. IV-B):
+ *   T_l(x) = T_parent(Rot(a_l, q)(x - o_l) + o_l),  T_0 = identity.
+ * Body points y_k = T_link(k)(rho_k). The CoG and inertia are the plain mass
+ * point sums. */
+void orc_fk(const orc_morph* m, const double* q, double* y, double* g_b, double* I_b,
+            double* mass) {
+  int L = m->n_links, N = m->n_points;
+  double* R = (double*)malloc(sizeof(double) * 9 * L);
+  double* t = (double*)malloc(sizeof(double) * 3 * L);
+  for (int i = 0; i < 9; ++i) R[i] = (i % 4 == 0) ? 1.0 : 0.0;
+  t[0] = t[1] = t[2] = 0.0;
+  for (int l = 1; l < L; ++l) {
+    const float* jt = m->joint + 8 * l;
+    int p = m->parent[l];
+    double o[3] = {jt[0], jt[1], jt[2]};
+    double a[3] = {jt[3], jt[4], jt[5]};
+    double an = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    a[0] /= an; a[1] /= an; a[2] /= an;
+    double Rj[9], Ro[3], u[3], w[3];
+    axis_angle(a, q[l - 1], Rj);
+    m3_mul(R + 9 * p, Rj, R + 9 * l);
+    m3_vec(Rj, o, Ro);
+    for (int i = 0; i < 3; ++i) u[i] = o[i] - Ro[i];
+    m3_vec(R + 9 * p, u, w);
+    for (int i = 0; i < 3; ++i) t[3 * l + i] = w[i] + t[3 * p + i];
+  }
+  double M = 0.0, gs[3] = {0, 0, 0};
+  for (int k = 0; k < N; ++k) {
+    const float* pt = m->points + 4 * k;
+    int l = m->pt_link[k];
+    double rho[3] = {pt[0], pt[1], pt[2]}, yk[3];
+    m3_vec(R + 9 * l, rho, yk);
+    for (int i = 0; i < 3; ++i) {
+      y[3 * k + i] = yk[i] + t[3 * l + i];
+      gs[i] += (double)pt[3] * y[3 * k + i];
+    }
+    M += pt[3];
+  }
+  for (int i = 0; i < 3; ++i) g_b[i] = gs[i] / M;
+  for (int i = 0; i < 9; ++i) I_b[i] = 0.0;
+  for (int k = 0; k < N; ++k) {
+    double mk = m->points[4 * k + 3];
+    double r[3] = {y[3 * k] - g_b[0], y[3 * k + 1] - g_b[1], y[3 * k + 2] - g_b[2]};
+    double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) I_b[3 * i + j] += mk * ((i == j ? rr : 0.0) - r[i] * r[j]);
+  }
+  *mass = M;
+  free(R);
+  free(t);
+}
+
+/* ------------------------------------------------------------------------- */
+/* height-map look-up (Sec. III-A)                                            */
+/* ------------------------------------------------------------------------- */
+
+/* The x-y coordinates are scaled by s and turned into integer indices of a 2-D
+ * table. Reading: index = floor(s (x - x0)), clamped onto the table (a NaN
+ * coordinate maps to cell 0). */
+static int cell_index(double u, int n) {
+  if (!(u >= 0.0)) return 0;
+  if (u >= (double)(n - 1)) return n - 1;
+  return (int)floor(u);
+}
+
+void orc_cell(const orc_params* p, double x, double y, int* i, int* j) {
+  *i = cell_index(p->hf_s * (x - p->hf_x0), p->hf_nx);
+  *j = cell_index(p->hf_s * (y - p->hf_y0), p->hf_ny);
+}
+
+double orc_height(const orc_params* p, double x, double y) {
+  int i, j;
+  orc_cell(p, x, y, &i, &j);
+  return (double)p->hf[(long)j * p->hf_nx + i];
+}
+
+/* ------------------------------------------------------------------------- */
+/* friction least squares (Sec. III-C, eqs. 1-6)                              */
+/* ------------------------------------------------------------------------- */
+
+/* Fit dst ~ [[1, -a3], [a3, 1]] src + (a1, a2) over the point pairs (eq. 2) by
+ * least squares (eq. 3). Each pair contributes two residual rows whose
+ * derivatives in (a1, a2, a3) are (1, 0, -y) and (0, 1, x); summing
+ * J^T J a = J^T (dst - src) gives the three linear equations (4)-(6).
+ * Reading: with one pair, or pairs with no spread (sum |src - mean|^2 <= n eps^2),
+ * the rotation is not determined and only the displacement is fitted. */
+int orc_lsq(int n, const double* src, const double* dst, double eps, double* a) {
+  a[0] = a[1] = a[2] = 0.0;
+  if (n <= 0) return 0;
+  double A[9] = {0}, b[3] = {0};
+  double sx = 0, sy = 0, s2 = 0;
+  for (int i = 0; i < n; ++i) {
+    double x = src[2 * i], y = src[2 * i + 1];
+    double dx = dst[2 * i] - x, dy = dst[2 * i + 1] - y;
+    double r1[3] = {1.0, 0.0, -y}; /* d/da of the x-residual */
+    double r2[3] = {0.0, 1.0, x};  /* d/da of the y-residual */
+    for (int u = 0; u < 3; ++u) {
+      for (int v = 0; v < 3; ++v) A[3 * u + v] += r1[u] * r1[v] + r2[u] * r2[v];
+      b[u] += r1[u] * dx + r2[u] * dy;
+    }
+    sx += x; sy += y; s2 += x * x + y * y;
+  }
+  double spread = s2 - (sx * sx + sy * sy) / n;
+  if (n >= 2 && spread > n * eps * eps && solve3(A, b, a)) return 3;
+  a[0] = b[0] / n;
+  a[1] = b[1] / n;
+  a[2] = 0.0;
+  return 2;
+}
+
+/* ------------------------------------------------------------------------- */
+/* the step                                                                   */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+  double *y, *r, *P, *Ps, *src, *dst;
+  int* kap;
+} work_t;
+
+static int work_alloc(work_t* w, int N) {
+  w->y = (double*)malloc(sizeof(double) * 3 * N);
+  w->r = (double*)malloc(sizeof(double) * 3 * N);
+  w->P = (double*)malloc(sizeof(double) * 3 * N);
+  w->Ps = (double*)malloc(sizeof(double) * 3 * N);
+  w->src = (double*)malloc(sizeof(double) * 2 * N);
+  w->dst = (double*)malloc(sizeof(double) * 2 * N);
+  w->kap = (int*)malloc(sizeof(int) * N);
+  return w->y && w->r && w->P && w->Ps && w->src && w->dst && w->kap;
+}
+
+static void work_free(work_t* w) {
+  free(w->y); free(w->r); free(w->P); free(w->Ps); free(w->src); free(w->dst); free(w->kap);
+}
+
+static int morph_ok(const orc_morph* m) {
+  if (!m || m->n_points <= 0 || m->n_links <= 0) return 0;
+  if (m->parent[0] != -1) return 0;
+  for (int l = 1; l < m->n_links; ++l)
+    if (m->parent[l] < 0 || m->parent[l] >= l) return 0;
+  for (int k = 0; k < m->n_points; ++k)
+    if (m->pt_link[k] < 0 || m->pt_link[k] >= m->n_links) return 0;
+  return 1;
+}
+
+/* S0: commanded angle of joint j at time t, clamped to its limits. */
+static double command(const orc_morph* m, const float* ctrl, int j, double t) {
+  const double two_pi = 6.283185307179586476925286766559;
+  double A = ctrl[3 * j], f = ctrl[3 * j + 1], phi = ctrl[3 * j + 2];
+  double qh = A * sin(two_pi * f * t + phi);
+  double lo = m->joint[8 * (j + 1) + 6], hi = m->joint[8 * (j + 1) + 7];
+  if (qh < lo) qh = lo;
+  if (qh > hi) qh = hi;
+  return qh;
+}
+
+/* Principal inertia test shared by the oracle's integrator: an inertia with
+ * det <= 1e-9 (trace/3)^3 (a point or a line of points) gets no angular
+ * acceleration. */
+static int inertia_regular(const double* I) {
+  double tr = (I[0] + I[4] + I[8]) / 3.0;
+  return tr > 0.0 && det3(I) > 1e-9 * tr * tr * tr;
+}
+
+static double torso_height(const orc_morph* m, const orc_params* p, const double* st,
+                           const double* g_b) {
+  (void)m;
+  double R[9], Rg[3];
+  quat_to_mat(st + ORC_Q, R);
+  m3_vec(R, g_b, Rg);
+  double o[3] = {st[ORC_C] - Rg[0], st[ORC_C + 1] - Rg[1], st[ORC_C + 2] - Rg[2]};
+  return o[2] - orc_height(p, o[0], o[1]);
+}
+
+static int step_ws(const orc_morph* m, const orc_params* p, const float* ctrl, double* st,
+                   double* diag, work_t* w) {
+  const int N = m->n_points, J = m->n_links - 1;
+  if (st[ORC_FLAGS] != 0.0) return 0; /* frozen instance */
+  const long n = (long)st[ORC_STEP];
+  const double dt = p->dt, t = (double)n * dt;
+  double* q = st + ORC_HDR;
+  double* q_prev = q + J;
+  double* c = st + ORC_C;
+  double* Q = st + ORC_Q;
+  double* v = st + ORC_V;
+  double* om = st + ORC_W;
+
+  /* body points about the CoG at the current joint angles */
+  double g_b[3], I_b[9], M;
+  orc_fk(m, q, w->y, g_b, I_b, &M);
+  for (int k = 0; k < N; ++k)
+    for (int i = 0; i < 3; ++i) w->r[3 * k + i] = w->y[3 * k + i] - g_b[i];
+
+  /* S1: detection at P^n (strictly below the stored height is contact) */
+  double R[9];
+  quat_to_mat(Q, R);
+  int n_contact = 0;
+  for (int k = 0; k < N; ++k) {
+    double Rr[3];
+    m3_vec(R, w->r + 3 * k, Rr);
+    for (int i = 0; i < 3; ++i) w->P[3 * k + i] = c[i] + Rr[i];
+    double d = orc_height(p, w->P[3 * k], w->P[3 * k + 1]) - w->P[3 * k + 2];
+    w->kap[k] = d > 0.0;
+    n_contact += w->kap[k];
+  }
+
+  /* S2: per-point normal force along +z, summed to force and torque about c */
+  double F = 0.0, tau[3] = {0, 0, 0};
+  for (int k = 0; k < N; ++k) {
+    if (!w->kap[k]) continue;
+    double arm[3] = {w->P[3 * k] - c[0], w->P[3 * k + 1] - c[1], w->P[3 * k + 2] - c[2]};
+    double wxa[3];
+    cross3(om, arm, wxa);
+    double uz = v[2] + wxa[2];
+    double d = orc_height(p, w->P[3 * k], w->P[3 * k + 1]) - w->P[3 * k + 2];
+    double f = p->k_n * d * (1.0 - p->zeta * uz);
+    if (f < 0.0) f = 0.0;
+    double fz[3] = {0.0, 0.0, f}, tk[3];
+    cross3(arm, fz, tk);
+    F += f;
+    for (int i = 0; i < 3; ++i) tau[i] += tk[i];
+  }
+
+  /* S3: joint-angle determination every K steps; c, Q, v, omega are kept */
+  if (n % p->K == 0) {
+    for (int j = 0; j < J; ++j) {
+      q_prev[j] = q[j];
+      q[j] = command(m, ctrl, j, t);
+    }
+    orc_fk(m, q, w->y, g_b, I_b, &M);
+    for (int k = 0; k < N; ++k)
+      for (int i = 0; i < 3; ++i) w->r[3 * k + i] = w->y[3 * k + i] - g_b[i];
+  }
+
+  /* S4: trial integration, semi-implicit Euler */
+  double v1[3], om1[3], c1[3], Q1[4];
+  for (int i = 0; i < 3; ++i) v1[i] = v[i] + dt * p->g[i];
+  v1[2] += dt * F / M;
+  {
+    double Rt[9], tmp[9], Iw[9], Lw[3], gyro[3], rhs[3], acc[3] = {0, 0, 0};
+    m3_transpose(R, Rt);
+    m3_mul(R, I_b, tmp);
+    m3_mul(tmp, Rt, Iw);
+    m3_vec(Iw, om, Lw);
+    cross3(om, Lw, gyro);
+    for (int i = 0; i < 3; ++i) rhs[i] = tau[i] - gyro[i];
+    if (!(inertia_regular(I_b) && solve3(Iw, rhs, acc))) acc[0] = acc[1] = acc[2] = 0.0;
+    for (int i = 0; i < 3; ++i) om1[i] = om[i] + dt * acc[i];
+  }
+  for (int i = 0; i < 3; ++i) c1[i] = c[i] + dt * v1[i];
+  {
+    double th[3] = {dt * om1[0], dt * om1[1], dt * om1[2]}, dq[4];
+    quat_exp(th, dq);
+    quat_mul(dq, Q, Q1);
+    quat_normalize(Q1);
+  }
+  double R1[9];
+  quat_to_mat(Q1, R1);
+
+  /* S5: predicted points P*, friction set = contact at both P^n and P* */
+  int nS = 0;
+  for (int k = 0; k < N; ++k) {
+    double Rr[3];
+    m3_vec(R1, w->r + 3 * k, Rr);
+    for (int i = 0; i < 3; ++i) w->Ps[3 * k + i] = c1[i] + Rr[i];
+    double ds = orc_height(p, w->Ps[3 * k], w->Ps[3 * k + 1]) - w->Ps[3 * k + 2];
+    if (w->kap[k] && ds > 0.0) {
+      /* ground-plane coordinates about the predicted CoG c1 */
+      w->src[2 * nS] = w->P[3 * k] - c1[0];
+      w->src[2 * nS + 1] = w->P[3 * k + 1] - c1[1];
+      w->dst[2 * nS] = w->Ps[3 * k] - c1[0];
+      w->dst[2 * nS + 1] = w->Ps[3 * k + 1] - c1[1];
+      ++nS;
+    }
+  }
+
+  /* S6: least-squares displacement and rotation of the contact points */
+  double a[3];
+  orc_lsq(nS, w->src, w->dst, p->eps, a);
+
+  /* S7: cap by the maximum static friction mu F_N */
+  double lam = 0.0, Ff = 0.0;
+  if (nS > 0) {
+    double sbx = 0.0, sby = 0.0;
+    for (int i = 0; i < nS; ++i) {
+      sbx += w->dst[2 * i] - w->src[2 * i];
+      sby += w->dst[2 * i + 1] - w->src[2 * i + 1];
+    }
+    sbx /= nS;
+    sby /= nS;
+    Ff = M * sqrt(sbx * sbx + sby * sby) / (dt * dt);
+    if (isinf(p->mu) || Ff <= p->mu * F) lam = 1.0;
+    else lam = p->mu * F / Ff;
+  }
+
+  /* S8: move back by the capped fitted motion (translation, then yaw about the
+   * CoG) and remove the matching velocity */
+  double a3 = a[2] < -1.0 ? -1.0 : (a[2] > 1.0 ? 1.0 : a[2]);
+  double alpha = asin(a3);
+  double Q2[4];
+  {
+    double half = -0.5 * lam * alpha;
+    double qz[4] = {cos(half), 0.0, 0.0, sin(half)};
+    quat_mul(qz, Q1, Q2);
+  }
+  c[0] = c1[0] - lam * a[0];
+  c[1] = c1[1] - lam * a[1];
+  c[2] = c1[2];
+  for (int i = 0; i < 4; ++i) Q[i] = Q2[i];
+  v[0] = v1[0] - lam * a[0] / dt;
+  v[1] = v1[1] - lam * a[1] / dt;
+  v[2] = v1[2];
+  om[0] = om1[0];
+  om[1] = om1[1];
+  om[2] = om1[2] - lam * alpha / dt;
+
+  /* S9: telemetry and health */
+  st[ORC_TELE + 0] += torso_height(m, p, st, g_b);
+  st[ORC_TELE + 1] += n_contact;
+  st[ORC_TELE + 2] += (nS > 0 && lam < 1.0) ? 1.0 : 0.0;
+  int bad = 0;
+  for (int i = 0; i < 13; ++i)
+    if (!isfinite(st[i])) bad |= ORC_FLAG_NONFINITE;
+  double vv = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  double ww = sqrt(om[0] * om[0] + om[1] * om[1] + om[2] * om[2]);
+  if (vv > 50.0 || ww > 500.0) bad |= ORC_FLAG_SPEED;
+  st[ORC_FLAGS] = (double)bad;
+  st[ORC_STEP] = (double)(n + 1);
+
+  if (diag) {
+    diag[ORC_D_FN] = F;
+    for (int i = 0; i < 3; ++i) diag[ORC_D_TAU + i] = tau[i];
+    diag[ORC_D_NC] = n_contact;
+    diag[ORC_D_NS] = nS;
+    for (int i = 0; i < 3; ++i) diag[ORC_D_A + i] = a[i];
+    diag[ORC_D_LAMBDA] = lam;
+    diag[ORC_D_FF] = Ff;
+  }
+  return 0;
+}
+
+int orc_init_state(const orc_morph* m, const orc_params* p, const float* ctrl,
+                   const float* pose, double* st) {
+  (void)p;
+  if (!morph_ok(m)) return -1;
+  const int J = m->n_links - 1, N = m->n_points;
+  memset(st, 0, sizeof(double) * ORC_STATE_LEN(J));
+  double* q = st + ORC_HDR;
+  for (int j = 0; j < J; ++j) {
+    q[j] = command(m, ctrl, j, 0.0);
+    q[J + j] = q[j];
+  }
+  double Q[4] = {pose[3], pose[4], pose[5], pose[6]};
+  quat_normalize(Q);
+  double* y = (double*)malloc(sizeof(double) * 3 * N);
+  double g_b[3], I_b[9], M, R[9], Rg[3];
+  orc_fk(m, q, y, g_b, I_b, &M);
+  free(y);
+  quat_to_mat(Q, R);
+  m3_vec(R, g_b, Rg);
+  for (int i = 0; i < 3; ++i) st[ORC_C + i] = (double)pose[i] + Rg[i];
+  for (int i = 0; i < 4; ++i) st[ORC_Q + i] = Q[i];
+  return 0;
+}
+
+void orc_points(const orc_morph* m, const double* st, double* P) {
+  const int N = m->n_points, J = m->n_links - 1;
+  (void)J;
+  double* y = (double*)malloc(sizeof(double) * 3 * N);
+  double g_b[3], I_b[9], M, R[9];
+  orc_fk(m, st + ORC_HDR, y, g_b, I_b, &M);
+  quat_to_mat(st + ORC_Q, R);
+  for (int k = 0; k < N; ++k) {
+    double r[3] = {y[3 * k] - g_b[0], y[3 * k + 1] - g_b[1], y[3 * k + 2] - g_b[2]}, Rr[3];
+    m3_vec(R, r, Rr);
+    for (int i = 0; i < 3; ++i) P[3 * k + i] = st[ORC_C + i] + Rr[i];
+  }
+  free(y);
+}
+
+int orc_step(const orc_morph* m, const orc_params* p, const float* ctrl, double* st,
+             double* diag) {
+  if (!morph_ok(m) || p->K < 1 || p->dt <= 0.0) return -1;
+  work_t w;
+  if (!work_alloc(&w, m->n_points)) {
+    work_free(&w);
+    return -1;
+  }
+  int rc = step_ws(m, p, ctrl, st, diag, &w);
+  work_free(&w);
+  return rc;
+}
+
+int orc_run(const orc_morph* m, const orc_params* p, const float* ctrl, double* st,
+            long n_steps) {
+  if (!morph_ok(m) || p->K < 1 || p->dt <= 0.0 || n_steps < 0) return -1;
+  work_t w;
+  if (!work_alloc(&w, m->n_points)) {
+    work_free(&w);
+    return -1;
+  }
+  for (long s = 0; s < n_steps; ++s) step_ws(m, p, ctrl, st, NULL, &w);
+  work_free(&w);
+  return 0;
+}
+
+int orc_run_batch(int n_inst, const orc_morph* morphs, const int* inst_morph,
+                  const orc_params* p, const float* const* ctrl, double* const* states,
+                  long n_steps, int n_threads) {
+  int used = 1;
+#ifdef _OPENMP
+  if (n_threads <= 0) n_threads = omp_get_max_threads();
+  used = n_threads;
+#pragma omp parallel for schedule(static) num_threads(n_threads)
+#endif
+  for (int i = 0; i < n_inst; ++i)
+    orc_run(&morphs[inst_morph[i]], p, ctrl[i], states[i], n_steps);
+  return used;
+}

@@ -1,0 +1,119 @@
+/*
+ * npx_oracle.h -- FP64 CPU oracle of the NeoPhysIx per-frame step
+ * (Fischer & Ihme, "NeoPhysIx: An Ultra Fast 3D Physical Simulator as
+ * Development Tool for AI Algorithms", arXiv 2411.05799).
+ *
+ * TEST INFRASTRUCTURE ONLY. This library is the plain, slow, obviously correct
+ * reference that the GPU path is checked against. Only the tests, the smoke
+ * check and the benchmark's CPU-baseline leg may load it. It shares no code,
+ * header, table or constant with the GPU library; both read the same float32
+ * input arrays and nothing else.
+ *
+ * Every quantity is double precision, round-to-nearest, built without
+ * fast-math and with floating-point contraction off.
+ *
+ * Parity pins: every step part is pinned by a closed form, an invariant, a
+ * textbook routine or brute force (see tests/test_oracle_pins.py). The whole
+ * step composed over long chaotic horizons has no closed form: beyond those
+ * pins its parity is unpinned.
+ */
+#ifndef NPX_ORACLE_H
+#define NPX_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One robot: mass points in the construction frame and its hinge tree. */
+typedef struct {
+  int n_points;
+  int n_links;
+  const float* points;  /* [n_points][4] x, y, z, mass */
+  const int* pt_link;   /* [n_points] */
+  const int* parent;    /* [n_links], parent[0] = -1, parent[l] < l */
+  const float* joint;   /* [n_links][8] anchor xyz, axis xyz, lo, hi */
+} orc_morph;
+
+typedef struct {
+  double dt;
+  int K;          /* joint-update interval (steps) */
+  double g[3];
+  double mu;      /* friction coefficient, +inf = always stick */
+  double k_n;     /* normal stiffness per point */
+  double zeta;    /* Hunt-Crossley damping */
+  double eps;     /* LSQ spread threshold */
+  int hf_nx, hf_ny;
+  double hf_s, hf_x0, hf_y0;
+  const float* hf; /* [hf_ny][hf_nx] */
+} orc_params;
+
+/* Per-instance state vector (double), fixed offsets; q and q_prev follow. */
+enum {
+  ORC_C = 0,       /* world centre of gravity (3) */
+  ORC_Q = 3,       /* torso orientation quaternion w, x, y, z (4) */
+  ORC_V = 7,       /* CoG velocity (3) */
+  ORC_W = 10,      /* angular velocity, world frame (3) */
+  ORC_STEP = 13,   /* step counter n, t = n * dt */
+  ORC_FLAGS = 14,  /* health flags; non-zero freezes the instance */
+  ORC_TELE = 15,   /* telemetry accumulators (4) */
+  ORC_HDR = 19     /* q[J] starts here, then q_prev[J] */
+};
+#define ORC_STATE_LEN(J) (ORC_HDR + 2 * (J))
+
+/* Per-step diagnostics written by orc_step when diag != NULL. */
+enum {
+  ORC_D_FN = 0,      /* total normal force F_N */
+  ORC_D_TAU = 1,     /* torque about the CoG (3) */
+  ORC_D_NC = 4,      /* points in contact at P^n */
+  ORC_D_NS = 5,      /* points in the friction set */
+  ORC_D_A = 6,       /* a1, a2, a3 (3) */
+  ORC_D_LAMBDA = 9,  /* static-friction cap factor */
+  ORC_D_FF = 10,     /* friction force estimate */
+  ORC_D_LEN = 11
+};
+
+/* Flag bits. */
+#define ORC_FLAG_NONFINITE 1
+#define ORC_FLAG_SPEED 2
+
+int orc_version(void);
+
+/* Forward kinematics at joint angles q: torso-frame points y [N][3], CoG g_b,
+ * inertia about the CoG I_b [3][3] (row-major), total mass. */
+void orc_fk(const orc_morph* m, const double* q, double* y, double* g_b, double* I_b,
+            double* mass);
+
+/* Height-map look-up: cell indices and the stored height. */
+void orc_cell(const orc_params* p, double x, double y, int* i, int* j);
+double orc_height(const orc_params* p, double x, double y);
+
+/* Friction least squares on n point pairs (ground-plane coordinates):
+ * src [n][2] at t, dst [n][2] at t+1. Writes a1, a2, a3. Returns the number of
+ * unknowns solved (0 none, 2 translation only, 3 full). */
+int orc_lsq(int n, const double* src, const double* dst, double eps, double* a);
+
+/* State from a start pose [7] = torso origin xyz + quaternion, at rest. */
+int orc_init_state(const orc_morph* m, const orc_params* p, const float* ctrl,
+                   const float* pose, double* state);
+
+/* World positions of all points for a state [N][3]. */
+void orc_points(const orc_morph* m, const double* state, double* P);
+
+/* One step n -> n+1. Returns 0, or -1 on invalid input. */
+int orc_step(const orc_morph* m, const orc_params* p, const float* ctrl, double* state,
+             double* diag);
+
+/* n_steps steps of one instance. */
+int orc_run(const orc_morph* m, const orc_params* p, const float* ctrl, double* state,
+            long n_steps);
+
+/* n_steps steps of n_inst independent instances on up to n_threads threads
+ * (n_threads <= 0: all). Returns the thread count used. */
+int orc_run_batch(int n_inst, const orc_morph* morphs, const int* inst_morph,
+                  const orc_params* p, const float* const* ctrl, double* const* states,
+                  long n_steps, int n_threads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

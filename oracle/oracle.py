@@ -1,0 +1,191 @@
+"""ctypes binding of the FP64 oracle (npx_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg use it; the GPU library never does.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnpx_oracle.so")
+SRC = os.path.join(HERE, "npx_oracle.c")
+
+# state-vector offsets (mirror of the enum in npx_oracle.h)
+C_, Q_, V_, W_, STEP, FLAGS, TELE, HDR = 0, 3, 7, 10, 13, 14, 15, 19
+D_FN, D_TAU, D_NC, D_NS, D_A, D_LAMBDA, D_FF, D_LEN = 0, 1, 4, 5, 6, 9, 10, 11
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc: FP64, -O2, no fast-math, contraction off, OpenMP."""
+    if not force and os.path.exists(LIB_PATH) and os.path.getmtime(LIB_PATH) >= os.path.getmtime(SRC):
+        return LIB_PATH
+    tmp = LIB_PATH + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+                           "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
+                           SRC, "-o", tmp, "-lm"])
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class _Morph(C.Structure):
+    _fields_ = [("n_points", C.c_int), ("n_links", C.c_int),
+                ("points", C.POINTER(C.c_float)), ("pt_link", C.POINTER(C.c_int)),
+                ("parent", C.POINTER(C.c_int)), ("joint", C.POINTER(C.c_float))]
+
+
+class _Params(C.Structure):
+    _fields_ = [("dt", C.c_double), ("K", C.c_int), ("g", C.c_double * 3), ("mu", C.c_double),
+                ("k_n", C.c_double), ("zeta", C.c_double), ("eps", C.c_double),
+                ("hf_nx", C.c_int), ("hf_ny", C.c_int), ("hf_s", C.c_double),
+                ("hf_x0", C.c_double), ("hf_y0", C.c_double), ("hf", C.POINTER(C.c_float))]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        dp = C.POINTER(C.c_double)
+        fp = C.POINTER(C.c_float)
+        L.orc_fk.argtypes = [C.POINTER(_Morph), dp, dp, dp, dp, dp]
+        L.orc_cell.argtypes = [C.POINTER(_Params), C.c_double, C.c_double,
+                               C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.orc_height.argtypes = [C.POINTER(_Params), C.c_double, C.c_double]
+        L.orc_height.restype = C.c_double
+        L.orc_lsq.argtypes = [C.c_int, dp, dp, C.c_double, dp]
+        L.orc_init_state.argtypes = [C.POINTER(_Morph), C.POINTER(_Params), fp, fp, dp]
+        L.orc_points.argtypes = [C.POINTER(_Morph), dp, dp]
+        L.orc_step.argtypes = [C.POINTER(_Morph), C.POINTER(_Params), fp, dp, dp]
+        L.orc_run.argtypes = [C.POINTER(_Morph), C.POINTER(_Params), fp, dp, C.c_long]
+        L.orc_run_batch.argtypes = [C.c_int, C.POINTER(_Morph), C.POINTER(C.c_int),
+                                    C.POINTER(_Params), C.POINTER(fp), C.POINTER(dp),
+                                    C.c_long, C.c_int]
+        _lib = L
+    return _lib
+
+
+def _fptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _iptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int))
+
+
+class OracleMorph:
+    def __init__(self, m):
+        self.points = np.ascontiguousarray(m.points, dtype=np.float32)
+        self.pt_link = np.ascontiguousarray(m.pt_link, dtype=np.int32)
+        self.parent = np.ascontiguousarray(m.parent, dtype=np.int32)
+        self.joint = np.ascontiguousarray(m.joint, dtype=np.float32)
+        self.n_points = int(self.points.shape[0])
+        self.n_links = int(self.parent.shape[0])
+        self.n_joints = self.n_links - 1
+        self.c = _Morph(self.n_points, self.n_links, _fptr(self.points), _iptr(self.pt_link),
+                        _iptr(self.parent), _fptr(self.joint))
+
+    def fk(self, q):
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        y = np.zeros((self.n_points, 3))
+        g = np.zeros(3)
+        I = np.zeros((3, 3))
+        M = np.zeros(1)
+        lib().orc_fk(C.byref(self.c), _dptr(q), _dptr(y), _dptr(g), _dptr(I), _dptr(M))
+        return y, g, I, float(M[0])
+
+
+class OracleParams:
+    def __init__(self, params, hf):
+        self.H = np.ascontiguousarray(hf.H, dtype=np.float32)
+        g = (C.c_double * 3)(*[float(x) for x in params.g])
+        self.c = _Params(float(params.dt), int(params.K), g, float(params.mu), float(params.k_n),
+                         float(params.zeta), float(params.eps), int(hf.nx), int(hf.ny),
+                         float(hf.s), float(hf.x0), float(hf.y0), _fptr(self.H))
+
+    def cell(self, x, y):
+        i, j = C.c_int(), C.c_int()
+        lib().orc_cell(C.byref(self.c), float(x), float(y), C.byref(i), C.byref(j))
+        return i.value, j.value
+
+    def height(self, x, y):
+        return lib().orc_height(C.byref(self.c), float(x), float(y))
+
+
+def lsq(src, dst, eps=1e-4):
+    src = np.ascontiguousarray(src, dtype=np.float64).reshape(-1, 2)
+    dst = np.ascontiguousarray(dst, dtype=np.float64).reshape(-1, 2)
+    a = np.zeros(3)
+    k = lib().orc_lsq(int(src.shape[0]), _dptr(src), _dptr(dst), float(eps), _dptr(a))
+    return a, k
+
+
+class OracleWorld:
+    """A workload on the oracle: one float64 state vector per instance."""
+
+    def __init__(self, w):
+        self.w = w
+        self.morphs = [OracleMorph(m) for m in w.morphs]
+        self.params = OracleParams(w.params, w.hf)
+        self.ctrl = [np.ascontiguousarray(c, dtype=np.float32) for c in w.ctrl]
+        self.inst_morph = np.ascontiguousarray(w.inst_morph, dtype=np.int32)
+        self._cmorphs = (_Morph * len(self.morphs))(*[m.c for m in self.morphs])
+
+    def morph_of(self, i):
+        return self.morphs[int(self.inst_morph[i])]
+
+    def init_state(self, i):
+        m = self.morph_of(i)
+        st = np.zeros(HDR + 2 * m.n_joints)
+        pose = np.ascontiguousarray(self.w.pose[i], dtype=np.float32)
+        rc = lib().orc_init_state(C.byref(m.c), C.byref(self.params.c), _fptr(self.ctrl[i]),
+                                  _fptr(pose), _dptr(st))
+        assert rc == 0, "invalid morphology"
+        return st
+
+    def init_states(self):
+        return [self.init_state(i) for i in range(self.w.n_instances)]
+
+    def step(self, i, st, diag=False):
+        m = self.morph_of(i)
+        d = np.zeros(D_LEN) if diag else None
+        rc = lib().orc_step(C.byref(m.c), C.byref(self.params.c), _fptr(self.ctrl[i]), _dptr(st),
+                            _dptr(d) if diag else None)
+        assert rc == 0
+        return d
+
+    def run(self, i, st, n_steps):
+        m = self.morph_of(i)
+        rc = lib().orc_run(C.byref(m.c), C.byref(self.params.c), _fptr(self.ctrl[i]), _dptr(st),
+                           int(n_steps))
+        assert rc == 0
+
+    def run_batch(self, states, n_steps, idx=None, threads=0):
+        """Advance states[k] (instance idx[k]) by n_steps on `threads` host threads."""
+        idx = np.arange(len(states)) if idx is None else np.asarray(idx)
+        n = len(states)
+        im = np.ascontiguousarray(self.inst_morph[idx], dtype=np.int32)
+        fp = C.POINTER(C.c_float)
+        dp = C.POINTER(C.c_double)
+        cptr = (fp * n)(*[_fptr(self.ctrl[int(i)]) for i in idx])
+        sptr = (dp * n)(*[_dptr(s) for s in states])
+        return lib().orc_run_batch(n, self._cmorphs, _iptr(im), C.byref(self.params.c), cptr, sptr,
+                                   int(n_steps), int(threads))
+
+    def points(self, i, st):
+        m = self.morph_of(i)
+        P = np.zeros((m.n_points, 3))
+        lib().orc_points(C.byref(m.c), _dptr(np.ascontiguousarray(st)), _dptr(P))
+        return P
