@@ -1,0 +1,185 @@
+/*
+ * npx.h -- C ABI of the MI355X-native batched legged-robot step of NeoPhysIx
+ * (Fischer & Ihme, arXiv 2411.05799).
+ *
+ * A robot is a set of mass points grouped into rigid links joined by hinges
+ * (Sec. III-A, IV-A/B). Many robots ("instances") are stepped together on one
+ * GPU; each step is the paper's frame: point-cloud collision against a
+ * height-map look-up table (Sec. III-A), kinematic joint-angle determination
+ * (Sec. III-B), friction estimated by least squares of the contact-point
+ * motion (Sec. III-C, eqs. 1-6) capped by the maximum static friction, and
+ * integration. The user's move() of Fig. 1 becomes controller data.
+ *
+ * Conventions for every entry point:
+ *  - SI units, z up, right-hand rule for hinge angles, quaternions (w,x,y,z).
+ *  - Every call returns npx_status (NPX_OK = 0); on failure npx_last_error()
+ *    holds a thread-local message. No exception crosses the ABI.
+ *  - Host pointers are only read during the call; the world copies what it
+ *    needs. Device pointers (the *_on_device flags) must be HIP device memory
+ *    of the world's device and stay valid only for the call.
+ *  - Per-instance fields are struct-of-arrays: component-major [comp][I].
+ *  - npx_step_n is asynchronous on the given HIP stream; npx_read_state and
+ *    npx_write_state first synchronise the stream of the last npx_step_n.
+ *    Kernel faults surface as NPX_EHIP at the next synchronising call.
+ *  - Numerical blow-ups are not errors: the instance is flagged (field
+ *    NPX_F_FLAGS) and frozen, the others continue.
+ */
+#ifndef NPX_H
+#define NPX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NPX_OK = 0,
+  NPX_EINVAL = -1,       /* bad argument or inconsistent tables */
+  NPX_ENOMEM = -2,       /* device or host allocation failed */
+  NPX_EHIP = -3,         /* a HIP runtime call or kernel failed */
+  NPX_ESTATE = -4,       /* call not valid in the object's current state */
+  NPX_EUNSUPPORTED = -5  /* shape beyond what the kernels are built for */
+} npx_status;
+
+#define NPX_MAX_JOINTS 63    /* links per robot <= 64 */
+#define NPX_MAX_POINTS 1024  /* mass points per robot */
+
+const char* npx_last_error(void);
+int npx_version(void);
+
+/* ---------------------------------------------------------------------- */
+/* Morphology tables (the finalised robot of Sec. IV, construction frame) */
+/* ---------------------------------------------------------------------- */
+/* points  [n_points][4]: x, y, z (construction frame = torso frame at the zero
+ *         pose) and mass of each mass point (Sec. III-A).
+ * pt_link [n_points]: link that owns the point; link 0 is the torso.
+ * parent  [n_links]: parent link, parent[0] = -1, parent[l] < l.
+ * joint   [n_links][8]: hinge of link l (createJoint, Sec. IV-B / Appendix):
+ *         anchor xyz and axis xyz in the construction frame, then the lower
+ *         and upper limit in rad (|limit| >= 1e30 means none). Row 0 unused.
+ *         Joint j drives link j+1; J = n_links - 1. */
+typedef struct {
+  int32_t n_points;
+  int32_t n_links;
+  const float* points;
+  const int32_t* pt_link;
+  const int32_t* parent;
+  const float* joint;
+} npx_morph_tables;
+
+/* ---------------------------------------------------------------------- */
+/* World: instances, terrain, physical constants                          */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+  double dt;              /* frame length, s (> 0) */
+  int32_t joint_interval; /* joints are set every K frames (Sec. III-B), K >= 1 */
+  double g[3];            /* gravity */
+  double mu;              /* friction coefficient; +inf = pure stick */
+  double k_n;             /* normal penalty stiffness per contact point, N/m */
+  double zeta;            /* Hunt-Crossley damping, s/m */
+  double eps_lsq;         /* rotation is fitted only if the contact spread > eps, m */
+  /* height-map look-up table (Sec. III-A): cell (i, j) covers
+   * [x0 + i/s, x0 + (i+1)/s) x [y0 + j/s, y0 + (j+1)/s); outside clamps. */
+  int32_t hf_nx, hf_ny;
+  double hf_s, hf_x0, hf_y0;
+  const float* hf_heights; /* host [hf_ny][hf_nx] */
+  int64_t n_instances;
+  int32_t n_morphs;
+  const npx_morph_tables* morphs;  /* host [n_morphs] */
+  const int32_t* instance_morph;   /* host [n_instances] */
+  const float* init_pose;          /* host [n_instances][7]: torso-origin xyz, quaternion;
+                                      the robot starts at rest with q = q_cmd(0) and its
+                                      CoG where that pose puts it */
+  const float* ctrl;               /* host [n_instances][J_max][3] sinusoid controller
+                                      (see npx_set_controller), J_max = max(1, max
+                                      n_links - 1); NULL = all zero */
+} npx_world_desc;
+
+typedef struct npx_world npx_world;
+
+/* Creates a world on the current HIP device; copies every host input. */
+npx_status npx_create_world(const npx_world_desc* desc, npx_world** out);
+
+/* NULL-safe. Waits for the world's pending work, then frees it. */
+void npx_destroy_world(npx_world* w);
+
+/* Sizes: instances, joint stride J_max (max joints over morphologies) and
+ * N_max (max points). Any pointer may be NULL. */
+npx_status npx_world_dims(const npx_world* w, int64_t* n_instances, int32_t* j_max,
+                          int32_t* n_max);
+
+/* Controller (the user's move() of Fig. 1, as data). Replaces the parameters
+ * for the frames that follow; the state is not touched.
+ * kind NPX_CTRL_SINUSOID: params [n_instances][J_max][3] = (A, f, phi): joint j
+ * is commanded A sin(2 pi f t + phi) rad at t = n dt, clamped to its limits.
+ * n_floats must equal n_instances * J_max * 3. */
+#define NPX_CTRL_SINUSOID 0
+npx_status npx_set_controller(npx_world* w, int kind, const float* params, size_t n_floats,
+                              int params_on_device);
+
+/* Advances every instance by n frames (n >= 0), asynchronously on hip_stream
+ * (a hipStream_t; NULL = default stream). */
+npx_status npx_step_n(npx_world* w, int64_t n, void* hip_stream);
+
+/* State fields, SoA [comp][n_instances]. */
+enum {
+  NPX_F_COG = 0,        /* float [3][I]  world centre of gravity */
+  NPX_F_QUAT = 1,       /* float [4][I]  torso orientation (w,x,y,z) */
+  NPX_F_VEL = 2,        /* float [3][I]  CoG velocity */
+  NPX_F_OMEGA = 3,      /* float [3][I]  angular velocity, world frame */
+  NPX_F_JOINT = 4,      /* float [J_max][I] applied joint angles */
+  NPX_F_JOINT_PREV = 5, /* float [J_max][I] joint angles before the last update */
+  NPX_F_STEP = 6,       /* int32 [I] frame counter n (t = n dt) */
+  NPX_F_FLAGS = 7,      /* int32 [I] health flags, non-zero = frozen */
+  NPX_F_TELE = 8,       /* double [4][I] telemetry sums: torso height above the
+                           cell under it, contact points, slipping frames, 0 */
+  NPX_F_BODY = 9        /* float [13][I] COG, QUAT, VEL, OMEGA in one block */
+};
+#define NPX_FLAG_NONFINITE 1
+#define NPX_FLAG_SPEED 2 /* |v| > 50 m/s or |omega| > 500 rad/s */
+
+/* Copies a field to dst (bytes must equal the field size). Synchronous. */
+npx_status npx_read_state(npx_world* w, int field, void* dst, size_t bytes, int dst_on_device);
+/* Overwrites a field from src (bytes must equal the field size). Synchronous.
+ * Used for checkpoint/resume and to start parity windows from given states. */
+npx_status npx_write_state(npx_world* w, int field, const void* src, size_t bytes,
+                           int src_on_device);
+
+/* World positions of every mass point at the current state, computed by the
+ * step's own transform path: float [n_instances][N_max][3] (rows past an
+ * instance's point count are zero). Synchronous. */
+npx_status npx_read_points(npx_world* w, float* dst, size_t bytes, int dst_on_device);
+
+/* ---------------------------------------------------------------------- */
+/* Launch shape (chosen by the autotuner or set by hand)                   */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t lanes_per_instance; /* 16, 32 or 64 lanes of a wave per robot */
+  int32_t persistent;         /* 1: resident grid pulling tasks from a queue */
+  int32_t chunk_steps;        /* frames per kernel launch (state stays in registers) */
+  int32_t use_graph;          /* 1: replay chunk launches from cached hipGraphs */
+  int32_t waves_per_cu;       /* resident waves per CU in persistent mode */
+} npx_launch;
+
+npx_status npx_get_launch(const npx_world* w, npx_launch* out);
+/* Rejects shapes the kernels are not built for with NPX_EUNSUPPORTED. */
+npx_status npx_set_launch(npx_world* w, const npx_launch* cfg);
+
+/* Times `steps` frames of each candidate launch shape on a scratch copy of the
+ * state (the world's state is untouched), applies the fastest and writes it to
+ * best. times_ms (may be NULL) receives one time per candidate tried, at most
+ * max_results; n_tried receives the count. */
+npx_status npx_autotune(npx_world* w, int32_t steps, void* hip_stream, npx_launch* best,
+                        npx_launch* tried, float* times_ms, int32_t max_results,
+                        int32_t* n_tried);
+
+/* Algorithmic FP32 operations of one frame of instance i, counted from the
+ * step's formulas (the roofline numerator). */
+npx_status npx_flops_per_step(const npx_world* w, int64_t i, double* flops);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

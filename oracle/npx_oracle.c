@@ -207,16 +207,21 @@ void orc_fk(const orc_morph* m, const double* q, double* y, double* g_b, double*
 
 /* The x-y coordinates are scaled by s and turned into integer indices of a 2-D
  * table. Reading: index = floor(s (x - x0)), clamped onto the table (a NaN
- * coordinate maps to cell 0). */
-static int cell_index(double u, int n) {
-  if (!(u >= 0.0)) return 0;
-  if (u >= (double)(n - 1)) return n - 1;
-  return (int)floor(u);
+ * coordinate maps to cell 0). The index is an integer decided by floating
+ * point, so it is taken in the precision of the GPU path: the coordinate,
+ * origin and scale are rounded to float32 and s (x - x0) is evaluated in
+ * float32. Everything else in the oracle stays double. */
+static int cell_index(double x, double x0, double s, int n) {
+  volatile float d = (float)x - (float)x0; /* float32 subtraction, no contraction */
+  float u = d * (float)s;
+  if (!(u >= 0.0f)) return 0;
+  if (u >= (float)(n - 1)) return n - 1;
+  return (int)floorf(u);
 }
 
 void orc_cell(const orc_params* p, double x, double y, int* i, int* j) {
-  *i = cell_index(p->hf_s * (x - p->hf_x0), p->hf_nx);
-  *j = cell_index(p->hf_s * (y - p->hf_y0), p->hf_ny);
+  *i = cell_index(x, p->hf_x0, p->hf_s, p->hf_nx);
+  *j = cell_index(y, p->hf_y0, p->hf_s, p->hf_ny);
 }
 
 double orc_height(const orc_params* p, double x, double y) {

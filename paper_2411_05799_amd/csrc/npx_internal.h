@@ -1,0 +1,72 @@
+// Internal interface between the host runtime and the step kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace npx {
+
+// Link table row (LINK_F floats): hinge anchor [0..2], axis [3..5], lower and
+// upper limit [6..7], link mass [8], link CoG in the construction frame
+// [9..11], inertia about the link CoG in construction axes [12..17]
+// (xx yy zz xy xz yz).
+constexpr int LINK_F = 18;
+constexpr int LK_MASS = 8, LK_COG = 9, LK_INERTIA = 12;
+constexpr int TELE_N = 4;
+constexpr int BODY_ROWS = 13;  // c(3) Q(4) v(3) w(3)
+
+inline int state_rows(int j_max) { return BODY_ROWS + 2 * j_max; }
+
+struct StepArgs {
+  int n_inst;             // instances in the world (SoA stride)
+  int n_tasks;            // instances stepped by this launch
+  int n_blocks;           // ceil(n_tasks / instances per wave)
+  const int* order;       // [n_tasks] instance of each task
+  int j_max;              // joint stride of ctrl and q
+  int max_depth;          // deepest link over all morphologies
+  const int* inst_morph;  // [n_inst]
+  const int4* morph_info; // [n_morphs] point offset, points, link offset, links
+  const float* morph_mass;
+  const float4* pts;      // [total points] x y z m (construction frame)
+  const int* pt_link;     // [total points]
+  const float* links;     // [total links][LINK_F]
+  const int* link_parent; // [total links]
+  const int* link_depth;  // [total links]
+  const float* ctrl;      // [n_inst][j_max][3] A f phi
+  float dt;
+  double dt_d;
+  int K;
+  float gx, gy, gz;
+  float mu;
+  int mu_inf;
+  float kn, zeta, eps;
+  const float* hf;
+  int hf_nx, hf_ny;
+  float hf_s, hf_x0, hf_y0;
+  float* st;              // [state_rows(j_max)][n_inst]
+  int* step;              // [n_inst]
+  int* flags;             // [n_inst]
+  double* tele;           // [TELE_N][n_inst]
+  int n_steps;            // frames advanced by this launch
+  int* queue;             // persistent mode: task-block counter (zeroed before launch)
+  float* points_out;      // with n_steps == 0: [n_inst][n_max][3] world points
+  int n_max;
+  int place;              // with n_steps == 0: set q = q_cmd(t_n) and turn the
+                          // torso-origin position held in the CoG rows into the CoG
+};
+
+// Kernel shape: lanes per instance G, points per lane PPL, links per lane LPL.
+struct Shape {
+  int G, PPL, LPL;
+};
+
+// Smallest built shape for a given G that holds n_max points and l_max links;
+// returns false when none does.
+bool pick_shape(int G, int n_max, int l_max, Shape* out);
+hipError_t launch_step(const StepArgs& a, const Shape& s, int grid, hipStream_t stream);
+hipError_t launch_zero(int* p, hipStream_t stream);
+// Max resident blocks of one wave per CU for a shape (occupancy query).
+int resident_blocks_per_cu(const Shape& s);
+
+}  // namespace npx

@@ -1,0 +1,629 @@
+// The NeoPhysIx frame for many robots at once, FP32, gfx950.
+//
+// Layout of the work: a wave of 64 lanes holds 64/G robots; each robot owns a
+// segment of G consecutive lanes. A segment's lanes share the robot's mass
+// points (point k lives on lane k mod G, register slot k / G) and its links
+// (link l on lane l mod G, slot l / G). Per-robot scalars (CoG, orientation,
+// velocities, forces, the friction fit) are kept redundantly in every lane of
+// the segment, so the per-point phases need no broadcast. Segment-wide sums
+// (contact force and torque, link mass properties, the seven friction moments)
+// are butterfly reductions inside the segment; every lane ends with the same
+// bits, and the order is fixed, so a robot's trajectory does not depend on
+// which segment or wave runs it. Link transforms pass from link lanes to point
+// lanes through LDS. The state stays in registers for a whole launch of
+// n_steps frames and touches HBM once at each end.
+//
+// The frame (Sec. III; readings as in the oracle):
+//   S1 detection of every point against the height-map table (Sec. III-A)
+//   S2 normal penalty forces along +z, summed to force and torque about the CoG
+//   S3 joint-angle determination every K frames (Sec. III-B): new joint angles,
+//      new body points about the unchanged world CoG
+//   S4 trial semi-implicit Euler step to the predicted points P*
+//   S5 friction set: in contact at P^n and at P* (eq. 3)
+//   S6 the normal equations (4)-(6) solved in closed form on slip moments
+//   S7 cap by the maximum static friction mu F_N (Sec. III-C)
+//   S8 move back by the capped fit, remove the matching velocity, commit
+#include "npx_internal.h"
+
+namespace npx {
+
+namespace {
+
+constexpr float kTwoPi = 6.28318530717958647692f;
+constexpr double kInvTwoPi = 0.15915494309189533577;
+
+template <int G>
+__device__ __forceinline__ float seg_sum(float x) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+// sin and cos of one angle. Quadrant reduction x = k pi/2 + r, |r| <= pi/4, with
+// pi/2 split in two parts and fused multiply-adds (Cody & Waite), then the
+// minimax polynomials of the Cephes library (S. L. Moshier) on the reduced
+// range. About 1 ulp for |x| < 1e4 rad; every angle of the step is far below.
+__device__ __forceinline__ void sin_cos(float x, float* s, float* c) {
+  const float k = rintf(x * 0.636619772367581343f);
+  float r = fmaf(-k, 1.57079637050628662109375f, x);
+  r = fmaf(-k, -4.37113900018624283e-8f, r);
+  const float r2 = r * r;
+  const float sr = fmaf(r * r2, fmaf(r2, fmaf(r2, -1.9515295891e-4f, 8.3321608736e-3f),
+                                     -1.6666654611e-1f), r);
+  const float cr = fmaf(r2 * r2, fmaf(r2, fmaf(r2, 2.443315711809948e-5f, -1.388731625493765e-3f),
+                                      4.166664568298827e-2f), fmaf(-0.5f, r2, 1.f));
+  const int q = (int)k;
+  const float ss = (q & 1) ? cr : sr;
+  const float cc = (q & 1) ? sr : cr;
+  *s = (q & 2) ? -ss : ss;
+  *c = ((q + 1) & 2) ? -cc : cc;
+}
+
+__device__ __forceinline__ void quat_to_mat(float w, float x, float y, float z, float R[9]) {
+  float xx = x * x, yy = y * y, zz = z * z;
+  float xy = x * y, xz = x * z, yz = y * z, wx = w * x, wy = w * y, wz = w * z;
+  R[0] = 1.f - 2.f * (yy + zz); R[1] = 2.f * (xy - wz);       R[2] = 2.f * (xz + wy);
+  R[3] = 2.f * (xy + wz);       R[4] = 1.f - 2.f * (xx + zz); R[5] = 2.f * (yz - wx);
+  R[6] = 2.f * (xz - wy);       R[7] = 2.f * (yz + wx);       R[8] = 1.f - 2.f * (xx + yy);
+}
+
+// Height-map look-up (Sec. III-A): floor(s (x - x0)) clamped onto the table;
+// fmaxf maps a NaN coordinate to cell 0.
+__device__ __forceinline__ float hf_at(const StepArgs& a, float x, float y) {
+  float u = fminf(fmaxf((x - a.hf_x0) * a.hf_s, 0.f), (float)(a.hf_nx - 1));
+  float w = fminf(fmaxf((y - a.hf_y0) * a.hf_s, 0.f), (float)(a.hf_ny - 1));
+  int i = (int)u, j = (int)w;
+  return a.hf[j * a.hf_nx + i];
+}
+
+enum Mode { kStep = 0, kPlace = 1, kPoints = 2 };
+
+template <int G, int PPL, int LPL, int MODE>
+__device__ __forceinline__ void run_block(const StepArgs& a, float4 (*T)[3], int tb, int seg,
+                                          int sl) {
+  constexpr int IPW = 64 / G;
+  const int I = a.n_inst;
+  const int task = tb * IPW + seg;
+  const bool valid = task < a.n_tasks;
+  const int inst = valid ? a.order[task] : 0;
+  const int mi = valid ? a.inst_morph[inst] : 0;
+  const int4 info = a.morph_info[mi];
+  const int N = valid ? info.y : 0;
+  const int L = valid ? info.w : 1;
+  const int pt_off = info.x, lk_off = info.z;
+  const float M = a.morph_mass[mi];
+  const float* st = a.st;
+
+  // ---- links of this lane: table row and joint angles (the rest of the link
+  // data is read from the cache-resident tables where it is used)
+  int lrow[LPL];
+  bool lv[LPL], lj[LPL];
+  float q[LPL], qp[LPL];
+#pragma unroll
+  for (int l = 0; l < LPL; ++l) {
+    const int li = sl + l * G;
+    lv[l] = li < L;
+    lj[l] = lv[l] && li >= 1;
+    lrow[l] = lk_off + (lv[l] ? li : 0);
+    const int j = lj[l] ? li - 1 : 0;
+    q[l] = lj[l] ? st[(size_t)(BODY_ROWS + j) * I + inst] : 0.f;
+    qp[l] = lj[l] ? st[(size_t)(BODY_ROWS + a.j_max + j) * I + inst] : 0.f;
+  }
+
+  // ---- per-robot state (same value in every lane of the segment)
+  float c[3], Q[4], v[3], w[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    c[i] = st[(size_t)i * I + inst];
+    v[i] = st[(size_t)(7 + i) * I + inst];
+    w[i] = st[(size_t)(10 + i) * I + inst];
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) Q[i] = st[(size_t)(3 + i) * I + inst];
+  int n = a.step[inst];
+  int fl = a.flags[inst];
+  double tele[TELE_N];
+#pragma unroll
+  for (int i = 0; i < TELE_N; ++i) tele[i] = a.tele[(size_t)i * I + inst];
+
+  // ---- body points about the CoG and mass properties at angles q
+  float rx[PPL], ry[PPL], rz[PPL];
+  float gb[3], Iinv[6], Ib[6];
+  bool Ireg;
+
+  auto forward_kinematics = [&]() __attribute__((always_inline)) {
+    // joint-local transforms x -> Rj x + tj (rotation about the hinge through its anchor)
+    float Rl[LPL][9], tl[LPL][3];
+#pragma unroll
+    for (int l = 0; l < LPL; ++l) {
+      const float* lk = a.links + (size_t)lrow[l] * LINK_F;
+      const float ao[3] = {lk[0], lk[1], lk[2]};
+      float x = lk[3], y = lk[4], z = lk[5];
+      const float n2 = x * x + y * y + z * z;
+      const float inv = n2 > 0.f ? 1.f / sqrtf(n2) : 0.f;
+      x *= inv;
+      y *= inv;
+      z *= inv;
+      float s, co;
+      sin_cos(q[l], &s, &co);
+      const float C1 = 1.f - co;
+      float Rj[9] = {co + x * x * C1,     x * y * C1 - z * s, x * z * C1 + y * s,
+                     y * x * C1 + z * s,  co + y * y * C1,    y * z * C1 - x * s,
+                     z * x * C1 - y * s,  z * y * C1 + x * s, co + z * z * C1};
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Rl[l][i] = Rj[i];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        tl[l][i] = ao[i] - (Rj[3 * i] * ao[0] + Rj[3 * i + 1] * ao[1] + Rj[3 * i + 2] * ao[2]);
+    }
+    if (sl == 0) {
+      T[0][0] = make_float4(1.f, 0.f, 0.f, 0.f);
+      T[0][1] = make_float4(0.f, 1.f, 0.f, 0.f);
+      T[0][2] = make_float4(0.f, 0.f, 1.f, 0.f);
+    }
+    // link transforms down the tree, one depth level at a time
+    for (int lev = 1; lev <= a.max_depth; ++lev) {
+      __syncthreads();
+#pragma unroll
+      for (int l = 0; l < LPL; ++l) {
+        if (lv[l] && a.link_depth[lrow[l]] == lev) {
+          const int par = a.link_parent[lrow[l]];
+          const float4 p0 = T[par][0], p1 = T[par][1], p2 = T[par][2];
+          const float Rp[9] = {p0.x, p0.y, p0.z, p1.x, p1.y, p1.z, p2.x, p2.y, p2.z};
+          const float tp[3] = {p0.w, p1.w, p2.w};
+          float R[9], t[3];
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+              R[3 * i + k] = Rp[3 * i] * Rl[l][k] + Rp[3 * i + 1] * Rl[l][3 + k] +
+                             Rp[3 * i + 2] * Rl[l][6 + k];
+            t[i] = Rp[3 * i] * tl[l][0] + Rp[3 * i + 1] * tl[l][1] + Rp[3 * i + 2] * tl[l][2] +
+                   tp[i];
+          }
+          const int li = sl + l * G;
+          T[li][0] = make_float4(R[0], R[1], R[2], t[0]);
+          T[li][1] = make_float4(R[3], R[4], R[5], t[1]);
+          T[li][2] = make_float4(R[6], R[7], R[8], t[2]);
+        }
+      }
+    }
+    __syncthreads();
+    // mass properties: sum over links of m p and R I R^T + m (|p|^2 1 - p p^T)
+    float acc[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) acc[i] = 0.f;
+#pragma unroll
+    for (int l = 0; l < LPL; ++l) {
+      if (lv[l]) {
+        const int li = sl + l * G;
+        const float4 r0 = T[li][0], r1 = T[li][1], r2 = T[li][2];
+        const float R[9] = {r0.x, r0.y, r0.z, r1.x, r1.y, r1.z, r2.x, r2.y, r2.z};
+        float p[3];
+        const float* lk = a.links + (size_t)lrow[l] * LINK_F;
+        const float lc[3] = {lk[LK_COG], lk[LK_COG + 1], lk[LK_COG + 2]};
+        p[0] = R[0] * lc[0] + R[1] * lc[1] + R[2] * lc[2] + r0.w;
+        p[1] = R[3] * lc[0] + R[4] * lc[1] + R[5] * lc[2] + r1.w;
+        p[2] = R[6] * lc[0] + R[7] * lc[1] + R[8] * lc[2] + r2.w;
+        const float m = lk[LK_MASS];
+        acc[0] += m * p[0];
+        acc[1] += m * p[1];
+        acc[2] += m * p[2];
+        // A = R I (I symmetric: xx yy zz xy xz yz)
+        const float* S = lk + LK_INERTIA;
+        const float Ifull[9] = {S[0], S[3], S[4], S[3], S[1], S[5], S[4], S[5], S[2]};
+        float A[9];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int k = 0; k < 3; ++k)
+            A[3 * i + k] = R[3 * i] * Ifull[k] + R[3 * i + 1] * Ifull[3 + k] +
+                           R[3 * i + 2] * Ifull[6 + k];
+        const float pp = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+        // (A R^T)_ik = sum_j A_ij R_kj
+        acc[3] += A[0] * R[0] + A[1] * R[1] + A[2] * R[2] + m * (pp - p[0] * p[0]);
+        acc[4] += A[3] * R[3] + A[4] * R[4] + A[5] * R[5] + m * (pp - p[1] * p[1]);
+        acc[5] += A[6] * R[6] + A[7] * R[7] + A[8] * R[8] + m * (pp - p[2] * p[2]);
+        acc[6] += A[0] * R[3] + A[1] * R[4] + A[2] * R[5] - m * p[0] * p[1];
+        acc[7] += A[0] * R[6] + A[1] * R[7] + A[2] * R[8] - m * p[0] * p[2];
+        acc[8] += A[3] * R[6] + A[4] * R[7] + A[5] * R[8] - m * p[1] * p[2];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) acc[i] = seg_sum<G>(acc[i]);
+    const float invM = 1.f / M;
+    gb[0] = acc[0] * invM;
+    gb[1] = acc[1] * invM;
+    gb[2] = acc[2] * invM;
+    const float gg = gb[0] * gb[0] + gb[1] * gb[1] + gb[2] * gb[2];
+    Ib[0] = acc[3] - M * (gg - gb[0] * gb[0]);
+    Ib[1] = acc[4] - M * (gg - gb[1] * gb[1]);
+    Ib[2] = acc[5] - M * (gg - gb[2] * gb[2]);
+    Ib[3] = acc[6] + M * gb[0] * gb[1];
+    Ib[4] = acc[7] + M * gb[0] * gb[2];
+    Ib[5] = acc[8] + M * gb[1] * gb[2];
+    {
+      const float xx = Ib[0], yy = Ib[1], zz = Ib[2], xy = Ib[3], xz = Ib[4], yz = Ib[5];
+      const float c00 = yy * zz - yz * yz, c11 = xx * zz - xz * xz, c22 = xx * yy - xy * xy;
+      const float c01 = xz * yz - xy * zz, c02 = xy * yz - xz * yy, c12 = xy * xz - xx * yz;
+      const float det = xx * c00 + xy * c01 + xz * c02;
+      const float tr = (xx + yy + zz) * (1.f / 3.f);
+      Ireg = tr > 0.f && det > 1e-9f * tr * tr * tr;
+      const float id = Ireg ? 1.f / det : 0.f;
+      Iinv[0] = c00 * id; Iinv[1] = c11 * id; Iinv[2] = c22 * id;
+      Iinv[3] = c01 * id; Iinv[4] = c02 * id; Iinv[5] = c12 * id;
+    }
+    // body points y = T_link rho, about the CoG
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+      const int k = sl + p * G;
+      const bool ok = k < N;
+      const int kk = pt_off + (ok ? k : 0);
+      const float4 rho = a.pts[kk];
+      const int lk = ok ? a.pt_link[kk] : 0;
+      const float4 r0 = T[lk][0], r1 = T[lk][1], r2 = T[lk][2];
+      const float yx = r0.x * rho.x + r0.y * rho.y + r0.z * rho.z + r0.w - gb[0];
+      const float yy = r1.x * rho.x + r1.y * rho.y + r1.z * rho.z + r1.w - gb[1];
+      const float yz = r2.x * rho.x + r2.y * rho.y + r2.z * rho.z + r2.w - gb[2];
+      rx[p] = ok ? yx : 0.f;
+      ry[p] = ok ? yy : 0.f;
+      rz[p] = ok ? yz : 0.f;
+    }
+  };
+
+  // S0: commanded angle of this lane's joints at frame n, clamped to the limits
+  auto command = [&](int l) __attribute__((always_inline)) {
+    const int li = sl + l * G;
+    const float* cp = a.ctrl + ((size_t)inst * a.j_max + (lj[l] ? li - 1 : 0)) * 3;
+    const float* lk = a.links + (size_t)lrow[l] * LINK_F;
+    const double t = (double)n * a.dt_d;
+    double ph = (double)cp[1] * t + (double)cp[2] * kInvTwoPi;
+    ph -= floor(ph);
+    float sq, cq;
+    sin_cos(kTwoPi * (float)ph, &sq, &cq);
+    const float qh = cp[0] * sq;
+    return lj[l] ? fminf(fmaxf(qh, lk[6]), lk[7]) : 0.f;
+  };
+
+  if (MODE == kPlace) {
+#pragma unroll
+    for (int l = 0; l < LPL; ++l) {
+      q[l] = command(l);
+      qp[l] = q[l];
+    }
+  }
+
+  forward_kinematics();
+
+  if (MODE == kPlace) {
+    float R[9];
+    quat_to_mat(Q[0], Q[1], Q[2], Q[3], R);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) c[i] += R[3 * i] * gb[0] + R[3 * i + 1] * gb[1] + R[3 * i + 2] * gb[2];
+  }
+
+  if (MODE == kPoints) {
+    float R[9];
+    quat_to_mat(Q[0], Q[1], Q[2], Q[3], R);
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+      const int k = sl + p * G;
+      if (valid && k < N) {
+        float* o = a.points_out + ((size_t)inst * a.n_max + k) * 3;
+        o[0] = c[0] + (R[0] * rx[p] + R[1] * ry[p] + R[2] * rz[p]);
+        o[1] = c[1] + (R[3] * rx[p] + R[4] * ry[p] + R[5] * rz[p]);
+        o[2] = c[2] + (R[6] * rx[p] + R[7] * ry[p] + R[8] * rz[p]);
+      }
+    }
+  }
+
+  const float dt = a.dt;
+  for (int s = 0; s < (MODE == kStep ? a.n_steps : 0); ++s) {
+    const bool active = valid && fl == 0;
+    float R[9];
+    quat_to_mat(Q[0], Q[1], Q[2], Q[3], R);
+
+    // S1 + S2: detection at P^n and normal forces. Ux, Uy keep the points'
+    // offsets from the CoG (R r), not their world positions: the friction fit
+    // below works on small offsets and slips, which float32 holds far better
+    // than world coordinates.
+    float Ux[PPL], Uy[PPL];
+    unsigned kap = 0u;
+    float F = 0.f, tx = 0.f, ty = 0.f, nc = 0.f;
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+      const int k = sl + p * G;
+      const float ux = R[0] * rx[p] + R[1] * ry[p] + R[2] * rz[p];
+      const float uy = R[3] * rx[p] + R[4] * ry[p] + R[5] * rz[p];
+      const float uz = R[6] * rx[p] + R[7] * ry[p] + R[8] * rz[p];
+      const float Px = c[0] + ux, Py = c[1] + uy, Pz = c[2] + uz;
+      Ux[p] = ux;
+      Uy[p] = uy;
+      if (k < N) {
+        const float d = hf_at(a, Px, Py) - Pz;
+        if (d > 0.f) {
+          kap |= 1u << p;
+          const float vz = v[2] + (w[0] * uy - w[1] * ux);
+          const float f = fmaxf(a.kn * d * (1.f - a.zeta * vz), 0.f);
+          F += f;
+          tx += uy * f;
+          ty -= ux * f;
+          nc += 1.f;
+        }
+      }
+    }
+    F = seg_sum<G>(F);
+    tx = seg_sum<G>(tx);
+    ty = seg_sum<G>(ty);
+    nc = seg_sum<G>(nc);
+
+    // S3: joint-angle determination every K frames (c, Q, v, w kept)
+    const bool upd = (n % a.K) == 0;
+    if (__any(upd)) {
+      const bool take = upd && active;
+#pragma unroll
+      for (int l = 0; l < LPL; ++l) {
+        const float qn = command(l);
+        qp[l] = take ? q[l] : qp[l];
+        q[l] = take ? qn : q[l];
+      }
+      forward_kinematics();
+    }
+
+    // S4: trial step. Body-frame Euler equation: I_b dw_b = tau_b - w_b x I_b w_b
+    float v1[3], w1[3], c1[3], Q1[4];
+    v1[0] = v[0] + dt * a.gx;
+    v1[1] = v[1] + dt * a.gy;
+    v1[2] = v[2] + dt * (a.gz + F / M);
+    {
+      const float wb[3] = {R[0] * w[0] + R[3] * w[1] + R[6] * w[2],
+                           R[1] * w[0] + R[4] * w[1] + R[7] * w[2],
+                           R[2] * w[0] + R[5] * w[1] + R[8] * w[2]};
+      const float tb_[3] = {R[0] * tx + R[3] * ty, R[1] * tx + R[4] * ty, R[2] * tx + R[5] * ty};
+      const float Lb[3] = {Ib[0] * wb[0] + Ib[3] * wb[1] + Ib[4] * wb[2],
+                           Ib[3] * wb[0] + Ib[1] * wb[1] + Ib[5] * wb[2],
+                           Ib[4] * wb[0] + Ib[5] * wb[1] + Ib[2] * wb[2]};
+      const float rb[3] = {tb_[0] - (wb[1] * Lb[2] - wb[2] * Lb[1]),
+                           tb_[1] - (wb[2] * Lb[0] - wb[0] * Lb[2]),
+                           tb_[2] - (wb[0] * Lb[1] - wb[1] * Lb[0])};
+      const float ab[3] = {Iinv[0] * rb[0] + Iinv[3] * rb[1] + Iinv[4] * rb[2],
+                           Iinv[3] * rb[0] + Iinv[1] * rb[1] + Iinv[5] * rb[2],
+                           Iinv[4] * rb[0] + Iinv[5] * rb[1] + Iinv[2] * rb[2]};
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        w1[i] = w[i] + dt * (R[3 * i] * ab[0] + R[3 * i + 1] * ab[1] + R[3 * i + 2] * ab[2]);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) c1[i] = c[i] + dt * v1[i];
+    {
+      const float th0 = dt * w1[0], th1 = dt * w1[1], th2 = dt * w1[2];
+      const float ang = sqrtf(th0 * th0 + th1 * th1 + th2 * th2);
+      float dq[4];
+      if (ang < 1e-12f) {
+        dq[0] = 1.f; dq[1] = 0.5f * th0; dq[2] = 0.5f * th1; dq[3] = 0.5f * th2;
+      } else {
+        float sh, ch;
+        sin_cos(0.5f * ang, &sh, &ch);
+        const float k = sh / ang;
+        dq[0] = ch; dq[1] = k * th0; dq[2] = k * th1; dq[3] = k * th2;
+      }
+      Q1[0] = dq[0] * Q[0] - dq[1] * Q[1] - dq[2] * Q[2] - dq[3] * Q[3];
+      Q1[1] = dq[0] * Q[1] + dq[1] * Q[0] + dq[2] * Q[3] - dq[3] * Q[2];
+      Q1[2] = dq[0] * Q[2] - dq[1] * Q[3] + dq[2] * Q[0] + dq[3] * Q[1];
+      Q1[3] = dq[0] * Q[3] + dq[1] * Q[2] - dq[2] * Q[1] + dq[3] * Q[0];
+      const float inv = 1.f / sqrtf(Q1[0] * Q1[0] + Q1[1] * Q1[1] + Q1[2] * Q1[2] + Q1[3] * Q1[3]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) Q1[i] *= inv;
+    }
+    float R1[9];
+    quat_to_mat(Q1[0], Q1[1], Q1[2], Q1[3], R1);
+
+    // S5 + S6 moments over the friction set in the ground plane about the
+    // predicted CoG c1: source xi = P^n - c1 = R r_old - (c1 - c), target
+    // xi' = P* - c1 = R1 r_new, slip delta = xi' - xi. The normal equations
+    // (4)-(6) need n, sum xi, sum |xi|^2, sum delta and sum xi x delta.
+    const float dcx = c1[0] - c[0], dcy = c1[1] - c[1];
+    float mn = 0.f, Sx = 0.f, Sy = 0.f, S2 = 0.f, Dx = 0.f, Dy = 0.f, Cd = 0.f;
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+      if (kap & (1u << p)) {
+        const float ux = R1[0] * rx[p] + R1[1] * ry[p] + R1[2] * rz[p];
+        const float uy = R1[3] * rx[p] + R1[4] * ry[p] + R1[5] * rz[p];
+        const float uz = R1[6] * rx[p] + R1[7] * ry[p] + R1[8] * rz[p];
+        const float Px = c1[0] + ux, Py = c1[1] + uy, Pz = c1[2] + uz;
+        if (hf_at(a, Px, Py) - Pz > 0.f) {
+          const float sx = Ux[p] - dcx, sy = Uy[p] - dcy;
+          const float dx = (ux - Ux[p]) + dcx, dy = (uy - Uy[p]) + dcy;
+          mn += 1.f;
+          Sx += sx;
+          Sy += sy;
+          S2 += sx * sx + sy * sy;
+          Dx += dx;
+          Dy += dy;
+          Cd += sx * dy - sy * dx;
+        }
+      }
+    }
+    mn = seg_sum<G>(mn);
+    Sx = seg_sum<G>(Sx);
+    Sy = seg_sum<G>(Sy);
+    S2 = seg_sum<G>(S2);
+    Dx = seg_sum<G>(Dx);
+    Dy = seg_sum<G>(Dy);
+    Cd = seg_sum<G>(Cd);
+
+    // S6 closed form of eqs. (4)-(6) and S7 static-friction cap. In these
+    // moments a3 = [sum xi x delta - (Sx Dy - Sy Dx)/n] / (sum |xi|^2 - |S|^2/n),
+    // a = (D + a3 J^T S)/n, the mean slip is D/n.
+    float a1 = 0.f, a2 = 0.f, a3 = 0.f, lam = 0.f;
+    if (mn > 0.f) {
+      const float inv_n = 1.f / mn;
+      const float D = S2 - (Sx * Sx + Sy * Sy) * inv_n;
+      if (mn >= 2.f && D > mn * a.eps * a.eps) a3 = (Cd - (Sx * Dy - Sy * Dx) * inv_n) / D;
+      a1 = (Dx + Sy * a3) * inv_n;
+      a2 = (Dy - Sx * a3) * inv_n;
+      const float sbx = Dx * inv_n, sby = Dy * inv_n;
+      const float Ff = M * sqrtf(sbx * sbx + sby * sby) / (dt * dt);
+      lam = (a.mu_inf || Ff <= a.mu * F) ? 1.f : a.mu * F / Ff;
+    }
+
+    // S8 correction and commit
+    const float alpha = asinf(fminf(fmaxf(a3, -1.f), 1.f));
+    float Q2[4];
+    {
+      float sh, ch;
+      sin_cos(-0.5f * lam * alpha, &sh, &ch);
+      Q2[0] = ch * Q1[0] - sh * Q1[3];
+      Q2[1] = ch * Q1[1] - sh * Q1[2];
+      Q2[2] = ch * Q1[2] + sh * Q1[1];
+      Q2[3] = ch * Q1[3] + sh * Q1[0];
+    }
+    const float c2[3] = {c1[0] - lam * a1, c1[1] - lam * a2, c1[2]};
+    const float v2[3] = {v1[0] - lam * a1 / dt, v1[1] - lam * a2 / dt, v1[2]};
+    const float w2[3] = {w1[0], w1[1], w1[2] - lam * alpha / dt};
+
+    // S9 telemetry and health
+    float R2[9];
+    quat_to_mat(Q2[0], Q2[1], Q2[2], Q2[3], R2);
+    const float ox = c2[0] - (R2[0] * gb[0] + R2[1] * gb[1] + R2[2] * gb[2]);
+    const float oy = c2[1] - (R2[3] * gb[0] + R2[4] * gb[1] + R2[5] * gb[2]);
+    const float oz = c2[2] - (R2[6] * gb[0] + R2[7] * gb[1] + R2[8] * gb[2]);
+    const float th = oz - hf_at(a, ox, oy);
+    bool fin = true;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) fin = fin && isfinite(c2[i]) && isfinite(v2[i]) && isfinite(w2[i]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) fin = fin && isfinite(Q2[i]);
+    const float vv = v2[0] * v2[0] + v2[1] * v2[1] + v2[2] * v2[2];
+    const float ww = w2[0] * w2[0] + w2[1] * w2[1] + w2[2] * w2[2];
+    const int bad = (fin ? 0 : 1) | ((vv > 2500.f || ww > 250000.f) ? 2 : 0);
+
+    if (active) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        c[i] = c2[i];
+        v[i] = v2[i];
+        w[i] = w2[i];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) Q[i] = Q2[i];
+      tele[0] += (double)th;
+      tele[1] += (double)nc;
+      tele[2] += (mn > 0.f && lam < 1.f) ? 1.0 : 0.0;
+      fl = bad;
+      n += 1;
+    }
+  }
+
+  // ---- write back
+  if (valid && MODE != kPoints) {
+    float* so = a.st;
+    if (sl == 0) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        so[(size_t)i * I + inst] = c[i];
+        so[(size_t)(7 + i) * I + inst] = v[i];
+        so[(size_t)(10 + i) * I + inst] = w[i];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) so[(size_t)(3 + i) * I + inst] = Q[i];
+      a.step[inst] = n;
+      a.flags[inst] = fl;
+#pragma unroll
+      for (int i = 0; i < TELE_N; ++i) a.tele[(size_t)i * I + inst] = tele[i];
+    }
+#pragma unroll
+    for (int l = 0; l < LPL; ++l) {
+      const int li = sl + l * G;
+      if (lj[l]) {
+        so[(size_t)(BODY_ROWS + li - 1) * I + inst] = q[l];
+        so[(size_t)(BODY_ROWS + a.j_max + li - 1) * I + inst] = qp[l];
+      }
+    }
+  }
+}
+
+template <int G, int PPL, int LPL, int MODE>
+__global__ __launch_bounds__(64) void step_kernel(const StepArgs a) {
+  constexpr int IPW = 64 / G;
+  constexpr int LMAX = G * LPL;
+  __shared__ float4 T[IPW][LMAX][3];
+  const int lane = threadIdx.x;
+  const int seg = lane / G;
+  const int sl = lane - seg * G;
+  for (int it = 0;; ++it) {
+    int tb;
+    if (a.queue) {
+      int v = 0;
+      if (lane == 0) v = atomicAdd(a.queue, 1);
+      tb = __builtin_amdgcn_readfirstlane(v);
+    } else {
+      if (it > 0) break;
+      tb = blockIdx.x;
+    }
+    if (tb >= a.n_blocks) break;
+    run_block<G, PPL, LPL, MODE>(a, T[seg], tb, seg, sl);
+    __syncthreads();
+  }
+}
+
+__global__ void zero_kernel(int* p) { *p = 0; }
+
+}  // namespace
+
+// The built shapes: (G, PPL, LPL).
+#define NPX_SHAPES(X)                                                                  \
+  X(64, 2, 1) X(64, 4, 1) X(64, 6, 1) X(64, 8, 1) X(64, 10, 1) X(64, 12, 1) X(64, 16, 1) \
+  X(32, 4, 1) X(32, 8, 1) X(32, 12, 1) X(32, 12, 2) X(32, 16, 2) X(32, 20, 2)           \
+  X(16, 8, 2) X(16, 16, 2) X(16, 24, 2) X(16, 24, 3)
+
+bool pick_shape(int G, int n_max, int l_max, Shape* out) {
+  bool found = false;
+  Shape best{0, 1 << 30, 1 << 30};
+#define NPX_PICK(g, ppl, lpl)                                                          \
+  if (g == G && g * ppl >= n_max && g * lpl >= l_max &&                                \
+      (ppl < best.PPL || (ppl == best.PPL && lpl < best.LPL))) {                       \
+    best = Shape{g, ppl, lpl};                                                         \
+    found = true;                                                                      \
+  }
+  NPX_SHAPES(NPX_PICK)
+#undef NPX_PICK
+  if (found) *out = best;
+  return found;
+}
+
+hipError_t launch_step(const StepArgs& a, const Shape& s, int grid, hipStream_t stream) {
+#define NPX_LAUNCH(g, ppl, lpl)                                                        \
+  if (s.G == g && s.PPL == ppl && s.LPL == lpl) {                                      \
+    if (a.place)                                                                       \
+      hipLaunchKernelGGL((step_kernel<g, ppl, lpl, kPlace>), dim3(grid), dim3(64), 0,   \
+                         stream, a);                                                   \
+    else if (a.points_out)                                                             \
+      hipLaunchKernelGGL((step_kernel<g, ppl, lpl, kPoints>), dim3(grid), dim3(64), 0,  \
+                         stream, a);                                                   \
+    else                                                                               \
+      hipLaunchKernelGGL((step_kernel<g, ppl, lpl, kStep>), dim3(grid), dim3(64), 0,    \
+                         stream, a);                                                   \
+    return hipGetLastError();                                                          \
+  }
+  NPX_SHAPES(NPX_LAUNCH)
+#undef NPX_LAUNCH
+  return hipErrorInvalidValue;
+}
+
+int resident_blocks_per_cu(const Shape& s) {
+  int nb = 0;
+#define NPX_OCC(g, ppl, lpl)                                                           \
+  if (s.G == g && s.PPL == ppl && s.LPL == lpl)                                        \
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_kernel<g, ppl, lpl, kStep>, 64, 0);
+  NPX_SHAPES(NPX_OCC)
+#undef NPX_OCC
+  return nb;
+}
+
+hipError_t launch_zero(int* p, hipStream_t stream) {
+  hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(1), 0, stream, p);
+  return hipGetLastError();
+}
+
+}  // namespace npx

@@ -1,0 +1,680 @@
+// Host runtime of the C ABI in include/npx.h: world creation (morphology
+// tables to device CSR arrays), struct-of-arrays state, chunked launches of
+// the step kernel replayed from cached hipGraphs, persistent mode, the launch
+// autotuner and state I/O.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "npx.h"
+#include "npx_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+npx_status fail(npx_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(NPX_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));            \
+  } while (0)
+
+template <class T>
+hipError_t dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void**)p, count * sizeof(T));
+}
+
+}  // namespace
+
+struct npx_world {
+  int device = 0;
+  int n_inst = 0, j_max = 0, n_max = 0, l_max = 0, n_morphs = 0, max_depth = 0;
+  std::vector<int> morph_points, morph_links;  // per morph
+  std::vector<int> inst_morph;
+  double dt = 0, mu = 0;
+  int K = 1;
+
+  // device buffers
+  float* st = nullptr;
+  int* step = nullptr;
+  int* flags = nullptr;
+  double* tele = nullptr;
+  int* inst_morph_d = nullptr;
+  int4* morph_info = nullptr;
+  float* morph_mass = nullptr;
+  float4* pts = nullptr;
+  int* pt_link = nullptr;
+  float* links = nullptr;
+  int* link_parent = nullptr;
+  int* link_depth = nullptr;
+  float* ctrl = nullptr;
+  float* hf = nullptr;
+  int* order = nullptr;
+  int* queue = nullptr;
+
+  npx::StepArgs args{};
+  npx_launch launch{64, 0, 100, 1, 8};
+  npx::Shape shape{64, 2, 1};
+  hipStream_t last_stream = nullptr;
+  bool has_last_stream = false;
+  hipStream_t capture_stream = nullptr;
+  std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+  int cu_count = 256;
+
+  void drop_graphs() {
+    for (auto& kv : graphs) {
+      (void)hipGraphExecDestroy(kv.second.second);
+      (void)hipGraphDestroy(kv.second.first);
+    }
+    graphs.clear();
+  }
+};
+
+namespace {
+
+size_t field_bytes(const npx_world* w, int field, size_t* row0, size_t* rows, int* kind) {
+  // kind 0 float rows of st, 1 step, 2 flags, 3 tele
+  const size_t I = (size_t)w->n_inst;
+  *kind = 0;
+  switch (field) {
+    case NPX_F_COG: *row0 = 0; *rows = 3; break;
+    case NPX_F_QUAT: *row0 = 3; *rows = 4; break;
+    case NPX_F_VEL: *row0 = 7; *rows = 3; break;
+    case NPX_F_OMEGA: *row0 = 10; *rows = 3; break;
+    case NPX_F_JOINT: *row0 = npx::BODY_ROWS; *rows = (size_t)w->j_max; break;
+    case NPX_F_JOINT_PREV: *row0 = npx::BODY_ROWS + w->j_max; *rows = (size_t)w->j_max; break;
+    case NPX_F_BODY: *row0 = 0; *rows = npx::BODY_ROWS; break;
+    case NPX_F_STEP: *kind = 1; return I * sizeof(int);
+    case NPX_F_FLAGS: *kind = 2; return I * sizeof(int);
+    case NPX_F_TELE: *kind = 3; return I * npx::TELE_N * sizeof(double);
+    default: return 0;
+  }
+  return *rows * I * sizeof(float);
+}
+
+npx_status sync_last(npx_world* w) {
+  if (w->has_last_stream) HIP_TRY(hipStreamSynchronize(w->last_stream));
+  return NPX_OK;
+}
+
+// Launches `steps` frames (state stays in registers) as one kernel, plus the
+// queue reset in persistent mode.
+hipError_t enqueue_chunk(npx_world* w, int steps, hipStream_t s) {
+  npx::StepArgs a = w->args;
+  a.n_steps = steps;
+  const int ipw = 64 / w->shape.G;
+  a.n_blocks = (a.n_tasks + ipw - 1) / ipw;
+  int grid = a.n_blocks;
+  if (w->launch.persistent) {
+    int per_cu = std::max(1, std::min(w->launch.waves_per_cu, npx::resident_blocks_per_cu(w->shape)));
+    grid = std::min(a.n_blocks, per_cu * w->cu_count);
+    a.queue = w->queue;
+    hipError_t e = npx::launch_zero(w->queue, s);
+    if (e != hipSuccess) return e;
+  } else {
+    a.queue = nullptr;
+  }
+  if (grid <= 0) return hipSuccess;
+  return npx::launch_step(a, w->shape, grid, s);
+}
+
+npx_status run_steps(npx_world* w, int64_t n, hipStream_t s) {
+  const int chunk = std::max(1, w->launch.chunk_steps);
+  int64_t left = n;
+  while (left > 0) {
+    const int c = (int)std::min<int64_t>(left, chunk);
+    if (w->launch.use_graph) {
+      auto it = w->graphs.find(c);
+      if (it == w->graphs.end()) {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        HIP_TRY(hipStreamBeginCapture(w->capture_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue_chunk(w, c, w->capture_stream);
+        hipError_t e2 = hipStreamEndCapture(w->capture_stream, &g);
+        if (e != hipSuccess) return fail(NPX_EHIP, "capture of step chunk: %s", hipGetErrorString(e));
+        if (e2 != hipSuccess) return fail(NPX_EHIP, "end capture: %s", hipGetErrorString(e2));
+        HIP_TRY(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+        it = w->graphs.emplace(c, std::make_pair(g, ge)).first;
+      }
+      HIP_TRY(hipGraphLaunch(it->second.second, s));
+    } else {
+      hipError_t e = enqueue_chunk(w, c, s);
+      if (e != hipSuccess) return fail(NPX_EHIP, "step launch: %s", hipGetErrorString(e));
+    }
+    left -= c;
+  }
+  w->last_stream = s;
+  w->has_last_stream = true;
+  return NPX_OK;
+}
+
+bool shape_for(const npx_world* w, int G, npx::Shape* s) {
+  return npx::pick_shape(G, w->n_max, w->l_max, s);
+}
+
+// Task order: costlier robots first (longest-processing-time order), so the
+// tail of an uneven batch is made of the cheap ones.
+std::vector<int> task_order(const npx_world* w) {
+  std::vector<int> ord(w->n_inst);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+    int ma = w->inst_morph[a], mb = w->inst_morph[b];
+    long ca = (long)w->morph_points[ma] * 4 + w->morph_links[ma] * 16;
+    long cb = (long)w->morph_points[mb] * 4 + w->morph_links[mb] * 16;
+    return ca > cb;
+  });
+  return ord;
+}
+
+npx_status check_tables(const npx_morph_tables& m, int idx) {
+  if (m.n_points <= 0 || m.n_points > NPX_MAX_POINTS)
+    return fail(NPX_EINVAL, "morph %d: n_points %d out of [1, %d]", idx, m.n_points, NPX_MAX_POINTS);
+  if (m.n_links <= 0 || m.n_links > NPX_MAX_JOINTS + 1)
+    return fail(NPX_EINVAL, "morph %d: n_links %d out of [1, %d]", idx, m.n_links, NPX_MAX_JOINTS + 1);
+  if (!m.points || !m.pt_link || !m.parent || !m.joint)
+    return fail(NPX_EINVAL, "morph %d: null table", idx);
+  if (m.parent[0] != -1) return fail(NPX_EINVAL, "morph %d: parent[0] must be -1", idx);
+  for (int l = 1; l < m.n_links; ++l)
+    if (m.parent[l] < 0 || m.parent[l] >= l)
+      return fail(NPX_EINVAL, "morph %d: parent[%d] = %d must be in [0, %d)", idx, l, m.parent[l], l);
+  double M = 0;
+  for (int k = 0; k < m.n_points; ++k) {
+    if (m.pt_link[k] < 0 || m.pt_link[k] >= m.n_links)
+      return fail(NPX_EINVAL, "morph %d: pt_link[%d] = %d out of range", idx, k, m.pt_link[k]);
+    const float* p = m.points + 4 * k;
+    if (!std::isfinite(p[0]) || !std::isfinite(p[1]) || !std::isfinite(p[2]) ||
+        !std::isfinite(p[3]) || p[3] < 0)
+      return fail(NPX_EINVAL, "morph %d: point %d not finite or negative mass", idx, k);
+    M += p[3];
+  }
+  if (!(M > 0)) return fail(NPX_EINVAL, "morph %d: total mass must be > 0", idx);
+  for (int l = 1; l < m.n_links; ++l) {
+    const float* j = m.joint + 8 * l;
+    double n2 = (double)j[3] * j[3] + (double)j[4] * j[4] + (double)j[5] * j[5];
+    if (!(n2 > 0) || !std::isfinite(n2)) return fail(NPX_EINVAL, "morph %d: joint %d axis is zero", idx, l - 1);
+    if (!(j[6] <= j[7])) return fail(NPX_EINVAL, "morph %d: joint %d limits lo > hi", idx, l - 1);
+  }
+  return NPX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* npx_last_error(void) { return g_err.c_str(); }
+int npx_version(void) { return 1; }
+
+npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
+  if (!d || !out) return fail(NPX_EINVAL, "null argument");
+  *out = nullptr;
+  if (!(d->dt > 0) || d->joint_interval < 1) return fail(NPX_EINVAL, "dt must be > 0 and K >= 1");
+  if (d->n_instances <= 0 || d->n_instances > (1 << 26))
+    return fail(NPX_EINVAL, "n_instances %lld out of range", (long long)d->n_instances);
+  if (d->n_morphs <= 0 || !d->morphs || !d->instance_morph || !d->init_pose)
+    return fail(NPX_EINVAL, "missing morphologies, instance map or poses");
+  if (d->hf_nx <= 0 || d->hf_ny <= 0 || !d->hf_heights || !(d->hf_s > 0))
+    return fail(NPX_EINVAL, "bad height map");
+  if (!(d->mu >= 0) || !(d->k_n >= 0) || !(d->zeta >= 0) || !(d->eps_lsq >= 0))
+    return fail(NPX_EINVAL, "mu, k_n, zeta, eps must be >= 0");
+  for (int i = 0; i < d->n_morphs; ++i) {
+    npx_status s = check_tables(d->morphs[i], i);
+    if (s != NPX_OK) return s;
+  }
+  for (int64_t i = 0; i < d->n_instances; ++i)
+    if (d->instance_morph[i] < 0 || d->instance_morph[i] >= d->n_morphs)
+      return fail(NPX_EINVAL, "instance_morph[%lld] out of range", (long long)i);
+
+  npx_world* w = new npx_world();
+  HIP_TRY(hipGetDevice(&w->device));
+  {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, w->device) == hipSuccess && cus > 0)
+      w->cu_count = cus;
+  }
+  w->n_inst = (int)d->n_instances;
+  w->n_morphs = d->n_morphs;
+  w->dt = d->dt;
+  w->K = d->joint_interval;
+  w->mu = d->mu;
+  w->inst_morph.assign(d->instance_morph, d->instance_morph + d->n_instances);
+
+  // morphology CSR + per-link mass properties (double on the host, stored float)
+  std::vector<int4> info(d->n_morphs);
+  std::vector<float> mass(d->n_morphs);
+  std::vector<float4> pts;
+  std::vector<int> ptl, par, dep;
+  std::vector<float> lk;
+  for (int mi = 0; mi < d->n_morphs; ++mi) {
+    const npx_morph_tables& m = d->morphs[mi];
+    info[mi] = make_int4((int)pts.size(), m.n_points, (int)par.size(), m.n_links);
+    w->morph_points.push_back(m.n_points);
+    w->morph_links.push_back(m.n_links);
+    w->n_max = std::max(w->n_max, m.n_points);
+    w->l_max = std::max(w->l_max, m.n_links);
+    std::vector<double> lm(m.n_links, 0.0), lc(3 * m.n_links, 0.0), lI(6 * m.n_links, 0.0);
+    double M = 0;
+    for (int k = 0; k < m.n_points; ++k) {
+      const float* p = m.points + 4 * k;
+      pts.push_back(make_float4(p[0], p[1], p[2], p[3]));
+      ptl.push_back(m.pt_link[k]);
+      int l = m.pt_link[k];
+      lm[l] += p[3];
+      for (int i = 0; i < 3; ++i) lc[3 * l + i] += (double)p[3] * p[i];
+      M += p[3];
+    }
+    for (int l = 0; l < m.n_links; ++l)
+      for (int i = 0; i < 3; ++i) lc[3 * l + i] = lm[l] > 0 ? lc[3 * l + i] / lm[l] : 0.0;
+    for (int k = 0; k < m.n_points; ++k) {
+      const float* p = m.points + 4 * k;
+      int l = m.pt_link[k];
+      double r[3] = {p[0] - lc[3 * l], p[1] - lc[3 * l + 1], p[2] - lc[3 * l + 2]};
+      double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+      double mk = p[3];
+      lI[6 * l + 0] += mk * (rr - r[0] * r[0]);
+      lI[6 * l + 1] += mk * (rr - r[1] * r[1]);
+      lI[6 * l + 2] += mk * (rr - r[2] * r[2]);
+      lI[6 * l + 3] -= mk * r[0] * r[1];
+      lI[6 * l + 4] -= mk * r[0] * r[2];
+      lI[6 * l + 5] -= mk * r[1] * r[2];
+    }
+    mass[mi] = (float)M;
+    std::vector<int> depth(m.n_links, 0);
+    for (int l = 0; l < m.n_links; ++l) {
+      depth[l] = l == 0 ? 0 : depth[m.parent[l]] + 1;
+      w->max_depth = std::max(w->max_depth, depth[l]);
+      par.push_back(m.parent[l]);
+      dep.push_back(depth[l]);
+      const float* j = m.joint + 8 * l;
+      float row[npx::LINK_F];
+      for (int i = 0; i < 8; ++i) row[i] = l == 0 ? 0.f : j[i];
+      if (l == 0) { row[6] = -1e30f; row[7] = 1e30f; }
+      row[npx::LK_MASS] = (float)lm[l];
+      for (int i = 0; i < 3; ++i) row[npx::LK_COG + i] = (float)lc[3 * l + i];
+      for (int i = 0; i < 6; ++i) row[npx::LK_INERTIA + i] = (float)lI[6 * l + i];
+      lk.insert(lk.end(), row, row + npx::LINK_F);
+    }
+  }
+  w->j_max = std::max(1, w->l_max - 1);
+  if (!shape_for(w, 64, &w->shape)) {
+    delete w;
+    return fail(NPX_EUNSUPPORTED, "no kernel shape for %d points / %d links", w->n_max, w->l_max);
+  }
+
+  const size_t I = (size_t)w->n_inst;
+  const size_t rows = (size_t)npx::state_rows(w->j_max);
+  auto cleanup_fail = [&](npx_status s) {
+    npx_destroy_world(w);
+    return s;
+  };
+#define ALLOC(p, n)                                                                    \
+  if (dalloc(&(p), (n)) != hipSuccess)                                                 \
+    return cleanup_fail(fail(NPX_ENOMEM, "device allocation of %s failed", #p));
+  ALLOC(w->st, rows * I);
+  ALLOC(w->step, I);
+  ALLOC(w->flags, I);
+  ALLOC(w->tele, I * npx::TELE_N);
+  ALLOC(w->inst_morph_d, I);
+  ALLOC(w->morph_info, info.size());
+  ALLOC(w->morph_mass, mass.size());
+  ALLOC(w->pts, pts.size());
+  ALLOC(w->pt_link, ptl.size());
+  ALLOC(w->links, lk.size());
+  ALLOC(w->link_parent, par.size());
+  ALLOC(w->link_depth, dep.size());
+  ALLOC(w->ctrl, I * w->j_max * 3);
+  ALLOC(w->hf, (size_t)d->hf_nx * d->hf_ny);
+  ALLOC(w->order, I);
+  ALLOC(w->queue, 1);
+#undef ALLOC
+
+  auto h2d = [&](void* dst, const void* src, size_t bytes) {
+    return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+  };
+#define H2D(dst, src, bytes)                                                           \
+  if (h2d((dst), (src), (bytes)) != hipSuccess)                                        \
+    return cleanup_fail(fail(NPX_EHIP, "copy of %s failed", #dst));
+  H2D(w->inst_morph_d, d->instance_morph, I * sizeof(int));
+  H2D(w->morph_info, info.data(), info.size() * sizeof(int4));
+  H2D(w->morph_mass, mass.data(), mass.size() * sizeof(float));
+  H2D(w->pts, pts.data(), pts.size() * sizeof(float4));
+  H2D(w->pt_link, ptl.data(), ptl.size() * sizeof(int));
+  H2D(w->links, lk.data(), lk.size() * sizeof(float));
+  H2D(w->link_parent, par.data(), par.size() * sizeof(int));
+  H2D(w->link_depth, dep.data(), dep.size() * sizeof(int));
+  H2D(w->hf, d->hf_heights, (size_t)d->hf_nx * d->hf_ny * sizeof(float));
+  std::vector<int> ord = task_order(w);
+  H2D(w->order, ord.data(), I * sizeof(int));
+  {
+    std::vector<float> zero(I * w->j_max * 3, 0.f);
+    H2D(w->ctrl, d->ctrl ? d->ctrl : zero.data(), zero.size() * sizeof(float));
+    std::vector<int> zi(I, 0);
+    H2D(w->step, zi.data(), I * sizeof(int));
+    H2D(w->flags, zi.data(), I * sizeof(int));
+    std::vector<double> zt(I * npx::TELE_N, 0.0);
+    H2D(w->tele, zt.data(), zt.size() * sizeof(double));
+  }
+#undef H2D
+
+  npx::StepArgs& a = w->args;
+  a.n_inst = w->n_inst;
+  a.n_tasks = w->n_inst;
+  a.order = w->order;
+  a.j_max = w->j_max;
+  a.max_depth = w->max_depth;
+  a.inst_morph = w->inst_morph_d;
+  a.morph_info = w->morph_info;
+  a.morph_mass = w->morph_mass;
+  a.pts = w->pts;
+  a.pt_link = w->pt_link;
+  a.links = w->links;
+  a.link_parent = w->link_parent;
+  a.link_depth = w->link_depth;
+  a.ctrl = w->ctrl;
+  a.dt = (float)d->dt;
+  a.dt_d = d->dt;
+  a.K = d->joint_interval;
+  a.gx = (float)d->g[0];
+  a.gy = (float)d->g[1];
+  a.gz = (float)d->g[2];
+  a.mu_inf = std::isinf(d->mu) ? 1 : 0;
+  a.mu = a.mu_inf ? 0.f : (float)d->mu;
+  a.kn = (float)d->k_n;
+  a.zeta = (float)d->zeta;
+  a.eps = (float)d->eps_lsq;
+  a.hf = w->hf;
+  a.hf_nx = d->hf_nx;
+  a.hf_ny = d->hf_ny;
+  a.hf_s = (float)d->hf_s;
+  a.hf_x0 = (float)d->hf_x0;
+  a.hf_y0 = (float)d->hf_y0;
+  a.st = w->st;
+  a.step = w->step;
+  a.flags = w->flags;
+  a.tele = w->tele;
+  a.n_max = w->n_max;
+
+  if (hipStreamCreateWithFlags(&w->capture_stream, hipStreamNonBlocking) != hipSuccess)
+    return cleanup_fail(fail(NPX_EHIP, "stream creation failed"));
+
+  // initial state: at rest, q = q_cmd(0) = 0 for the zero controller; the CoG
+  // follows from the pose through the kernel's own mass properties
+  {
+    std::vector<float> host(rows * I, 0.f);
+    for (size_t i = 0; i < I; ++i) {
+      const float* p = d->init_pose + 7 * i;
+      double qn = std::sqrt((double)p[3] * p[3] + (double)p[4] * p[4] + (double)p[5] * p[5] + (double)p[6] * p[6]);
+      if (!(qn > 0) || !std::isfinite(qn)) return cleanup_fail(fail(NPX_EINVAL, "pose %zu: bad quaternion", i));
+      for (int k = 0; k < 3; ++k) host[k * I + i] = p[k];
+      for (int k = 0; k < 4; ++k) host[(3 + k) * I + i] = (float)(p[3 + k] / qn);
+    }
+    if (h2d(w->st, host.data(), host.size() * sizeof(float)) != hipSuccess)
+      return cleanup_fail(fail(NPX_EHIP, "state upload failed"));
+  }
+  // q = q_cmd(0) and the torso-origin pose turned into the CoG, by the step
+  // kernel's own joint and mass-property path
+  {
+    npx::StepArgs pa = w->args;
+    pa.n_steps = 0;
+    pa.place = 1;
+    pa.queue = nullptr;
+    const int ipw = 64 / w->shape.G;
+    pa.n_blocks = (pa.n_tasks + ipw - 1) / ipw;
+    hipError_t e = npx::launch_step(pa, w->shape, pa.n_blocks, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return cleanup_fail(fail(NPX_EHIP, "placement kernel: %s", hipGetErrorString(e)));
+  }
+  *out = w;
+  return NPX_OK;
+}
+
+void npx_destroy_world(npx_world* w) {
+  if (!w) return;
+  if (w->has_last_stream) (void)hipStreamSynchronize(w->last_stream);
+  w->drop_graphs();
+  if (w->capture_stream) (void)hipStreamDestroy(w->capture_stream);
+  void* bufs[] = {w->st, w->step, w->flags, w->tele, w->inst_morph_d, w->morph_info,
+                  w->morph_mass, w->pts, w->pt_link, w->links, w->link_parent,
+                  w->link_depth, w->ctrl, w->hf, w->order, w->queue};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  delete w;
+}
+
+npx_status npx_world_dims(const npx_world* w, int64_t* n_instances, int32_t* j_max, int32_t* n_max) {
+  if (!w) return fail(NPX_EINVAL, "null world");
+  if (n_instances) *n_instances = w->n_inst;
+  if (j_max) *j_max = w->j_max;
+  if (n_max) *n_max = w->n_max;
+  return NPX_OK;
+}
+
+npx_status npx_set_controller(npx_world* w, int kind, const float* params, size_t n_floats,
+                              int on_device) {
+  if (!w || !params) return fail(NPX_EINVAL, "null argument");
+  if (kind != NPX_CTRL_SINUSOID) return fail(NPX_EUNSUPPORTED, "controller kind %d", kind);
+  const size_t need = (size_t)w->n_inst * w->j_max * 3;
+  if (n_floats != need) return fail(NPX_EINVAL, "controller needs %zu floats, got %zu", need, n_floats);
+  npx_status s = sync_last(w);
+  if (s != NPX_OK) return s;
+  HIP_TRY(hipMemcpy(w->ctrl, params, need * sizeof(float),
+                    on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+  return NPX_OK;
+}
+
+npx_status npx_step_n(npx_world* w, int64_t n, void* hip_stream) {
+  if (!w) return fail(NPX_EINVAL, "null world");
+  if (n < 0) return fail(NPX_EINVAL, "n must be >= 0");
+  if (n == 0) return NPX_OK;
+  return run_steps(w, n, (hipStream_t)hip_stream);
+}
+
+npx_status npx_read_state(npx_world* w, int field, void* dst, size_t bytes, int on_device) {
+  if (!w || !dst) return fail(NPX_EINVAL, "null argument");
+  size_t row0 = 0, rows = 0;
+  int kind = 0;
+  size_t need = field_bytes(w, field, &row0, &rows, &kind);
+  if (need == 0) return fail(NPX_EINVAL, "unknown field %d", field);
+  if (bytes != need) return fail(NPX_EINVAL, "field %d needs %zu bytes, got %zu", field, need, bytes);
+  npx_status s = sync_last(w);
+  if (s != NPX_OK) return s;
+  const void* src = kind == 0 ? (const void*)(w->st + row0 * w->n_inst)
+                  : kind == 1 ? (const void*)w->step
+                  : kind == 2 ? (const void*)w->flags : (const void*)w->tele;
+  HIP_TRY(hipMemcpy(dst, src, need, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+  return NPX_OK;
+}
+
+npx_status npx_write_state(npx_world* w, int field, const void* src, size_t bytes, int on_device) {
+  if (!w || !src) return fail(NPX_EINVAL, "null argument");
+  size_t row0 = 0, rows = 0;
+  int kind = 0;
+  size_t need = field_bytes(w, field, &row0, &rows, &kind);
+  if (need == 0) return fail(NPX_EINVAL, "unknown field %d", field);
+  if (bytes != need) return fail(NPX_EINVAL, "field %d needs %zu bytes, got %zu", field, need, bytes);
+  npx_status s = sync_last(w);
+  if (s != NPX_OK) return s;
+  void* dst = kind == 0 ? (void*)(w->st + row0 * w->n_inst)
+            : kind == 1 ? (void*)w->step
+            : kind == 2 ? (void*)w->flags : (void*)w->tele;
+  HIP_TRY(hipMemcpy(dst, src, need, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+  return NPX_OK;
+}
+
+npx_status npx_read_points(npx_world* w, float* dst, size_t bytes, int on_device) {
+  if (!w || !dst) return fail(NPX_EINVAL, "null argument");
+  const size_t need = (size_t)w->n_inst * w->n_max * 3 * sizeof(float);
+  if (bytes != need) return fail(NPX_EINVAL, "points need %zu bytes, got %zu", need, bytes);
+  npx_status s = sync_last(w);
+  if (s != NPX_OK) return s;
+  float* buf = nullptr;
+  if (on_device) {
+    buf = dst;
+  } else if (hipMalloc((void**)&buf, need) != hipSuccess) {
+    return fail(NPX_ENOMEM, "points buffer");
+  }
+  npx_status rc = NPX_OK;
+  do {
+    if (hipMemset(buf, 0, need) != hipSuccess) { rc = fail(NPX_EHIP, "memset"); break; }
+    npx::StepArgs a = w->args;
+    a.n_steps = 0;
+    a.queue = nullptr;
+    a.points_out = buf;
+    const int ipw = 64 / w->shape.G;
+    a.n_blocks = (a.n_tasks + ipw - 1) / ipw;
+    hipError_t e = npx::launch_step(a, w->shape, a.n_blocks, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) { rc = fail(NPX_EHIP, "points kernel: %s", hipGetErrorString(e)); break; }
+    if (!on_device && hipMemcpy(dst, buf, need, hipMemcpyDeviceToHost) != hipSuccess) {
+      rc = fail(NPX_EHIP, "points copy");
+      break;
+    }
+  } while (0);
+  if (!on_device) (void)hipFree(buf);
+  return rc;
+}
+
+npx_status npx_get_launch(const npx_world* w, npx_launch* out) {
+  if (!w || !out) return fail(NPX_EINVAL, "null argument");
+  *out = w->launch;
+  return NPX_OK;
+}
+
+npx_status npx_set_launch(npx_world* w, const npx_launch* cfg) {
+  if (!w || !cfg) return fail(NPX_EINVAL, "null argument");
+  npx::Shape s;
+  if (!shape_for(w, cfg->lanes_per_instance, &s))
+    return fail(NPX_EUNSUPPORTED, "no kernel with %d lanes per instance for %d points / %d links",
+                cfg->lanes_per_instance, w->n_max, w->l_max);
+  if (cfg->chunk_steps < 1 || cfg->chunk_steps > 100000)
+    return fail(NPX_EINVAL, "chunk_steps %d out of [1, 100000]", cfg->chunk_steps);
+  if (cfg->persistent && (cfg->waves_per_cu < 1 || cfg->waves_per_cu > 32))
+    return fail(NPX_EINVAL, "waves_per_cu %d out of [1, 32]", cfg->waves_per_cu);
+  npx_status st = sync_last(w);
+  if (st != NPX_OK) return st;
+  w->drop_graphs();
+  w->launch = *cfg;
+  w->shape = s;
+  return NPX_OK;
+}
+
+npx_status npx_autotune(npx_world* w, int32_t steps, void* hip_stream, npx_launch* best,
+                        npx_launch* tried, float* times_ms, int32_t max_results, int32_t* n_tried) {
+  if (!w || steps < 1) return fail(NPX_EINVAL, "bad autotune arguments");
+  hipStream_t s = (hipStream_t)hip_stream;
+  npx_status rc = sync_last(w);
+  if (rc != NPX_OK) return rc;
+  // scratch copies of the mutable state so the world's state is untouched
+  const size_t I = (size_t)w->n_inst;
+  const size_t rows = (size_t)npx::state_rows(w->j_max);
+  float* st2 = nullptr;
+  int *step2 = nullptr, *flags2 = nullptr;
+  double* tele2 = nullptr;
+  if (dalloc(&st2, rows * I) != hipSuccess || dalloc(&step2, I) != hipSuccess ||
+      dalloc(&flags2, I) != hipSuccess || dalloc(&tele2, I * npx::TELE_N) != hipSuccess) {
+    (void)hipFree(st2); (void)hipFree(step2); (void)hipFree(flags2); (void)hipFree(tele2);
+    return fail(NPX_ENOMEM, "autotune scratch");
+  }
+  npx::StepArgs saved = w->args;
+  npx_launch saved_launch = w->launch;
+  npx::Shape saved_shape = w->shape;
+  w->args.st = st2;
+  w->args.step = step2;
+  w->args.flags = flags2;
+  w->args.tele = tele2;
+  std::vector<npx_launch> cands;
+  const int chunk = std::max(1, std::min(steps, saved_launch.chunk_steps));
+  for (int G : {64, 32, 16}) {
+    npx::Shape sh;
+    if (!shape_for(w, G, &sh)) continue;
+    cands.push_back(npx_launch{G, 0, chunk, 0, 8});
+    for (int wpc : {4, 8, 16}) cands.push_back(npx_launch{G, 1, chunk, 0, wpc});
+  }
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  float best_ms = 1e30f;
+  npx_launch best_cfg = saved_launch;
+  int count = 0;
+  rc = NPX_OK;
+  for (const npx_launch& c : cands) {
+    w->drop_graphs();
+    w->launch = c;
+    shape_for(w, c.lanes_per_instance, &w->shape);
+    hipError_t e = hipMemcpyAsync(st2, w->st, rows * I * sizeof(float), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(step2, w->step, I * sizeof(int), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(flags2, w->flags, I * sizeof(int), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) { rc = fail(NPX_EHIP, "autotune copy"); break; }
+    // warm-up (also builds nothing: graphs are off while tuning)
+    if ((rc = run_steps(w, std::min(steps, chunk), s)) != NPX_OK) break;
+    (void)hipEventRecord(e0, s);
+    if ((rc = run_steps(w, steps, s)) != NPX_OK) break;
+    (void)hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(NPX_EHIP, "autotune sync"); break; }
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (tried && times_ms && count < max_results) {
+      tried[count] = c;
+      times_ms[count] = ms;
+    }
+    ++count;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_cfg = c;
+    }
+  }
+  (void)hipStreamSynchronize(s);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  w->drop_graphs();
+  w->args = saved;
+  w->launch = saved_launch;
+  w->shape = saved_shape;
+  (void)hipFree(st2);
+  (void)hipFree(step2);
+  (void)hipFree(flags2);
+  (void)hipFree(tele2);
+  if (n_tried) *n_tried = count;
+  if (rc != NPX_OK) return rc;
+  best_cfg.chunk_steps = saved_launch.chunk_steps;
+  best_cfg.use_graph = saved_launch.use_graph;
+  if (best) *best = best_cfg;
+  return npx_set_launch(w, &best_cfg);
+}
+
+npx_status npx_flops_per_step(const npx_world* w, int64_t i, double* flops) {
+  if (!w || !flops || i < 0 || i >= w->n_inst) return fail(NPX_EINVAL, "bad arguments");
+  const int mi = w->inst_morph[i];
+  const double N = w->morph_points[mi], L = w->morph_links[mi], K = w->K;
+  // per point every frame: two body-to-world transforms (15 + 3 each) and two
+  // table look-ups (4 + 1 each); per point every K frames: y = T rho - g_b (21);
+  // per link every K frames: controller 6, hinge rotation 35 + 18, tree
+  // composition 63, mass properties 131; per robot every frame: ~400
+  // (integration, inertia inverse, quaternion exponential, closed-form fit,
+  // cap, correction, telemetry). Contact-dependent force and moment terms
+  // (~30 per contact point) are not counted.
+  *flops = 46.0 * N + (21.0 * N + 253.0 * L) / K + 400.0;
+  return NPX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,294 @@
+"""Thin ctypes binding of libnpx.so (include/npx.h): argument marshalling only.
+
+Every step of the path runs in the HIP library; this module only packs numpy
+arrays and torch device pointers into the C ABI. Loading fails loudly when the
+library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import os
+
+import numpy as np
+
+from . import workloads as W
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libnpx.so")
+
+NPX_OK = 0
+F_COG, F_QUAT, F_VEL, F_OMEGA, F_JOINT, F_JOINT_PREV, F_STEP, F_FLAGS, F_TELE, F_BODY = range(10)
+CTRL_SINUSOID = 0
+TELE_N = 4
+
+
+class NpxError(RuntimeError):
+    pass
+
+
+class _MorphTables(C.Structure):
+    _fields_ = [("n_points", C.c_int32), ("n_links", C.c_int32),
+                ("points", C.POINTER(C.c_float)), ("pt_link", C.POINTER(C.c_int32)),
+                ("parent", C.POINTER(C.c_int32)), ("joint", C.POINTER(C.c_float))]
+
+
+class _WorldDesc(C.Structure):
+    _fields_ = [("dt", C.c_double), ("joint_interval", C.c_int32), ("g", C.c_double * 3),
+                ("mu", C.c_double), ("k_n", C.c_double), ("zeta", C.c_double),
+                ("eps_lsq", C.c_double), ("hf_nx", C.c_int32), ("hf_ny", C.c_int32),
+                ("hf_s", C.c_double), ("hf_x0", C.c_double), ("hf_y0", C.c_double),
+                ("hf_heights", C.POINTER(C.c_float)), ("n_instances", C.c_int64),
+                ("n_morphs", C.c_int32), ("morphs", C.POINTER(_MorphTables)),
+                ("instance_morph", C.POINTER(C.c_int32)), ("init_pose", C.POINTER(C.c_float)),
+                ("ctrl", C.POINTER(C.c_float))]
+
+
+class Launch(C.Structure):
+    _fields_ = [("lanes_per_instance", C.c_int32), ("persistent", C.c_int32),
+                ("chunk_steps", C.c_int32), ("use_graph", C.c_int32),
+                ("waves_per_cu", C.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """The HIP library; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise NpxError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2411_05799_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.npx_last_error.restype = C.c_char_p
+        L.npx_version.restype = C.c_int
+        L.npx_create_world.argtypes = [C.POINTER(_WorldDesc), C.POINTER(vp)]
+        L.npx_destroy_world.argtypes = [vp]
+        L.npx_destroy_world.restype = None
+        L.npx_world_dims.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int32)]
+        L.npx_set_controller.argtypes = [vp, C.c_int, vp, C.c_size_t, C.c_int]
+        L.npx_step_n.argtypes = [vp, C.c_int64, vp]
+        L.npx_read_state.argtypes = [vp, C.c_int, vp, C.c_size_t, C.c_int]
+        L.npx_write_state.argtypes = [vp, C.c_int, vp, C.c_size_t, C.c_int]
+        L.npx_read_points.argtypes = [vp, vp, C.c_size_t, C.c_int]
+        L.npx_get_launch.argtypes = [vp, C.POINTER(Launch)]
+        L.npx_set_launch.argtypes = [vp, C.POINTER(Launch)]
+        L.npx_autotune.argtypes = [vp, C.c_int32, vp, C.POINTER(Launch), C.POINTER(Launch),
+                                   C.POINTER(C.c_float), C.c_int32, C.POINTER(C.c_int32)]
+        L.npx_flops_per_step.argtypes = [vp, C.c_int64, C.POINTER(C.c_double)]
+        for name in ("npx_create_world", "npx_world_dims", "npx_set_controller", "npx_step_n",
+                     "npx_read_state", "npx_write_state", "npx_read_points", "npx_get_launch",
+                     "npx_set_launch", "npx_autotune", "npx_flops_per_step"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def check(rc):
+    if rc != NPX_OK:
+        raise NpxError(f"npx error {rc}: {lib().npx_last_error().decode()}")
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def j_max_of(morphs):
+    return max(1, max(m.n_links for m in morphs) - 1)
+
+
+def pack_ctrl(ctrl_list, j_max):
+    """Per-instance [J_i, 3] controllers -> [I][J_max][3] float32."""
+    out = np.zeros((len(ctrl_list), j_max, 3), dtype=np.float32)
+    for i, c in enumerate(ctrl_list):
+        out[i, : c.shape[0]] = c
+    return out
+
+
+class World:
+    """A world on the current HIP device (npx_create_world ... npx_destroy_world)."""
+
+    def __init__(self, w: W.Workload):
+        self.workload = w
+        self._keep = []
+        morphs = (_MorphTables * len(w.morphs))()
+        for i, m in enumerate(w.morphs):
+            arrs = (_f32(m.points), _i32(m.pt_link), _i32(m.parent), _f32(m.joint))
+            self._keep.append(arrs)
+            morphs[i] = _MorphTables(m.n_points, m.n_links,
+                                     arrs[0].ctypes.data_as(C.POINTER(C.c_float)),
+                                     arrs[1].ctypes.data_as(C.POINTER(C.c_int32)),
+                                     arrs[2].ctypes.data_as(C.POINTER(C.c_int32)),
+                                     arrs[3].ctypes.data_as(C.POINTER(C.c_float)))
+        self.j_max_expected = j_max_of(w.morphs)
+        H = _f32(w.hf.H)
+        im = _i32(w.inst_morph)
+        pose = _f32(w.pose)
+        ctrl = pack_ctrl(w.ctrl, self.j_max_expected)
+        self._keep += [morphs, H, im, pose, ctrl]
+        p = w.params
+        desc = _WorldDesc(float(p.dt), int(p.K), (C.c_double * 3)(*map(float, p.g)), float(p.mu),
+                          float(p.k_n), float(p.zeta), float(p.eps), int(w.hf.nx), int(w.hf.ny),
+                          float(w.hf.s), float(w.hf.x0), float(w.hf.y0),
+                          H.ctypes.data_as(C.POINTER(C.c_float)), int(w.n_instances),
+                          len(w.morphs), morphs, im.ctypes.data_as(C.POINTER(C.c_int32)),
+                          pose.ctypes.data_as(C.POINTER(C.c_float)),
+                          ctrl.ctypes.data_as(C.POINTER(C.c_float)))
+        h = C.c_void_p()
+        check(lib().npx_create_world(C.byref(desc), C.byref(h)))
+        self.h = h
+        self._keep = None
+        n, j, nm = C.c_int64(), C.c_int32(), C.c_int32()
+        check(lib().npx_world_dims(self.h, C.byref(n), C.byref(j), C.byref(nm)))
+        self.n_instances, self.j_max, self.n_max = int(n.value), int(j.value), int(nm.value)
+        assert self.j_max == self.j_max_expected
+
+    # -- lifetime ---------------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None):
+            lib().npx_destroy_world(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- calls ------------------------------------------------------------------
+    def set_controller(self, ctrl):
+        """ctrl: list of per-instance [J_i, 3] arrays, an [I, J_max, 3] array or a
+        torch device tensor of that shape."""
+        if hasattr(ctrl, "data_ptr"):
+            check(lib().npx_set_controller(self.h, CTRL_SINUSOID, C.c_void_p(ctrl.data_ptr()),
+                                           ctrl.numel(), 1))
+            return
+        arr = pack_ctrl(ctrl, self.j_max) if isinstance(ctrl, list) else _f32(ctrl)
+        check(lib().npx_set_controller(self.h, CTRL_SINUSOID, arr.ctypes.data_as(C.c_void_p),
+                                       arr.size, 0))
+
+    def step_n(self, n, stream=None):
+        """Advance n frames asynchronously on `stream` (a torch.cuda.Stream or raw handle)."""
+        s = _stream_handle(stream)
+        check(lib().npx_step_n(self.h, int(n), C.c_void_p(s)))
+
+    def _field_shape(self, field):
+        I = self.n_instances
+        return {F_COG: ((3, I), np.float32), F_QUAT: ((4, I), np.float32),
+                F_VEL: ((3, I), np.float32), F_OMEGA: ((3, I), np.float32),
+                F_JOINT: ((self.j_max, I), np.float32), F_JOINT_PREV: ((self.j_max, I), np.float32),
+                F_STEP: ((I,), np.int32), F_FLAGS: ((I,), np.int32),
+                F_TELE: ((TELE_N, I), np.float64), F_BODY: ((13, I), np.float32)}[field]
+
+    def read_state(self, field, out=None):
+        """Field as a numpy array (or into a torch device tensor `out`)."""
+        shape, dt = self._field_shape(field)
+        if out is not None and hasattr(out, "data_ptr"):
+            check(lib().npx_read_state(self.h, field, C.c_void_p(out.data_ptr()),
+                                       out.numel() * out.element_size(), 1))
+            return out
+        a = np.empty(shape, dtype=dt)
+        check(lib().npx_read_state(self.h, field, a.ctypes.data_as(C.c_void_p), a.nbytes, 0))
+        return a
+
+    def write_state(self, field, value):
+        shape, dt = self._field_shape(field)
+        if hasattr(value, "data_ptr"):
+            check(lib().npx_write_state(self.h, field, C.c_void_p(value.data_ptr()),
+                                        value.numel() * value.element_size(), 1))
+            return
+        a = np.ascontiguousarray(value, dtype=dt).reshape(shape)
+        check(lib().npx_write_state(self.h, field, a.ctypes.data_as(C.c_void_p), a.nbytes, 0))
+
+    def read_points(self):
+        a = np.empty((self.n_instances, self.n_max, 3), dtype=np.float32)
+        check(lib().npx_read_points(self.h, a.ctypes.data_as(C.c_void_p), a.nbytes, 0))
+        return a
+
+    def get_launch(self) -> Launch:
+        l = Launch()
+        check(lib().npx_get_launch(self.h, C.byref(l)))
+        return l
+
+    def set_launch(self, **kw):
+        l = self.get_launch()
+        for k, v in kw.items():
+            setattr(l, k, int(v))
+        check(lib().npx_set_launch(self.h, C.byref(l)))
+        return l
+
+    def autotune(self, steps=50, stream=None, cache=None, key=None):
+        """Pick the fastest launch shape; with `cache` (a JSON path) and `key`,
+        reuse an earlier choice for the same workload key."""
+        if cache and key and os.path.exists(cache):
+            try:
+                with open(cache) as f:
+                    known = json.load(f)
+                if key in known:
+                    self.set_launch(**known[key]["best"])
+                    return known[key]
+            except (OSError, ValueError):
+                pass
+        best = Launch()
+        tried = (Launch * 32)()
+        times = (C.c_float * 32)()
+        n = C.c_int32()
+        check(lib().npx_autotune(self.h, int(steps), C.c_void_p(_stream_handle(stream)),
+                                 C.byref(best), tried, times, 32, C.byref(n)))
+        rec = {"best": best.as_dict(),
+               "tried": [dict(tried[i].as_dict(), ms=float(times[i])) for i in range(n.value)]}
+        if cache and key:
+            known = {}
+            if os.path.exists(cache):
+                try:
+                    with open(cache) as f:
+                        known = json.load(f)
+                except (OSError, ValueError):
+                    known = {}
+            known[key] = rec
+            with open(cache, "w") as f:
+                json.dump(known, f, indent=1, sort_keys=True)
+        return rec
+
+    def flops_per_step(self, i=None):
+        """Algorithmic FP32 operations of one frame (instance i, or summed over all)."""
+        idx = range(self.n_instances) if i is None else [i]
+        tot = 0.0
+        d = C.c_double()
+        for k in idx:
+            check(lib().npx_flops_per_step(self.h, int(k), C.byref(d)))
+            tot += d.value
+        return tot
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return int(stream.cuda_stream)
+    return int(stream)
+
+
+def exported_symbols():
+    """Names of every function declared in include/npx.h."""
+    import re
+    hdr = os.path.join(os.path.dirname(PKG), "include", "npx.h")
+    txt = re.sub(r"/\*.*?\*/", "", open(hdr).read(), flags=re.S)
+    txt = re.sub(r"//[^\n]*", "", txt)
+    return sorted(set(re.findall(r"\b(npx_[a-z_0-9]+)\s*\(", txt)))

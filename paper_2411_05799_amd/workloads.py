@@ -234,7 +234,7 @@ def random_legged(rng: np.random.Generator) -> Morph:
 
 def flat_ground(s: float = 50.0) -> Heightfield:
     """Flat plane z = 0: a single cell, every look-up clamps onto it."""
-    return Heightfield(nx=1, ny=1, s=s, x0=-5.12, y0=-5.12,
+    return Heightfield(nx=1, ny=1, s=s, x0=float(np.float32(-5.12)), y0=float(np.float32(-5.12)),
                        H=np.zeros((1, 1), dtype=np.float32), height_fn=None)
 
 
@@ -262,8 +262,8 @@ def octave_terrain(seed: int, nx: int = 512, ny: int = 512, cell: float = 0.02,
                                       + np.sin(2 * np.pi * y / lam[o] + ps[o]))
         return out
 
-    x0 = -0.5 * nx * cell
-    y0 = -0.5 * ny * cell
+    x0 = float(np.float32(-0.5 * nx * cell))   # float32-representable origin
+    y0 = float(np.float32(-0.5 * ny * cell))
     xc = x0 + (np.arange(nx) + 0.5) * cell
     yc = y0 + (np.arange(ny) + 0.5) * cell
     H = h(xc[None, :], yc[:, None]).astype(np.float32)

@@ -1,0 +1,282 @@
+"""GPU FP32 path vs the FP64 oracle, through the C ABI.
+
+Tolerances: 200-frame windows from identical FP32-representable states agree to
+1e-4 m (CoG and every mass point) and 1e-3 rad (joint angles, torso
+orientation); long-horizon statistics (distance walked, mean torso height) over
+10,000 frames agree to 2%. Integer results (frame counters, flags) and
+determinism properties are bit-exact.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2411_05799_amd import native as N
+from paper_2411_05799_amd import workloads as W
+
+from _helpers import (ANG_TOL, POS_TOL, STAT_TOL, gpu_available, read_states, run_windows,
+                      write_states)
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a HIP device")]
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def assert_windows(results, label):
+    worst = max(results, key=lambda r: max(r[2].cog, r[2].pts) / POS_TOL
+                + max(r[2].joint, r[2].orient) / ANG_TOL)
+    say(f"{label}: {len(results)} windows, worst (start {worst[0]}, inst {worst[1]}): {worst[2]}")
+    bad = [(s, i, st) for s, i, st in results if not st.ok()]
+    assert not bad, f"{len(bad)} windows out of tolerance, e.g. {bad[:3]}"
+
+
+def test_placement_matches_oracle():
+    say("case: placement config1 + hexapod batch 16")
+    for w in (W.config1(), W.hexapod_batch(16, seed=5)):
+        ow = O.OracleWorld(w)
+        with N.World(w) as gw:
+            got = read_states(gw, range(w.n_instances), lambda i: 18)
+        for i in range(w.n_instances):
+            ref = ow.init_state(i)
+            assert np.abs(ref[:13] - got[i][:13]).max() < 2e-6
+            assert np.abs(ref[O.HDR:] - got[i][O.HDR:]).max() < 2e-6
+
+
+def test_config1_windows_all_10k():
+    """Config 1 (one hexapod, flat plane): every 200-frame window of 10,000 frames."""
+    say("case: config1 windows, 50 x 200 frames")
+    w = W.config1()
+    ow = O.OracleWorld(w)
+    with N.World(w) as gw:
+        res = run_windows(ow, gw, [0], starts=list(range(0, 10_000, 200)))
+    assert_windows(res, "config1")
+
+
+def test_config1_long_horizon_statistics():
+    """Distance walked and mean torso height over 10,000 frames within 2%."""
+    say("case: config1 long horizon 10k")
+    w = W.config1()
+    ow = O.OracleWorld(w)
+    st = ow.init_state(0)
+    c0 = st[:2].copy()
+    ow.run(0, st, 10_000)
+    with N.World(w) as gw:
+        g0 = gw.read_state(N.F_COG)[:2, 0].astype(np.float64)
+        gw.step_n(10_000)
+        g = read_states(gw, [0], lambda i: 18)[0]
+    d_ref = float(np.linalg.norm(st[:2] - c0))
+    d_gpu = float(np.linalg.norm(g[:2] - g0))
+    h_ref = st[O.TELE] / 10_000
+    h_gpu = g[O.TELE] / 10_000
+    say(f"distance oracle {d_ref:.4f} m gpu {d_gpu:.4f} m; torso height oracle {h_ref:.5f} "
+        f"gpu {h_gpu:.5f} m")
+    assert int(g[O.STEP]) == 10_000 and int(g[O.FLAGS]) == 0
+    assert abs(d_gpu - d_ref) <= STAT_TOL * d_ref
+    assert abs(h_gpu - h_ref) <= STAT_TOL * h_ref
+
+
+def test_config2_full_size_sampled_windows():
+    """4,096 hexapods on the 512x512 terrain at the bench's launch shape: 32 sampled
+    instances x 5 windows of 200 frames."""
+    say("case: config2 4096 instances, 32 sampled x 5 windows")
+    w = W.config2()
+    ow = O.OracleWorld(w)
+    rng = np.random.default_rng(2)
+    idx = sorted(rng.choice(w.n_instances, size=32, replace=False).tolist())
+    with N.World(w) as gw:
+        from bench import pick_launch
+        pick_launch(gw, w)
+        res = run_windows(ow, gw, idx, starts=[0, 200, 400, 600, 800], every=40)
+    assert_windows(res, "config2")
+
+
+@pytest.mark.parametrize("lanes", [64, 32, 16])
+def test_launch_shapes_ragged_batch(lanes):
+    """37 hexapods on terrain (a ragged tail for every instances-per-wave) under each
+    lanes-per-robot shape, grid and persistent."""
+    say(f"case: ragged batch 37, lanes {lanes}")
+    w = W.hexapod_batch(37, seed=9, spread=1.0)
+    ow = O.OracleWorld(w)
+    for persistent in (0, 1):
+        with N.World(w) as gw:
+            gw.set_launch(lanes_per_instance=lanes, persistent=persistent, waves_per_cu=2)
+            res = run_windows(ow, gw, [0, 17, 36], starts=[0, 300], every=50)
+        assert_windows(res, f"lanes {lanes} persistent {persistent}")
+
+
+def test_uneven_morphologies():
+    """Config-3 style uneven batch (4/6/8 legs, 2-4 joints, 200-600 points)."""
+    say("case: uneven batch 48")
+    w = W.config3(n_inst=48)
+    ow = O.OracleWorld(w)
+    with N.World(w) as gw:
+        res = run_windows(ow, gw, list(range(0, 48, 5)), starts=[0, 400], every=50)
+    assert_windows(res, "uneven")
+
+
+def max_robot():
+    """1,024 points on 64 links: eight legs, seven of 8 links and one of 7."""
+    counts = [8] * 7 + [7]
+    per = np.full(63, 960 // 63)
+    per[: 960 - per.sum()] += 1
+    it = iter(per.tolist())
+    m = W.legged(leg_x=list(np.linspace(-0.12, 0.12, 4)),
+                 link_len=[[0.05] * (n - 1) + [0.1] for n in counts],
+                 link_mass=[[0.05] * n for n in counts],
+                 pts_per_link=[[next(it) for _ in range(n)] for n in counts], name="max")
+    assert m.n_points == 1024 and m.n_links == 64
+    return m
+
+
+def test_max_size_robot():
+    """The largest robot the kernels take: 1,024 points on 64 links."""
+    say("case: max-size robot 1024 points 64 links")
+    rng = np.random.default_rng(1)
+    m = max_robot()
+    ctrl = [W.sinusoid_controller(rng, m.n_joints) * np.array([0.3, 1, 1], np.float32)]
+    w = W.Workload(params=W.Params(), hf=W.octave_terrain(4), morphs=[m],
+                   inst_morph=np.zeros(1, np.int32), ctrl=ctrl,
+                   pose=np.array([[0, 0, 0.3, 1, 0, 0, 0]], np.float32))
+    ow = O.OracleWorld(w)
+    with N.World(w) as gw:
+        res = run_windows(ow, gw, [0], starts=[0, 200, 600], every=50)
+    assert_windows(res, "max robot")
+
+
+def test_degenerate_bodies_and_paper_mode():
+    """A single mass point (singular inertia), a box in free flight, mu = inf, and the
+    paper's own operating point (10 ms frames, joints every 8 frames, 0.1 m cells)."""
+    say("case: degenerate bodies / paper mode")
+    pt = W.Morph(points=np.array([[0, 0, 0, 1.0]], np.float32), pt_link=np.zeros(1, np.int32),
+                 parent=np.array([-1], np.int32), joint=np.zeros((1, 8), np.float32), name="pt")
+    box = W.Morph(points=np.array([[sx * 0.1, sy * 0.05, sz * 0.025, 0.125]
+                                   for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)],
+                                  np.float32),
+                  pt_link=np.zeros(8, np.int32), parent=np.array([-1], np.int32),
+                  joint=np.zeros((1, 8), np.float32), name="box")
+    hexa = W.hexapod()
+    cases = [
+        (W.Params(), pt, [0.0, 0.0, 0.05]),
+        (W.Params(mu=math.inf), box, [0.0, 0.0, 0.06]),
+        (W.Params(), box, [0.0, 0.0, 5.0]),
+        (W.Params(dt=1e-2, K=8, k_n=1000.0, zeta=5.0), hexa, [0.0, 0.0, 0.15]),
+    ]
+    for p, m, xyz in cases:
+        hf = W.flat_ground(s=10.0) if p.dt > 5e-3 else W.octave_terrain(6)
+        rng = np.random.default_rng(3)
+        w = W.Workload(params=p, hf=hf, morphs=[m], inst_morph=np.zeros(1, np.int32),
+                       ctrl=[W.sinusoid_controller(rng, max(m.n_joints, 0))],
+                       pose=np.array([xyz + [1, 0, 0, 0]], np.float32))
+        ow = O.OracleWorld(w)
+        with N.World(w) as gw:
+            res = run_windows(ow, gw, [0], starts=[0, 200], every=25)
+        assert_windows(res, f"{m.name} dt={p.dt} K={p.K} mu={p.mu}")
+
+
+def _body(gw):
+    return np.concatenate([gw.read_state(N.F_BODY).ravel(), gw.read_state(N.F_JOINT).ravel(),
+                           gw.read_state(N.F_STEP).astype(np.float32).ravel()])
+
+
+def test_bitwise_chunking_graphs_and_persistence():
+    """A trajectory does not depend on chunk length, hipGraph replay or the
+    persistent queue (same lanes per robot): bit-identical states."""
+    say("case: bitwise chunking / graphs / persistent")
+    w = W.hexapod_batch(40, seed=11)
+    out = []
+    for chunk, graph, pers in ((100, 1, 0), (7, 0, 0), (33, 1, 1), (300, 0, 1)):
+        with N.World(w) as gw:
+            gw.set_launch(lanes_per_instance=32, chunk_steps=chunk, use_graph=graph,
+                          persistent=pers, waves_per_cu=3)
+            gw.step_n(150)
+            gw.step_n(150)
+            out.append(_body(gw))
+    for o in out[1:]:
+        np.testing.assert_array_equal(out[0], o)
+
+
+def test_bitwise_batch_composition():
+    """Instance results are the same alone or inside any batch."""
+    say("case: bitwise batch composition")
+    w = W.hexapod_batch(24, seed=12)
+    with N.World(w) as gw:
+        gw.set_launch(lanes_per_instance=16)
+        gw.step_n(300)
+        full = gw.read_state(N.F_BODY)
+    for pick in ([5], [5, 0, 23], [23, 22, 21, 20, 19]):
+        sub = W.subset(w, pick)
+        with N.World(sub) as gs:
+            gs.set_launch(lanes_per_instance=16)
+            gs.step_n(300)
+            part = gs.read_state(N.F_BODY)
+        np.testing.assert_array_equal(part, full[:, pick])
+
+
+def test_health_flag_isolates_instance():
+    """A NaN written into one instance flags and freezes it; the others continue
+    bit-identically to a clean run."""
+    say("case: health isolation")
+    w = W.hexapod_batch(8, seed=13)
+    with N.World(w) as clean:
+        clean.step_n(200)
+        ref = clean.read_state(N.F_BODY)
+    with N.World(w) as gw:
+        om = gw.read_state(N.F_OMEGA)
+        om[0, 3] = np.nan
+        gw.write_state(N.F_OMEGA, om)
+        gw.step_n(200)
+        got = gw.read_state(N.F_BODY)
+        flags = gw.read_state(N.F_FLAGS)
+        steps = gw.read_state(N.F_STEP)
+    assert flags[3] & 1 and steps[3] == 1
+    others = [i for i in range(8) if i != 3]
+    np.testing.assert_array_equal(got[:, others], ref[:, others])
+    assert (flags[others] == 0).all() and (steps[others] == 200).all()
+    # the oracle flags the same instance the same way
+    ow = O.OracleWorld(w)
+    st = ow.init_state(3)
+    st[O.W_] = np.nan
+    ow.run(3, st, 5)
+    assert int(st[O.FLAGS]) & 1 and int(st[O.STEP]) == 1
+
+
+def test_checkpoint_resume_is_exact():
+    say("case: checkpoint/resume")
+    w = W.hexapod_batch(12, seed=14)
+    fields = [N.F_BODY, N.F_JOINT, N.F_JOINT_PREV, N.F_STEP, N.F_FLAGS, N.F_TELE]
+    with N.World(w) as gw:
+        gw.step_n(100)
+        saved = {f: gw.read_state(f) for f in fields}
+        gw.step_n(100)
+        a = {f: gw.read_state(f) for f in fields}
+        for f in fields:
+            gw.write_state(f, saved[f])
+        gw.step_n(100)
+        b = {f: gw.read_state(f) for f in fields}
+    for f in fields:
+        np.testing.assert_array_equal(a[f], b[f])
+
+
+def test_torch_stream_and_device_buffers():
+    """Stepping on a torch stream and reading into a torch device tensor."""
+    say("case: torch stream / device tensors")
+    import torch
+    w = W.hexapod_batch(10, seed=15)
+    with N.World(w) as gw:
+        s = torch.cuda.Stream()
+        gw.step_n(50, stream=s)
+        t = torch.empty((13, 10), dtype=torch.float32, device="cuda")
+        gw.read_state(N.F_BODY, out=t)
+        host = gw.read_state(N.F_BODY)
+        np.testing.assert_array_equal(t.cpu().numpy(), host)
+        ctrl = torch.zeros((10, gw.j_max, 3), dtype=torch.float32, device="cuda")
+        gw.set_controller(ctrl)
+        gw.step_n(10, stream=s)
+        q = gw.read_state(N.F_JOINT)
+        assert np.abs(q).max() == 0.0   # zero controller holds the joints at 0
