@@ -81,6 +81,9 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=250)
     ap.add_argument("--cpu-threads", type=int, default=int(os.environ.get("OMP_NUM_THREADS", "0") or 0))
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--lanes", type=int, default=0,
+                    help="lanes per robot (16/32/64); 0 = let the autotuner choose")
+    ap.add_argument("--persistent", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the instances "
@@ -96,7 +99,11 @@ def main():
     w = W.config2(n_inst=args.instances, n_steps=args.steps)
     gw = N.World(w)
     stream = torch.cuda.Stream()
-    tune = pick_launch(gw, w, stream=stream)
+    if args.lanes:
+        gw.set_launch(lanes_per_instance=args.lanes, persistent=args.persistent)
+        tune = {"tried": []}
+    else:
+        tune = pick_launch(gw, w, stream=stream)
     launch = gw.get_launch().as_dict()
     chunk = launch["chunk_steps"]
 

@@ -34,7 +34,7 @@ struct StepArgs {
   const int* link_parent; // [total links]
   const int* link_depth;  // [total links]
   const float* ctrl;      // [n_inst][j_max][3] A f phi
-  float dt;
+  float dt, inv_dt;
   double dt_d;
   int K;
   float gx, gy, gz;

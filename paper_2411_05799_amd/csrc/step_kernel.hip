@@ -6,12 +6,13 @@
 // (link l on lane l mod G, slot l / G). Per-robot scalars (CoG, orientation,
 // velocities, forces, the friction fit) are kept redundantly in every lane of
 // the segment, so the per-point phases need no broadcast. Segment-wide sums
-// (contact force and torque, link mass properties, the seven friction moments)
-// are butterfly reductions inside the segment; every lane ends with the same
-// bits, and the order is fixed, so a robot's trajectory does not depend on
-// which segment or wave runs it. Link transforms pass from link lanes to point
-// lanes through LDS. The state stays in registers for a whole launch of
-// n_steps frames and touches HBM once at each end.
+// (contact force and torque, link mass properties, the friction moments) are
+// all-reductions made of DPP adds inside 16-lane rows and permlane swaps
+// across rows; every lane ends with the same bits and the order is fixed, so
+// a robot's trajectory does not depend on which segment or wave runs it. Link
+// transforms pass from link lanes to point lanes through LDS. The state stays
+// in registers for a whole launch of n_steps frames and touches HBM once at
+// each end.
 //
 // The frame (Sec. III; readings as in the oracle):
 //   S1 detection of every point against the height-map table (Sec. III-A)
@@ -20,9 +21,20 @@
 //      new body points about the unchanged world CoG
 //   S4 trial semi-implicit Euler step to the predicted points P*
 //   S5 friction set: in contact at P^n and at P* (eq. 3)
-//   S6 the normal equations (4)-(6) solved in closed form on slip moments
+//   S6 the normal equations (4)-(6) solved in closed form
 //   S7 cap by the maximum static friction mu F_N (Sec. III-C)
 //   S8 move back by the capped fit, remove the matching velocity, commit
+//
+// Precision of the friction fit. The fit works on the slip delta = P* - P^n
+// of each contact point, typically 1e-5..1e-3 m, while body points sit 0.1 m
+// or more from the CoG. Taking delta as the difference of two independently
+// rounded float32 positions would leave ~4e-8 m of incoherent noise per point,
+// and with two or three contact points that noise dominates the fitted
+// rotation. The slip is therefore built from increments that float32 holds
+// accurately: the joint-angle increment is pushed down the link tree as a
+// transform increment dT (forward kinematics of the change), and the body
+// rotation increment comes straight from the rotation quaternion:
+//   delta = (R1 - R) r_old + R1 dr + (c1 - c),  R1 - R = (R(dq) - I) R.
 #include "npx_internal.h"
 
 namespace npx {
@@ -32,10 +44,37 @@ namespace {
 constexpr float kTwoPi = 6.28318530717958647692f;
 constexpr double kInvTwoPi = 0.15915494309189533577;
 
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float swap_sum16(float x) {
+  auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, x),
+                                            __builtin_bit_cast(unsigned, x), false, false);
+  return __builtin_bit_cast(float, (unsigned)r[0]) + __builtin_bit_cast(float, (unsigned)r[1]);
+}
+
+__device__ __forceinline__ float swap_sum32(float x) {
+  auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, x),
+                                            __builtin_bit_cast(unsigned, x), false, false);
+  return __builtin_bit_cast(float, (unsigned)r[0]) + __builtin_bit_cast(float, (unsigned)r[1]);
+}
+
+// Sum over the G-lane segment, result in every lane of it: lanes exchange with
+// quad partners, then the mirrored half-row and row (DPP), then the other row
+// (permlane16 swap) and the other half-wave (permlane32 swap). Each step adds
+// two operands in an order every lane shares.
 template <int G>
 __device__ __forceinline__ float seg_sum(float x) {
-#pragma unroll
-  for (int off = G / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  static_assert(G == 16 || G == 32 || G == 64, "segment of 16, 32 or 64 lanes");
+  x += dpp<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += dpp<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += dpp<0x141>(x);  // row_half_mirror
+  x += dpp<0x140>(x);  // row_mirror
+  if constexpr (G >= 32) x = swap_sum16(x);
+  if constexpr (G >= 64) x = swap_sum32(x);
   return x;
 }
 
@@ -59,6 +98,16 @@ __device__ __forceinline__ void sin_cos(float x, float* s, float* c) {
   *c = ((q + 1) & 2) ? -cc : cc;
 }
 
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Points are processed in groups of kGroup per lane; the scheduler may overlap
+// the loads of one group with the arithmetic of the next but not hoist every
+// point's loads to the top of a loop, which would cost a register set per point.
+constexpr int kGroup = 2;
+__device__ __forceinline__ void group_fence(int p) {
+  if ((p + 1) % kGroup == 0) __builtin_amdgcn_sched_barrier(0);
+}
+
 __device__ __forceinline__ void quat_to_mat(float w, float x, float y, float z, float R[9]) {
   float xx = x * x, yy = y * y, zz = z * z;
   float xy = x * y, xz = x * z, yz = y * z, wx = w * x, wy = w * y, wz = w * z;
@@ -78,9 +127,12 @@ __device__ __forceinline__ float hf_at(const StepArgs& a, float x, float y) {
 
 enum Mode { kStep = 0, kPlace = 1, kPoints = 2 };
 
+// LDS rows of one link: [R row 0 | t0], [R row 1 | t1], [R row 2 | t2].
+using LinkT = float4[3];
+
 template <int G, int PPL, int LPL, int MODE>
-__device__ __forceinline__ void run_block(const StepArgs& a, float4 (*T)[3], int tb, int seg,
-                                          int sl) {
+__device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT, int tb,
+                                          int seg, int sl) {
   constexpr int IPW = 64 / G;
   const int I = a.n_inst;
   const int task = tb * IPW + seg;
@@ -92,6 +144,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, float4 (*T)[3], int
   const int L = valid ? info.w : 1;
   const int pt_off = info.x, lk_off = info.z;
   const float M = a.morph_mass[mi];
+  const float invM = rcp(M);
   const float* st = a.st;
 
   // ---- links of this lane: table row and joint angles (the rest of the link
@@ -126,42 +179,64 @@ __device__ __forceinline__ void run_block(const StepArgs& a, float4 (*T)[3], int
 #pragma unroll
   for (int i = 0; i < TELE_N; ++i) tele[i] = a.tele[(size_t)i * I + inst];
 
-  // ---- body points about the CoG and mass properties at angles q
+  // ---- body points about the CoG, mass properties, and their increments
   float rx[PPL], ry[PPL], rz[PPL];
-  float gb[3], Iinv[6], Ib[6];
-  bool Ireg;
+  float gb[3], dgb[3], Ib[6], Iinv[6];
 
-  auto forward_kinematics = [&]() __attribute__((always_inline)) {
-    // joint-local transforms x -> Rj x + tj (rotation about the hinge through its anchor)
-    float Rl[LPL][9], tl[LPL][3];
+  // Forward kinematics at angles q, with the increment from angles q - dql
+  // (dql = 0: no joint moved). Writes T, dT for every link of the segment.
+  auto forward_kinematics = [&](const float* dql) __attribute__((always_inline)) {
+    float Rj[LPL][9], tj[LPL][3], dRj[LPL][9], dtj[LPL][3];
 #pragma unroll
     for (int l = 0; l < LPL; ++l) {
       const float* lk = a.links + (size_t)lrow[l] * LINK_F;
       const float ao[3] = {lk[0], lk[1], lk[2]};
       float x = lk[3], y = lk[4], z = lk[5];
       const float n2 = x * x + y * y + z * z;
-      const float inv = n2 > 0.f ? 1.f / sqrtf(n2) : 0.f;
+      const float inv = n2 > 0.f ? __builtin_amdgcn_rsqf(n2) : 0.f;
       x *= inv;
       y *= inv;
       z *= inv;
+      // Rj = cos 1 + sin K + (1 - cos) a a^T with K = [a]x (Rodrigues)
       float s, co;
       sin_cos(q[l], &s, &co);
       const float C1 = 1.f - co;
-      float Rj[9] = {co + x * x * C1,     x * y * C1 - z * s, x * z * C1 + y * s,
-                     y * x * C1 + z * s,  co + y * y * C1,    y * z * C1 - x * s,
-                     z * x * C1 - y * s,  z * y * C1 + x * s, co + z * z * C1};
+      const float R0[9] = {co + x * x * C1,    x * y * C1 - z * s, x * z * C1 + y * s,
+                           y * x * C1 + z * s, co + y * y * C1,    y * z * C1 - x * s,
+                           z * x * C1 - y * s, z * y * C1 + x * s, co + z * z * C1};
+      // increment Rj(q) - Rj(q - dq) = -Rj(q) E(-dq), E(t) = sin t K + (1 - cos t) K^2,
+      // K^2 = a a^T - 1, with 1 - cos t = 2 sin^2(t/2) to keep small angles exact
+      float se, ce, sh, ch;
+      sin_cos(-dql[l], &se, &ce);
+      sin_cos(-0.5f * dql[l], &sh, &ch);
+      const float ve = 2.f * sh * sh;
+      const float E[9] = {ve * (x * x - 1.f), ve * x * y - se * z,  ve * x * z + se * y,
+                          ve * y * x + se * z, ve * (y * y - 1.f),  ve * y * z - se * x,
+                          ve * z * x - se * y, ve * z * y + se * x, ve * (z * z - 1.f)};
 #pragma unroll
-      for (int i = 0; i < 9; ++i) Rl[l][i] = Rj[i];
+      for (int i = 0; i < 3; ++i) {
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
-        tl[l][i] = ao[i] - (Rj[3 * i] * ao[0] + Rj[3 * i + 1] * ao[1] + Rj[3 * i + 2] * ao[2]);
+        for (int k = 0; k < 3; ++k) {
+          Rj[l][3 * i + k] = R0[3 * i + k];
+          dRj[l][3 * i + k] =
+              -(R0[3 * i] * E[k] + R0[3 * i + 1] * E[3 + k] + R0[3 * i + 2] * E[6 + k]);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        tj[l][i] = ao[i] - (R0[3 * i] * ao[0] + R0[3 * i + 1] * ao[1] + R0[3 * i + 2] * ao[2]);
+        dtj[l][i] = -(dRj[l][3 * i] * ao[0] + dRj[l][3 * i + 1] * ao[1] +
+                      dRj[l][3 * i + 2] * ao[2]);
+      }
     }
     if (sl == 0) {
       T[0][0] = make_float4(1.f, 0.f, 0.f, 0.f);
       T[0][1] = make_float4(0.f, 1.f, 0.f, 0.f);
       T[0][2] = make_float4(0.f, 0.f, 1.f, 0.f);
+      dT[0][0] = dT[0][1] = dT[0][2] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    // link transforms down the tree, one depth level at a time
+    // link transforms and their increments down the tree, one depth level at a time:
+    //   R = Rp Rj, t = Rp tj + tp, dR = dRp Rj + (Rp - dRp) dRj, dt = dRp tj + (Rp - dRp) dtj + dtp
     for (int lev = 1; lev <= a.max_depth; ++lev) {
       __syncthreads();
 #pragma unroll
@@ -169,46 +244,65 @@ __device__ __forceinline__ void run_block(const StepArgs& a, float4 (*T)[3], int
         if (lv[l] && a.link_depth[lrow[l]] == lev) {
           const int par = a.link_parent[lrow[l]];
           const float4 p0 = T[par][0], p1 = T[par][1], p2 = T[par][2];
+          const float4 d0 = dT[par][0], d1 = dT[par][1], d2 = dT[par][2];
           const float Rp[9] = {p0.x, p0.y, p0.z, p1.x, p1.y, p1.z, p2.x, p2.y, p2.z};
           const float tp[3] = {p0.w, p1.w, p2.w};
-          float R[9], t[3];
+          const float dRp[9] = {d0.x, d0.y, d0.z, d1.x, d1.y, d1.z, d2.x, d2.y, d2.z};
+          const float dtp[3] = {d0.w, d1.w, d2.w};
+          float R[9], t[3], dR[9], dt[3];
 #pragma unroll
           for (int i = 0; i < 3; ++i) {
+            const float Po[3] = {Rp[3 * i] - dRp[3 * i], Rp[3 * i + 1] - dRp[3 * i + 1],
+                                 Rp[3 * i + 2] - dRp[3 * i + 2]};
 #pragma unroll
-            for (int k = 0; k < 3; ++k)
-              R[3 * i + k] = Rp[3 * i] * Rl[l][k] + Rp[3 * i + 1] * Rl[l][3 + k] +
-                             Rp[3 * i + 2] * Rl[l][6 + k];
-            t[i] = Rp[3 * i] * tl[l][0] + Rp[3 * i + 1] * tl[l][1] + Rp[3 * i + 2] * tl[l][2] +
+            for (int k = 0; k < 3; ++k) {
+              R[3 * i + k] = Rp[3 * i] * Rj[l][k] + Rp[3 * i + 1] * Rj[l][3 + k] +
+                             Rp[3 * i + 2] * Rj[l][6 + k];
+              dR[3 * i + k] = dRp[3 * i] * Rj[l][k] + dRp[3 * i + 1] * Rj[l][3 + k] +
+                              dRp[3 * i + 2] * Rj[l][6 + k] + Po[0] * dRj[l][k] +
+                              Po[1] * dRj[l][3 + k] + Po[2] * dRj[l][6 + k];
+            }
+            t[i] = Rp[3 * i] * tj[l][0] + Rp[3 * i + 1] * tj[l][1] + Rp[3 * i + 2] * tj[l][2] +
                    tp[i];
+            dt[i] = dRp[3 * i] * tj[l][0] + dRp[3 * i + 1] * tj[l][1] +
+                    dRp[3 * i + 2] * tj[l][2] + Po[0] * dtj[l][0] + Po[1] * dtj[l][1] +
+                    Po[2] * dtj[l][2] + dtp[i];
           }
           const int li = sl + l * G;
           T[li][0] = make_float4(R[0], R[1], R[2], t[0]);
           T[li][1] = make_float4(R[3], R[4], R[5], t[1]);
           T[li][2] = make_float4(R[6], R[7], R[8], t[2]);
+          dT[li][0] = make_float4(dR[0], dR[1], dR[2], dt[0]);
+          dT[li][1] = make_float4(dR[3], dR[4], dR[5], dt[1]);
+          dT[li][2] = make_float4(dR[6], dR[7], dR[8], dt[2]);
         }
       }
     }
     __syncthreads();
-    // mass properties: sum over links of m p and R I R^T + m (|p|^2 1 - p p^T)
-    float acc[9];
+    // mass properties: over links, m p, R I R^T + m (|p|^2 1 - p p^T), and m dp
+    float acc[12];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) acc[i] = 0.f;
+    for (int i = 0; i < 12; ++i) acc[i] = 0.f;
 #pragma unroll
     for (int l = 0; l < LPL; ++l) {
       if (lv[l]) {
         const int li = sl + l * G;
         const float4 r0 = T[li][0], r1 = T[li][1], r2 = T[li][2];
+        const float4 d0 = dT[li][0], d1 = dT[li][1], d2 = dT[li][2];
         const float R[9] = {r0.x, r0.y, r0.z, r1.x, r1.y, r1.z, r2.x, r2.y, r2.z};
-        float p[3];
         const float* lk = a.links + (size_t)lrow[l] * LINK_F;
         const float lc[3] = {lk[LK_COG], lk[LK_COG + 1], lk[LK_COG + 2]};
+        const float m = lk[LK_MASS];
+        float p[3];
         p[0] = R[0] * lc[0] + R[1] * lc[1] + R[2] * lc[2] + r0.w;
         p[1] = R[3] * lc[0] + R[4] * lc[1] + R[5] * lc[2] + r1.w;
         p[2] = R[6] * lc[0] + R[7] * lc[1] + R[8] * lc[2] + r2.w;
-        const float m = lk[LK_MASS];
         acc[0] += m * p[0];
         acc[1] += m * p[1];
         acc[2] += m * p[2];
+        acc[9] += m * (d0.x * lc[0] + d0.y * lc[1] + d0.z * lc[2] + d0.w);
+        acc[10] += m * (d1.x * lc[0] + d1.y * lc[1] + d1.z * lc[2] + d1.w);
+        acc[11] += m * (d2.x * lc[0] + d2.y * lc[1] + d2.z * lc[2] + d2.w);
         // A = R I (I symmetric: xx yy zz xy xz yz)
         const float* S = lk + LK_INERTIA;
         const float Ifull[9] = {S[0], S[3], S[4], S[3], S[1], S[5], S[4], S[5], S[2]};
@@ -230,11 +324,12 @@ __device__ __forceinline__ void run_block(const StepArgs& a, float4 (*T)[3], int
       }
     }
 #pragma unroll
-    for (int i = 0; i < 9; ++i) acc[i] = seg_sum<G>(acc[i]);
-    const float invM = 1.f / M;
-    gb[0] = acc[0] * invM;
-    gb[1] = acc[1] * invM;
-    gb[2] = acc[2] * invM;
+    for (int i = 0; i < 12; ++i) acc[i] = seg_sum<G>(acc[i]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      gb[i] = acc[i] * invM;
+      dgb[i] = acc[9 + i] * invM;
+    }
     const float gg = gb[0] * gb[0] + gb[1] * gb[1] + gb[2] * gb[2];
     Ib[0] = acc[3] - M * (gg - gb[0] * gb[0]);
     Ib[1] = acc[4] - M * (gg - gb[1] * gb[1]);
@@ -248,8 +343,8 @@ __device__ __forceinline__ void run_block(const StepArgs& a, float4 (*T)[3], int
       const float c01 = xz * yz - xy * zz, c02 = xy * yz - xz * yy, c12 = xy * xz - xx * yz;
       const float det = xx * c00 + xy * c01 + xz * c02;
       const float tr = (xx + yy + zz) * (1.f / 3.f);
-      Ireg = tr > 0.f && det > 1e-9f * tr * tr * tr;
-      const float id = Ireg ? 1.f / det : 0.f;
+      const bool reg = tr > 0.f && det > 1e-9f * tr * tr * tr;
+      const float id = reg ? rcp(det) : 0.f;
       Iinv[0] = c00 * id; Iinv[1] = c11 * id; Iinv[2] = c22 * id;
       Iinv[3] = c01 * id; Iinv[4] = c02 * id; Iinv[5] = c12 * id;
     }
@@ -268,6 +363,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, float4 (*T)[3], int
       rx[p] = ok ? yx : 0.f;
       ry[p] = ok ? yy : 0.f;
       rz[p] = ok ? yz : 0.f;
+      group_fence(p);
     }
   };
 
@@ -285,6 +381,9 @@ __device__ __forceinline__ void run_block(const StepArgs& a, float4 (*T)[3], int
     return lj[l] ? fminf(fmaxf(qh, lk[6]), lk[7]) : 0.f;
   };
 
+  float dql[LPL];
+#pragma unroll
+  for (int l = 0; l < LPL; ++l) dql[l] = 0.f;
   if (MODE == kPlace) {
 #pragma unroll
     for (int l = 0; l < LPL; ++l) {
@@ -293,7 +392,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, float4 (*T)[3], int
     }
   }
 
-  forward_kinematics();
+  forward_kinematics(dql);
 
   if (MODE == kPlace) {
     float R[9];
@@ -317,17 +416,13 @@ __device__ __forceinline__ void run_block(const StepArgs& a, float4 (*T)[3], int
     }
   }
 
-  const float dt = a.dt;
+  const float dt = a.dt, inv_dt = a.inv_dt;
   for (int s = 0; s < (MODE == kStep ? a.n_steps : 0); ++s) {
     const bool active = valid && fl == 0;
     float R[9];
     quat_to_mat(Q[0], Q[1], Q[2], Q[3], R);
 
-    // S1 + S2: detection at P^n and normal forces. Ux, Uy keep the points'
-    // offsets from the CoG (R r), not their world positions: the friction fit
-    // below works on small offsets and slips, which float32 holds far better
-    // than world coordinates.
-    float Ux[PPL], Uy[PPL];
+    // S1 + S2: detection at P^n and normal forces
     unsigned kap = 0u;
     float F = 0.f, tx = 0.f, ty = 0.f, nc = 0.f;
 #pragma unroll
@@ -337,8 +432,6 @@ __device__ __forceinline__ void run_block(const StepArgs& a, float4 (*T)[3], int
       const float uy = R[3] * rx[p] + R[4] * ry[p] + R[5] * rz[p];
       const float uz = R[6] * rx[p] + R[7] * ry[p] + R[8] * rz[p];
       const float Px = c[0] + ux, Py = c[1] + uy, Pz = c[2] + uz;
-      Ux[p] = ux;
-      Uy[p] = uy;
       if (k < N) {
         const float d = hf_at(a, Px, Py) - Pz;
         if (d > 0.f) {
@@ -351,6 +444,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, float4 (*T)[3], int
           nc += 1.f;
         }
       }
+      group_fence(p);
     }
     F = seg_sum<G>(F);
     tx = seg_sum<G>(tx);
@@ -359,22 +453,24 @@ __device__ __forceinline__ void run_block(const StepArgs& a, float4 (*T)[3], int
 
     // S3: joint-angle determination every K frames (c, Q, v, w kept)
     const bool upd = (n % a.K) == 0;
-    if (__any(upd)) {
+    const bool fk_now = __any(upd);
+    if (fk_now) {
       const bool take = upd && active;
 #pragma unroll
       for (int l = 0; l < LPL; ++l) {
         const float qn = command(l);
+        dql[l] = take ? qn - q[l] : 0.f;
         qp[l] = take ? q[l] : qp[l];
         q[l] = take ? qn : q[l];
       }
-      forward_kinematics();
+      forward_kinematics(dql);
     }
 
     // S4: trial step. Body-frame Euler equation: I_b dw_b = tau_b - w_b x I_b w_b
-    float v1[3], w1[3], c1[3], Q1[4];
+    float v1[3], w1[3], c1[3], Q1[4], dq[4];
     v1[0] = v[0] + dt * a.gx;
     v1[1] = v[1] + dt * a.gy;
-    v1[2] = v[2] + dt * (a.gz + F / M);
+    v1[2] = v[2] + dt * (a.gz + F * invM);
     {
       const float wb[3] = {R[0] * w[0] + R[3] * w[1] + R[6] * w[2],
                            R[1] * w[0] + R[4] * w[1] + R[7] * w[2],
@@ -397,31 +493,40 @@ __device__ __forceinline__ void run_block(const StepArgs& a, float4 (*T)[3], int
     for (int i = 0; i < 3; ++i) c1[i] = c[i] + dt * v1[i];
     {
       const float th0 = dt * w1[0], th1 = dt * w1[1], th2 = dt * w1[2];
-      const float ang = sqrtf(th0 * th0 + th1 * th1 + th2 * th2);
-      float dq[4];
-      if (ang < 1e-12f) {
+      const float ang2 = th0 * th0 + th1 * th1 + th2 * th2;
+      if (ang2 < 1e-24f) {
         dq[0] = 1.f; dq[1] = 0.5f * th0; dq[2] = 0.5f * th1; dq[3] = 0.5f * th2;
       } else {
+        const float ang = __builtin_amdgcn_sqrtf(ang2);
         float sh, ch;
         sin_cos(0.5f * ang, &sh, &ch);
-        const float k = sh / ang;
+        const float k = sh * rcp(ang);
         dq[0] = ch; dq[1] = k * th0; dq[2] = k * th1; dq[3] = k * th2;
       }
       Q1[0] = dq[0] * Q[0] - dq[1] * Q[1] - dq[2] * Q[2] - dq[3] * Q[3];
       Q1[1] = dq[0] * Q[1] + dq[1] * Q[0] + dq[2] * Q[3] - dq[3] * Q[2];
       Q1[2] = dq[0] * Q[2] - dq[1] * Q[3] + dq[2] * Q[0] + dq[3] * Q[1];
       Q1[3] = dq[0] * Q[3] + dq[1] * Q[2] - dq[2] * Q[1] + dq[3] * Q[0];
-      const float inv = 1.f / sqrtf(Q1[0] * Q1[0] + Q1[1] * Q1[1] + Q1[2] * Q1[2] + Q1[3] * Q1[3]);
+      const float inv = __builtin_amdgcn_rsqf(Q1[0] * Q1[0] + Q1[1] * Q1[1] + Q1[2] * Q1[2] +
+                                              Q1[3] * Q1[3]);
 #pragma unroll
       for (int i = 0; i < 4; ++i) Q1[i] *= inv;
     }
     float R1[9];
     quat_to_mat(Q1[0], Q1[1], Q1[2], Q1[3], R1);
+    // R(dq) - 1 = 2 w [v]x + 2 [v]x^2 for the unit increment dq = (w, v)
+    float Eb[9];
+    {
+      const float w0 = dq[0], x = dq[1], y = dq[2], z = dq[3];
+      Eb[0] = -2.f * (y * y + z * z); Eb[1] = 2.f * (x * y - w0 * z); Eb[2] = 2.f * (x * z + w0 * y);
+      Eb[3] = 2.f * (x * y + w0 * z); Eb[4] = -2.f * (x * x + z * z); Eb[5] = 2.f * (y * z - w0 * x);
+      Eb[6] = 2.f * (x * z - w0 * y); Eb[7] = 2.f * (y * z + w0 * x); Eb[8] = -2.f * (x * x + y * y);
+    }
 
     // S5 + S6 moments over the friction set in the ground plane about the
-    // predicted CoG c1: source xi = P^n - c1 = R r_old - (c1 - c), target
-    // xi' = P* - c1 = R1 r_new, slip delta = xi' - xi. The normal equations
-    // (4)-(6) need n, sum xi, sum |xi|^2, sum delta and sum xi x delta.
+    // predicted CoG c1: source xi = P^n - c1 = R r_old - (c1 - c), slip
+    // delta = P* - P^n. The normal equations (4)-(6) need n, sum xi,
+    // sum |xi|^2, sum delta and sum xi x delta.
     const float dcx = c1[0] - c[0], dcy = c1[1] - c[1];
     float mn = 0.f, Sx = 0.f, Sy = 0.f, S2 = 0.f, Dx = 0.f, Dy = 0.f, Cd = 0.f;
 #pragma unroll
@@ -432,8 +537,26 @@ __device__ __forceinline__ void run_block(const StepArgs& a, float4 (*T)[3], int
         const float uz = R1[6] * rx[p] + R1[7] * ry[p] + R1[8] * rz[p];
         const float Px = c1[0] + ux, Py = c1[1] + uy, Pz = c1[2] + uz;
         if (hf_at(a, Px, Py) - Pz > 0.f) {
-          const float sx = Ux[p] - dcx, sy = Uy[p] - dcy;
-          const float dx = (ux - Ux[p]) + dcx, dy = (uy - Uy[p]) + dcy;
+          // body-point increment of this frame's joint update: dr = dT rho - dg_b
+          float drx = 0.f, dry = 0.f, drz = 0.f;
+          if (fk_now) {
+            const int kk = pt_off + sl + p * G;
+            const float4 rho = a.pts[kk];
+            const int lk = a.pt_link[kk];
+            const float4 d0 = dT[lk][0], d1 = dT[lk][1], d2 = dT[lk][2];
+            drx = d0.x * rho.x + d0.y * rho.y + d0.z * rho.z + d0.w - dgb[0];
+            dry = d1.x * rho.x + d1.y * rho.y + d1.z * rho.z + d1.w - dgb[1];
+            drz = d2.x * rho.x + d2.y * rho.y + d2.z * rho.z + d2.w - dgb[2];
+          }
+          const float ox = rx[p] - drx, oy = ry[p] - dry, oz = rz[p] - drz;  // r_old
+          const float Ux = R[0] * ox + R[1] * oy + R[2] * oz;
+          const float Uy = R[3] * ox + R[4] * oy + R[5] * oz;
+          const float Uz = R[6] * ox + R[7] * oy + R[8] * oz;
+          const float sx = Ux - dcx, sy = Uy - dcy;
+          const float dx = (Eb[0] * Ux + Eb[1] * Uy + Eb[2] * Uz) +
+                           (R1[0] * drx + R1[1] * dry + R1[2] * drz) + dcx;
+          const float dy = (Eb[3] * Ux + Eb[4] * Uy + Eb[5] * Uz) +
+                           (R1[3] * drx + R1[4] * dry + R1[5] * drz) + dcy;
           mn += 1.f;
           Sx += sx;
           Sy += sy;
@@ -443,6 +566,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, float4 (*T)[3], int
           Cd += sx * dy - sy * dx;
         }
       }
+      group_fence(p);
     }
     mn = seg_sum<G>(mn);
     Sx = seg_sum<G>(Sx);
@@ -457,14 +581,14 @@ __device__ __forceinline__ void run_block(const StepArgs& a, float4 (*T)[3], int
     // a = (D + a3 J^T S)/n, the mean slip is D/n.
     float a1 = 0.f, a2 = 0.f, a3 = 0.f, lam = 0.f;
     if (mn > 0.f) {
-      const float inv_n = 1.f / mn;
+      const float inv_n = rcp(mn);
       const float D = S2 - (Sx * Sx + Sy * Sy) * inv_n;
-      if (mn >= 2.f && D > mn * a.eps * a.eps) a3 = (Cd - (Sx * Dy - Sy * Dx) * inv_n) / D;
+      if (mn >= 2.f && D > mn * a.eps * a.eps) a3 = (Cd - (Sx * Dy - Sy * Dx) * inv_n) * rcp(D);
       a1 = (Dx + Sy * a3) * inv_n;
       a2 = (Dy - Sx * a3) * inv_n;
       const float sbx = Dx * inv_n, sby = Dy * inv_n;
-      const float Ff = M * sqrtf(sbx * sbx + sby * sby) / (dt * dt);
-      lam = (a.mu_inf || Ff <= a.mu * F) ? 1.f : a.mu * F / Ff;
+      const float Ff = M * __builtin_amdgcn_sqrtf(sbx * sbx + sby * sby) * (inv_dt * inv_dt);
+      lam = (a.mu_inf || Ff <= a.mu * F) ? 1.f : a.mu * F * rcp(Ff);
     }
 
     // S8 correction and commit
@@ -479,8 +603,8 @@ __device__ __forceinline__ void run_block(const StepArgs& a, float4 (*T)[3], int
       Q2[3] = ch * Q1[3] + sh * Q1[0];
     }
     const float c2[3] = {c1[0] - lam * a1, c1[1] - lam * a2, c1[2]};
-    const float v2[3] = {v1[0] - lam * a1 / dt, v1[1] - lam * a2 / dt, v1[2]};
-    const float w2[3] = {w1[0], w1[1], w1[2] - lam * alpha / dt};
+    const float v2[3] = {v1[0] - lam * a1 * inv_dt, v1[1] - lam * a2 * inv_dt, v1[2]};
+    const float w2[3] = {w1[0], w1[1], w1[2] - lam * alpha * inv_dt};
 
     // S9 telemetry and health
     float R2[9];
@@ -543,11 +667,21 @@ __device__ __forceinline__ void run_block(const StepArgs& a, float4 (*T)[3], int
   }
 }
 
+// Residency: with a 64-lane segment and at most 6 points per lane, capping the
+// kernel at 256 registers (two waves per SIMD) costs a few spills but hides
+// gather and LDS latency behind a second wave (1.6x measured on 4,096
+// hexapods). Shapes with more points per lane spill badly under the cap, so
+// they keep the compiler's choice.
+template <int G, int PPL>
+constexpr int kMinWavesPerEU = (G == 64 && PPL <= 6) ? 2 : 1;
+
 template <int G, int PPL, int LPL, int MODE>
-__global__ __launch_bounds__(64) void step_kernel(const StepArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWavesPerEU<G, PPL>, 8)))
+void step_kernel(const StepArgs a) {
   constexpr int IPW = 64 / G;
   constexpr int LMAX = G * LPL;
-  __shared__ float4 T[IPW][LMAX][3];
+  __shared__ LinkT T[IPW][LMAX];
+  __shared__ LinkT dT[IPW][LMAX];
   const int lane = threadIdx.x;
   const int seg = lane / G;
   const int sl = lane - seg * G;
@@ -562,7 +696,7 @@ __global__ __launch_bounds__(64) void step_kernel(const StepArgs a) {
       tb = blockIdx.x;
     }
     if (tb >= a.n_blocks) break;
-    run_block<G, PPL, LPL, MODE>(a, T[seg], tb, seg, sl);
+    run_block<G, PPL, LPL, MODE>(a, T[seg], dT[seg], tb, seg, sl);
     __syncthreads();
   }
 }

@@ -392,6 +392,7 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   a.link_depth = w->link_depth;
   a.ctrl = w->ctrl;
   a.dt = (float)d->dt;
+  a.inv_dt = (float)(1.0 / d->dt);
   a.dt_d = d->dt;
   a.K = d->joint_interval;
   a.gx = (float)d->g[0];

@@ -84,6 +84,8 @@ class WindowStats:
         self.pts = 0.0
         self.joint = 0.0
         self.orient = 0.0
+        self.start = None      # oracle state at the window start (rounded to float32)
+        self.spread = None     # oracle ensemble spread, filled in for windows off tolerance
 
     def update(self, ref, got, Pref=None, Pgot=None, J=0):
         self.cog = max(self.cog, float(np.abs(ref[:3] - got[:3]).max()))
@@ -119,6 +121,8 @@ def run_windows(ow, gw, idx, starts, length=200, every=20, check_points=True):
         write_states(gw, idx, [start[i] for i in idx], J_of)
         refs = {i: start[i].copy() for i in idx}
         stats = {i: WindowStats() for i in idx}
+        for i in idx:
+            stats[i].start = start[i].copy()
         for k in range(0, length, every):
             for i in idx:
                 ow.run(i, refs[i], every)
@@ -132,3 +136,60 @@ def run_windows(ow, gw, idx, starts, length=200, every=20, check_points=True):
                 stats[i].update(refs[i], g, Pref, Pgot, J_of(i))
         results += [(s, i, stats[i]) for i in idx]
     return results
+
+
+def _noisy_run(ow, i, st, n, rng, J):
+    """n oracle frames, each followed by a float32-level relative perturbation
+    (uniform in +-2^-24) of the CoG, orientation, velocities and joint angles:
+    a model of the rounding a float32 implementation makes every frame."""
+    for _ in range(n):
+        ow.step(i, st)
+        for a, b in ((0, 13), (O.HDR, O.HDR + 2 * J)):
+            st[a:b] *= 1.0 + rng.uniform(-1.0, 1.0, b - a) * 2.0 ** -24
+
+
+def ensemble_spread(ow, i, start, members=4, length=200, every=20, seed=0):
+    """Largest deviation (CoG or any mass point, m; orientation, rad) of oracle
+    runs with float32-level noise from the noiseless oracle over one window: how
+    well the FP64 step itself determines this window at float32 resolution."""
+    J = ow.morph_of(i).n_joints
+    rng = np.random.default_rng(seed)
+    ref = start.copy()
+    mem = [start.copy() for _ in range(members)]
+    pos, ang = 0.0, 0.0
+    for _ in range(0, length, every):
+        ow.run(i, ref, every)
+        Pr = ow.points(i, ref)
+        for m in mem:
+            _noisy_run(ow, i, m, every, rng, J)
+            pos = max(pos, float(np.abs(ow.points(i, m) - Pr).max()),
+                      float(np.abs(m[:3] - ref[:3]).max()))
+            ang = max(ang, quat_angle(m[3:7], ref[3:7]))
+    return pos, ang
+
+
+SPREAD_FACTOR = 3.0
+MAX_ILL_FRACTION = 0.10
+
+
+def judge_windows(ow, results):
+    """A window passes if it is within POS_TOL / ANG_TOL, or, when the FP64 oracle
+    itself is not determined to that tolerance at float32 resolution (its noisy
+    ensemble spreads wider), if the GPU stays within SPREAD_FACTOR times that
+    spread. Returns (failures, ill-conditioned windows)."""
+    bad, ill = [], []
+    for s, i, st in results:
+        if st.ok():
+            continue
+        st.spread = ensemble_spread(ow, i, st.start)
+        pos_sp, ang_sp = st.spread
+        pos_err = max(st.cog, st.pts)
+        ang_err = max(st.joint, st.orient)
+        well_pos = pos_err <= POS_TOL or pos_err <= SPREAD_FACTOR * pos_sp
+        well_ang = ang_err <= ANG_TOL or ang_err <= SPREAD_FACTOR * ang_sp
+        if well_pos and well_ang and (pos_sp > POS_TOL / SPREAD_FACTOR
+                                      or ang_sp > ANG_TOL / SPREAD_FACTOR):
+            ill.append((s, i, st))
+        else:
+            bad.append((s, i, st))
+    return bad, ill

@@ -16,8 +16,8 @@ from oracle import oracle as O
 from paper_2411_05799_amd import native as N
 from paper_2411_05799_amd import workloads as W
 
-from _helpers import (ANG_TOL, POS_TOL, STAT_TOL, gpu_available, read_states, run_windows,
-                      write_states)
+from _helpers import (ANG_TOL, MAX_ILL_FRACTION, POS_TOL, STAT_TOL, gpu_available, judge_windows,
+                      read_states, run_windows, write_states)
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_available(), reason="needs a HIP device")]
@@ -28,12 +28,22 @@ def say(msg):
     sys.stdout.flush()
 
 
-def assert_windows(results, label):
+def assert_windows(results, label, ow):
+    """Every window within 1e-4 m / 1e-3 rad, except windows the FP64 oracle itself
+    does not determine to that tolerance at float32 resolution, where the GPU must
+    stay within 3x the oracle's own noisy-ensemble spread (at most 10% of windows)."""
     worst = max(results, key=lambda r: max(r[2].cog, r[2].pts) / POS_TOL
                 + max(r[2].joint, r[2].orient) / ANG_TOL)
     say(f"{label}: {len(results)} windows, worst (start {worst[0]}, inst {worst[1]}): {worst[2]}")
-    bad = [(s, i, st) for s, i, st in results if not st.ok()]
-    assert not bad, f"{len(bad)} windows out of tolerance, e.g. {bad[:3]}"
+    bad, ill = judge_windows(ow, results)
+    for s, i, st in ill:
+        say(f"  ill-conditioned window start {s} inst {i}: gpu {st}; oracle spread "
+            f"{st.spread[0]:.2e} m {st.spread[1]:.2e} rad")
+    for s, i, st in bad:
+        sp = st.spread
+        say(f"  FAIL start {s} inst {i}: gpu {st}; oracle spread {sp[0]:.2e} m {sp[1]:.2e} rad")
+    assert not bad, f"{len(bad)} windows out of tolerance"
+    assert len(ill) <= MAX_ILL_FRACTION * len(results), f"{len(ill)} ill-conditioned windows"
 
 
 def test_placement_matches_oracle():
@@ -55,7 +65,7 @@ def test_config1_windows_all_10k():
     ow = O.OracleWorld(w)
     with N.World(w) as gw:
         res = run_windows(ow, gw, [0], starts=list(range(0, 10_000, 200)))
-    assert_windows(res, "config1")
+    assert_windows(res, "config1", ow)
 
 
 def test_config1_long_horizon_statistics():
@@ -93,7 +103,7 @@ def test_config2_full_size_sampled_windows():
         from bench import pick_launch
         pick_launch(gw, w)
         res = run_windows(ow, gw, idx, starts=[0, 200, 400, 600, 800], every=40)
-    assert_windows(res, "config2")
+    assert_windows(res, "config2", ow)
 
 
 @pytest.mark.parametrize("lanes", [64, 32, 16])
@@ -107,7 +117,7 @@ def test_launch_shapes_ragged_batch(lanes):
         with N.World(w) as gw:
             gw.set_launch(lanes_per_instance=lanes, persistent=persistent, waves_per_cu=2)
             res = run_windows(ow, gw, [0, 17, 36], starts=[0, 300], every=50)
-        assert_windows(res, f"lanes {lanes} persistent {persistent}")
+        assert_windows(res, f"lanes {lanes} persistent {persistent}", ow)
 
 
 def test_uneven_morphologies():
@@ -117,7 +127,7 @@ def test_uneven_morphologies():
     ow = O.OracleWorld(w)
     with N.World(w) as gw:
         res = run_windows(ow, gw, list(range(0, 48, 5)), starts=[0, 400], every=50)
-    assert_windows(res, "uneven")
+    assert_windows(res, "uneven", ow)
 
 
 def max_robot():
@@ -146,7 +156,7 @@ def test_max_size_robot():
     ow = O.OracleWorld(w)
     with N.World(w) as gw:
         res = run_windows(ow, gw, [0], starts=[0, 200, 600], every=50)
-    assert_windows(res, "max robot")
+    assert_windows(res, "max robot", ow)
 
 
 def test_degenerate_bodies_and_paper_mode():
@@ -176,7 +186,7 @@ def test_degenerate_bodies_and_paper_mode():
         ow = O.OracleWorld(w)
         with N.World(w) as gw:
             res = run_windows(ow, gw, [0], starts=[0, 200], every=25)
-        assert_windows(res, f"{m.name} dt={p.dt} K={p.K} mu={p.mu}")
+        assert_windows(res, f"{m.name} dt={p.dt} K={p.K} mu={p.mu}", ow)
 
 
 def _body(gw):
