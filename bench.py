@@ -27,7 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK = 157.3e12   # MI355X published FP32 vector FLOP/s
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.txt")
+COPY_BYTES = 1 << 30   # plain device copy used to calibrate the HBM byte counters
 KERNEL_SRC = os.path.join(ROOT, "paper_2411_05799_amd", "csrc", "step_kernel.hip")
 
 
@@ -42,18 +43,31 @@ def pick_launch(gw, w, steps=50, stream=None):
     return rec
 
 
-def measured_traffic(chunk, n_inst):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel source and the same launch size; else None."""
+def measured_traffic(chunk, n_inst, lanes):
+    """HBM bytes per launch from the committed rocprofv3 counter summary (lines
+    "key: value"), if it was taken on the current kernel source at the same
+    launch size and shape; else None."""
     try:
         with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
+            t = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
+        t = {k.strip(): v.strip() for k, v in t.items()}
+        if (t.get("kernel_sha") != kernel_hash() or int(t.get("chunk_steps", -1)) != chunk
+                or int(t.get("instances", -1)) != n_inst or int(t.get("lanes", -1)) != lanes):
+            return None
+        return float(t["bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
         return None
-    if t.get("kernel_sha") != kernel_hash() or t.get("chunk_steps") != chunk \
-            or t.get("instances") != n_inst:
-        return None
-    return t.get("bytes_per_launch")
+
+
+def copy_calibration():
+    """One plain device-to-device copy of COPY_BYTES, for scaling FETCH_SIZE and
+    WRITE_SIZE: run under rocprofv3 --pmc, the copy's counters must read COPY_BYTES."""
+    import torch
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES}), flush=True)
 
 
 def cpu_baseline(w, n_inst, frames, threads):
@@ -84,7 +98,12 @@ def main():
     ap.add_argument("--lanes", type=int, default=0,
                     help="lanes per robot (16/32/64); 0 = let the autotuner choose")
     ap.add_argument("--persistent", type=int, default=0)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run the plain copy used to calibrate HBM byte counters")
     args = ap.parse_args()
+    if args.copy_calib:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the instances "
               "of a batch are independent, so a multi-GPU run would shard them with no "
@@ -136,7 +155,7 @@ def main():
     full = [ms for k, ms in enumerate(launch_ms) if (k + 1) * chunk <= args.steps]
     avg_ms = float(np.mean(full)) if full else float(np.mean(launch_ms))
     achieved = flops_frame * chunk / (avg_ms * 1e-3)
-    traffic = measured_traffic(chunk, I)
+    traffic = measured_traffic(chunk, I, launch["lanes_per_instance"])
 
     out = {
         "metric": "instance-steps/s",
