@@ -70,6 +70,57 @@ typedef struct {
 } npx_morph_tables;
 
 /* ---------------------------------------------------------------------- */
+/* Construction API of the paper (Sec. IV, appendix) -> morphology tables  */
+/* ---------------------------------------------------------------------- */
+/* Host only; nothing touches a device. Body-creating calls return the new
+ * body id (>= 0) or a negative npx_status; npx_morph_last_error() explains a
+ * failure. Bodies are made of mass points with the body's mass spread evenly
+ * (Sec. III-A); each has a reference point (point: its position; box, sphere:
+ * centre; cylinder: axis midpoint; ray: start) and an orientation. The morph
+ * object owns everything it returns; npx_morph_get_tables views stay valid until
+ * npx_morph_free. Calls that change a finalised morph return NPX_ESTATE. */
+typedef struct npx_morph npx_morph;
+npx_status npx_morph_new(npx_morph** out);
+void npx_morph_free(npx_morph* m); /* NULL-safe */
+const char* npx_morph_last_error(void);
+/* simplifyMode (Sec. IV-C): for cylinders and spheres created afterwards,
+ * 0 none, 1 the 8 corners of their bounding box, 2 two points, >= 3 one point. */
+npx_status npx_simplify_mode(npx_morph* m, int mode);
+int npx_create_point(npx_morph* m, double x, double y, double z, double mass);
+/* 8 corner points; w along x, h along z, d along y, centre (x, y, z). */
+int npx_create_box(npx_morph* m, double w, double h, double d, double x, double y, double z,
+                   double mass);
+/* ring_pts points on each end cap ring of radius rr (mode 0). */
+int npx_create_cylinder(npx_morph* m, double x1, double y1, double z1, double x2, double y2,
+                        double z2, double rr, double mass, int ring_pts);
+/* the 12 vertices of a regular icosahedron of radius rr (mode 0). */
+int npx_create_sphere(npx_morph* m, double x, double y, double z, double rr, double mass);
+/* no mass points; never collides. */
+int npx_create_ray(npx_morph* m, double x1, double y1, double z1, double x2, double y2, double z2);
+/* connectBodies: glue two bodies into one rigid link. */
+npx_status npx_connect_bodies(npx_morph* m, int id1, int id2);
+/* createJoint: hinge; anchor and axis in body 1's frame; body 1's link is the
+ * parent, body 2's the child. Returns the joint id. */
+int npx_create_joint(npx_morph* m, int id1, int id2, double anX, double anY, double anZ,
+                     double aX, double aY, double aZ);
+/* range of motion of a joint (default unlimited). */
+npx_status npx_set_joint_limits(npx_morph* m, int joint, double lo, double hi);
+/* moveBody: put the body's reference point at (tx, ty, tz). */
+npx_status npx_move_body(npx_morph* m, int id, double tx, double ty, double tz);
+/* rotateBody: roll alpha about x, then pitch beta about y, then yaw gamma about
+ * z (fixed construction axes, right-hand rule), about the reference point. */
+npx_status npx_rotate_body(npx_morph* m, int id, double alpha, double beta, double gamma);
+/* getMaxBodyID: the number of body ids handed out. */
+int npx_get_max_body_id(const npx_morph* m);
+/* finalizeConstruction: links = glued groups, root = the link of body 0, links
+ * ordered parents first; fails on a joint inside a link, a link with two
+ * parent joints or a body not reachable from the root. */
+npx_status npx_finalize_construction(npx_morph* m);
+npx_status npx_morph_get_tables(const npx_morph* m, npx_morph_tables* out);
+/* index of a joint id in the tables' joint order (the controller's order). */
+int npx_morph_joint_index(const npx_morph* m, int joint_id);
+
+/* ---------------------------------------------------------------------- */
 /* World: instances, terrain, physical constants                          */
 /* ---------------------------------------------------------------------- */
 typedef struct {

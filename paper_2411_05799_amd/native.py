@@ -82,6 +82,32 @@ def lib():
         L.npx_autotune.argtypes = [vp, C.c_int32, vp, C.POINTER(Launch), C.POINTER(Launch),
                                    C.POINTER(C.c_float), C.c_int32, C.POINTER(C.c_int32)]
         L.npx_flops_per_step.argtypes = [vp, C.c_int64, C.POINTER(C.c_double)]
+        d = C.c_double
+        L.npx_morph_last_error.restype = C.c_char_p
+        L.npx_morph_new.argtypes = [C.POINTER(vp)]
+        L.npx_morph_free.argtypes = [vp]
+        L.npx_morph_free.restype = None
+        L.npx_simplify_mode.argtypes = [vp, C.c_int]
+        L.npx_create_point.argtypes = [vp, d, d, d, d]
+        L.npx_create_box.argtypes = [vp, d, d, d, d, d, d, d]
+        L.npx_create_cylinder.argtypes = [vp, d, d, d, d, d, d, d, d, C.c_int]
+        L.npx_create_sphere.argtypes = [vp, d, d, d, d, d]
+        L.npx_create_ray.argtypes = [vp, d, d, d, d, d, d]
+        L.npx_connect_bodies.argtypes = [vp, C.c_int, C.c_int]
+        L.npx_create_joint.argtypes = [vp, C.c_int, C.c_int, d, d, d, d, d, d]
+        L.npx_set_joint_limits.argtypes = [vp, C.c_int, d, d]
+        L.npx_move_body.argtypes = [vp, C.c_int, d, d, d]
+        L.npx_rotate_body.argtypes = [vp, C.c_int, d, d, d]
+        L.npx_get_max_body_id.argtypes = [vp]
+        L.npx_finalize_construction.argtypes = [vp]
+        L.npx_morph_get_tables.argtypes = [vp, C.POINTER(_MorphTables)]
+        L.npx_morph_joint_index.argtypes = [vp, C.c_int]
+        for name in ("npx_morph_new", "npx_simplify_mode", "npx_create_point", "npx_create_box",
+                     "npx_create_cylinder", "npx_create_sphere", "npx_create_ray",
+                     "npx_connect_bodies", "npx_create_joint", "npx_set_joint_limits",
+                     "npx_move_body", "npx_rotate_body", "npx_get_max_body_id",
+                     "npx_finalize_construction", "npx_morph_get_tables", "npx_morph_joint_index"):
+            getattr(L, name).restype = C.c_int
         for name in ("npx_create_world", "npx_world_dims", "npx_set_controller", "npx_step_n",
                      "npx_read_state", "npx_write_state", "npx_read_points", "npx_get_launch",
                      "npx_set_launch", "npx_autotune", "npx_flops_per_step"):
@@ -275,6 +301,88 @@ class World:
             check(lib().npx_flops_per_step(self.h, int(k), C.byref(d)))
             tot += d.value
         return tot
+
+
+class MorphBuilder:
+    """The paper's construction API (npx_morph_*): bodies of mass points, glued
+    into links, joined by hinges, finalised into morphology tables."""
+
+    def __init__(self):
+        h = C.c_void_p()
+        self._call(lib().npx_morph_new(C.byref(h)))
+        self.h = h
+
+    @staticmethod
+    def _call(rc):
+        if rc < 0:
+            raise NpxError(f"npx error {rc}: {lib().npx_morph_last_error().decode()}")
+        return rc
+
+    def simplify_mode(self, mode):
+        return self._call(lib().npx_simplify_mode(self.h, int(mode)))
+
+    def create_point(self, x, y, z, m):
+        return self._call(lib().npx_create_point(self.h, x, y, z, m))
+
+    def create_box(self, w, h, d, x, y, z, m):
+        return self._call(lib().npx_create_box(self.h, w, h, d, x, y, z, m))
+
+    def create_cylinder(self, x1, y1, z1, x2, y2, z2, rr, m, ring_pts=8):
+        return self._call(lib().npx_create_cylinder(self.h, x1, y1, z1, x2, y2, z2, rr, m,
+                                                    int(ring_pts)))
+
+    def create_sphere(self, x, y, z, rr, m):
+        return self._call(lib().npx_create_sphere(self.h, x, y, z, rr, m))
+
+    def create_ray(self, x1, y1, z1, x2, y2, z2):
+        return self._call(lib().npx_create_ray(self.h, x1, y1, z1, x2, y2, z2))
+
+    def connect_bodies(self, id1, id2):
+        return self._call(lib().npx_connect_bodies(self.h, int(id1), int(id2)))
+
+    def create_joint(self, id1, id2, anchor, axis):
+        return self._call(lib().npx_create_joint(self.h, int(id1), int(id2), *map(float, anchor),
+                                                 *map(float, axis)))
+
+    def set_joint_limits(self, joint, lo, hi):
+        return self._call(lib().npx_set_joint_limits(self.h, int(joint), lo, hi))
+
+    def move_body(self, id_, tx, ty, tz):
+        return self._call(lib().npx_move_body(self.h, int(id_), tx, ty, tz))
+
+    def rotate_body(self, id_, alpha, beta, gamma):
+        return self._call(lib().npx_rotate_body(self.h, int(id_), alpha, beta, gamma))
+
+    def get_max_body_id(self):
+        return self._call(lib().npx_get_max_body_id(self.h))
+
+    def finalize_construction(self):
+        return self._call(lib().npx_finalize_construction(self.h))
+
+    def joint_index(self, joint_id):
+        return self._call(lib().npx_morph_joint_index(self.h, int(joint_id)))
+
+    def tables(self, name="built"):
+        """The finalised robot as a workloads.Morph (copies of the tables)."""
+        t = _MorphTables()
+        self._call(lib().npx_morph_get_tables(self.h, C.byref(t)))
+        n, l = t.n_points, t.n_links
+        pts = np.ctypeslib.as_array(t.points, shape=(n * 4,)).reshape(n, 4).copy()
+        return W.Morph(points=pts, pt_link=np.ctypeslib.as_array(t.pt_link, shape=(n,)).copy(),
+                       parent=np.ctypeslib.as_array(t.parent, shape=(l,)).copy(),
+                       joint=np.ctypeslib.as_array(t.joint, shape=(l * 8,)).reshape(l, 8).copy(),
+                       name=name)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().npx_morph_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _stream_handle(stream):

@@ -324,3 +324,32 @@ def test_torch_stream_and_device_buffers():
         gw.step_n(10, stream=s)
         q = gw.read_state(N.F_JOINT)
         assert np.abs(q).max() == 0.0   # zero controller holds the joints at 0
+
+
+def test_robot_built_with_construction_api():
+    """A quadruped made with createBox/createCylinder/createJoint/rotateBody, stepped
+    on the GPU from the tables npx_finalize_construction writes."""
+    say("case: construction-API quadruped")
+    b = N.MorphBuilder()
+    torso = b.create_box(0.3, 0.05, 0.2, 0, 0, 0, 2.0)
+    extra = b.create_sphere(0, 0, 0.04, 0.03, 0.3)
+    b.connect_bodies(torso, extra)
+    for hx in (-0.12, 0.12):
+        for side in (-1, 1):
+            hip = (hx, side * 0.1, 0.0)
+            knee = (hx, side * 0.18, 0.0)
+            upper = b.create_cylinder(*hip, *knee, 0.01, 0.15, ring_pts=8)
+            lower = b.create_cylinder(*knee, hx, side * 0.18, -0.11, 0.01, 0.1, ring_pts=8)
+            b.create_joint(torso, upper, (hx, side * 0.1, 0.0), (0, 0, 1))
+            b.create_joint(upper, lower, (0, 0, 0.0), (1, 0, 0))   # anchor: upper's midpoint
+    b.finalize_construction()
+    m = b.tables("quadruped")
+    rng = np.random.default_rng(4)
+    ctrl = [W.sinusoid_controller(rng, m.n_joints)]
+    w = W.Workload(params=W.Params(), hf=W.octave_terrain(5), morphs=[m],
+                   inst_morph=np.zeros(1, np.int32), ctrl=ctrl,
+                   pose=np.array([[0, 0, 0.16, 1, 0, 0, 0]], np.float32))
+    ow = O.OracleWorld(w)
+    with N.World(w) as gw:
+        res = run_windows(ow, gw, [0], starts=[0, 400], every=40)
+    assert_windows(res, "construction-API quadruped", ow)

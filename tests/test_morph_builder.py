@@ -1,0 +1,147 @@
+"""The paper's construction API (npx_morph_*) on the host: geometry of the
+primitives, move/rotate, simplify modes, the link tree and its errors."""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+from oracle import oracle as O
+from paper_2411_05799_amd import native as N
+
+pytestmark = pytest.mark.skipif(not os.path.exists(N.LIB_PATH), reason="libnpx.so not built")
+
+
+def test_box_corners_and_mass():
+    b = N.MorphBuilder()
+    i = b.create_box(0.2, 0.05, 0.1, 1.0, 2.0, 3.0, 0.8)   # w x, h z, d y
+    assert i == 0 and b.get_max_body_id() == 1
+    b.finalize_construction()
+    t = b.tables()
+    assert t.n_points == 8 and t.n_links == 1
+    np.testing.assert_allclose(np.sort(np.unique(t.points[:, 0])), [0.9, 1.1], atol=1e-6)
+    np.testing.assert_allclose(np.sort(np.unique(t.points[:, 1])), [1.95, 2.05], atol=1e-6)
+    np.testing.assert_allclose(np.sort(np.unique(t.points[:, 2])), [2.975, 3.025], atol=1e-6)
+    np.testing.assert_allclose(t.points[:, 3], 0.1, atol=1e-7)
+
+
+def test_rotate_is_fixed_axis_rpy_about_reference_and_move_places_it():
+    a, be, g = 0.3, -0.7, 1.1
+    b = N.MorphBuilder()
+    i = b.create_box(0.2, 0.05, 0.1, 0.0, 0.0, 0.0, 1.0)
+    b.rotate_body(i, a, be, g)
+    b.move_body(i, 0.5, -0.25, 0.125)
+    b.finalize_construction()
+    got = b.tables().points[:, :3].astype(np.float64)
+    R = Rotation.from_euler("xyz", [a, be, g]).as_matrix()   # extrinsic x, y, z
+    local = np.array([[sx * 0.1, sy * 0.05, sz * 0.025]
+                      for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)])
+    np.testing.assert_allclose(got, local @ R.T + [0.5, -0.25, 0.125], atol=1e-6)
+
+
+def test_cylinder_sphere_ray_and_simplify_modes():
+    counts = {}
+    for mode in (0, 1, 2, 3, 7):
+        b = N.MorphBuilder()
+        b.simplify_mode(mode)
+        c = b.create_cylinder(0, 0, 0, 0.1, 0, 0, 0.01, 0.2, ring_pts=6)
+        s = b.create_sphere(0.3, 0, 0, 0.02, 0.1)
+        r = b.create_ray(0, 0, 0, 0, 0, 1)
+        b.connect_bodies(c, s)
+        b.connect_bodies(c, r)
+        assert b.get_max_body_id() == 3
+        b.finalize_construction()
+        t = b.tables()
+        counts[mode] = t.n_points
+        np.testing.assert_allclose(t.points[:, 3].astype(np.float64).sum(), 0.3, rtol=1e-6)
+        if mode == 0:
+            cyl = t.points[:12, :3].astype(np.float64)
+            # two rings of radius 0.01 about the x axis at x = 0 and x = 0.1
+            np.testing.assert_allclose(np.hypot(cyl[:, 1], cyl[:, 2]), 0.01, atol=1e-7)
+            np.testing.assert_allclose(sorted(set(np.round(cyl[:, 0], 6))), [0.0, 0.1], atol=1e-6)
+            sph = t.points[12:, :3].astype(np.float64) - [0.3, 0, 0]
+            np.testing.assert_allclose(np.linalg.norm(sph, axis=1), 0.02, atol=1e-7)
+    assert counts == {0: 12 + 12, 1: 8 + 8, 2: 2 + 2, 3: 1 + 1, 7: 1 + 1}
+
+
+def two_link(angle_axis=(0, 0, 1)):
+    b = N.MorphBuilder()
+    base = b.create_box(0.2, 0.05, 0.1, 0, 0, 0, 1.0)
+    arm = b.create_cylinder(0.1, 0, 0, 0.3, 0, 0, 0.01, 0.2, ring_pts=4)
+    j = b.create_joint(base, arm, (0.1, 0, 0), angle_axis)
+    return b, j
+
+
+def test_joint_turns_child_about_anchor():
+    """Through the oracle's kinematics: the arm turns about the hinge anchor."""
+    b, j = two_link()
+    b.finalize_construction()
+    t = b.tables()
+    assert list(t.parent) == [-1, 0] and b.joint_index(j) == 0
+    np.testing.assert_allclose(t.joint[1, :6], [0.1, 0, 0, 0, 0, 1], atol=1e-7)
+    om = O.OracleMorph(t)
+    y, _, _, _ = om.fk(np.array([math.pi / 2]))
+    arm = t.pt_link == 1
+    o = t.joint[1, :3].astype(np.float64)          # the float32 anchor both sides read
+    rho = t.points[arm, :3].astype(np.float64) - o
+    rot = rho @ np.array([[0, -1, 0], [1, 0, 0], [0, 0, 1]]).T + o
+    np.testing.assert_allclose(y[arm], rot, atol=1e-12)
+
+
+def test_anchor_and_axis_are_in_body_one_frame():
+    b = N.MorphBuilder()
+    base = b.create_box(0.2, 0.05, 0.1, 0, 0, 0, 1.0)
+    b.rotate_body(base, 0, 0, math.pi / 2)
+    b.move_body(base, 1.0, 0, 0)
+    arm = b.create_point(1.0, 0.3, 0, 0.1)
+    b.create_joint(base, arm, (0.1, 0, 0), (1, 0, 0))
+    b.finalize_construction()
+    np.testing.assert_allclose(b.tables().joint[1, :6], [1.0, 0.1, 0, 0, 1, 0], atol=1e-6)
+
+
+def test_tree_order_and_errors():
+    # links come out parents first whatever the creation order
+    b = N.MorphBuilder()
+    root = b.create_box(0.2, 0.05, 0.1, 0, 0, 0, 1.0)
+    tip = b.create_point(0.5, 0, 0, 0.1)
+    mid = b.create_point(0.3, 0, 0, 0.1)
+    j_tip = b.create_joint(mid, tip, (0, 0, 0), (0, 0, 1))
+    j_mid = b.create_joint(root, mid, (0.1, 0, 0), (0, 0, 1))
+    b.set_joint_limits(j_tip, -0.5, 0.5)
+    b.finalize_construction()
+    t = b.tables()
+    assert list(t.parent) == [-1, 0, 1]
+    assert b.joint_index(j_mid) == 0 and b.joint_index(j_tip) == 1
+    np.testing.assert_allclose(t.joint[2, 6:], [-0.5, 0.5])
+    with pytest.raises(N.NpxError):
+        b.create_point(0, 0, 0, 1.0)          # finalised
+    # a joint between glued bodies
+    b = N.MorphBuilder()
+    p, q = b.create_point(0, 0, 0, 1), b.create_point(1, 0, 0, 1)
+    b.connect_bodies(p, q)
+    b.create_joint(p, q, (0, 0, 0), (0, 0, 1))
+    with pytest.raises(N.NpxError, match="glued"):
+        b.finalize_construction()
+    # a link with two parent joints
+    b = N.MorphBuilder()
+    p, q, r = (b.create_point(x, 0, 0, 1) for x in (0, 1, 2))
+    b.create_joint(p, r, (0, 0, 0), (0, 0, 1))
+    b.create_joint(q, r, (0, 0, 0), (0, 0, 1))
+    with pytest.raises(N.NpxError, match="two parent"):
+        b.finalize_construction()
+    # a body not reachable from the root
+    b = N.MorphBuilder()
+    b.create_point(0, 0, 0, 1)
+    b.create_point(1, 0, 0, 1)
+    with pytest.raises(N.NpxError, match="not connected"):
+        b.finalize_construction()
+    # bad arguments
+    b = N.MorphBuilder()
+    with pytest.raises(N.NpxError):
+        b.create_joint(0, 1, (0, 0, 0), (0, 0, 1))
+    p, q = b.create_point(0, 0, 0, 1), b.create_point(1, 0, 0, 1)
+    with pytest.raises(N.NpxError, match="axis"):
+        b.create_joint(p, q, (0, 0, 0), (0, 0, 0))
+    with pytest.raises(N.NpxError):
+        b.create_cylinder(0, 0, 0, 0, 0, 0, 0.01, 1.0)
