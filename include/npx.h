@@ -230,6 +230,77 @@ npx_status npx_autotune(npx_world* w, int32_t steps, void* hip_stream, npx_launc
  * step's formulas (the roofline numerator). */
 npx_status npx_flops_per_step(const npx_world* w, int64_t i, double* flops);
 
+/* ==== Learned surrogate: the 10-frame state-delta network ====================
+ * The surrogate is a plain multilayer perceptron, n_in -> n_hidden (x
+ * n_hidden_layers, SiLU after each) -> n_out, that predicts the change of an
+ * instance's state over the next 10 frames from features of its current state,
+ * so that controller candidates can be ranked without stepping them; the
+ * stepping path above stays the judge of every candidate it ranks highly.  The
+ * paper has no learned component: this object serves batched controller search
+ * around its simulator.
+ *
+ * Precision: NPX_SUR_BF16 keeps FP32 master weights and runs every product on
+ * BF16 operands with FP32 accumulation; NPX_SUR_FP32 uses FP32 operands
+ * throughout (for checking gradients).  Inputs and targets are standardised
+ * inside, (x - mean) / std per column with the statistics given to
+ * npx_sur_set_norm (identity until then); outputs come back in raw units.
+ *
+ * Parameters, in the flat order every call uses: for each layer in turn its
+ * weights W [out][in] row-major, then its biases b [out].
+ *
+ * Buffers passed to forward/grad/train_step are device pointers: inputs x
+ * [rows][ldx] FP32 (the first n_in columns are read), targets y [rows][ldy]
+ * FP32, an optional row index list rows[batch] (int32, NULL = rows 0..batch-1)
+ * that gathers the batch, outputs [batch][ldy] FP32.  Calls are asynchronous
+ * on `stream` and share the object's work buffers: calls on one object that
+ * overlap in time race.  get/set_params and set_norm synchronise the device. */
+typedef struct npx_sur npx_sur;
+
+enum { NPX_SUR_BF16 = 0, NPX_SUR_FP32 = 1 };
+
+typedef struct {
+  int32_t n_in, n_hidden, n_hidden_layers, n_out;
+  int32_t max_batch;   /* largest batch of any call, <= 2^24 */
+  int32_t precision;   /* NPX_SUR_BF16 or NPX_SUR_FP32 */
+  int32_t training;    /* nonzero: also allocate backward and Adam buffers */
+  uint64_t seed;       /* initial weights and biases ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in)) */
+} npx_sur_desc;
+
+/* NPX_EINVAL for a bad shape (n_hidden_layers 1..7), NPX_ENOMEM when device
+ * memory runs out.  The object owns all its device memory. */
+npx_status npx_sur_create(const npx_sur_desc* d, npx_sur** out);
+void npx_sur_destroy(npx_sur* s);  /* NULL-safe; waits for the device */
+npx_status npx_sur_param_count(const npx_sur* s, int64_t* n);
+/* n must equal the parameter count; setting resets the Adam moments and step. */
+npx_status npx_sur_get_params(npx_sur* s, float* dst, int64_t n, int dst_on_device);
+npx_status npx_sur_set_params(npx_sur* s, const float* src, int64_t n, int src_on_device);
+/* Host arrays: x_mean, x_std [n_in], y_mean, y_std [n_out].  A standard
+ * deviation <= 1e-12 (a constant column) is replaced by 1. */
+npx_status npx_sur_set_norm(npx_sur* s, const float* x_mean, const float* x_std,
+                            const float* y_mean, const float* y_std);
+/* Adam moment decay rates and epsilon (defaults 0.9, 0.999, 1e-8). */
+npx_status npx_sur_set_adam(npx_sur* s, double beta1, double beta2, double eps);
+/* y[b] = network(x[rows[b]]) in raw units, b < batch <= max_batch. */
+npx_status npx_sur_forward(npx_sur* s, const float* x, int64_t ldx, const int32_t* rows,
+                           int64_t batch, float* y, int64_t ldy, void* stream);
+/* Loss = mean over the batch and the n_out columns of the squared error of the
+ * standardised prediction against the standardised target; writes it to
+ * loss[0] (device, may be NULL) and its gradient with respect to the
+ * parameters to grad[param_count] (device, flat order, may be NULL).  Needs
+ * `training`; NPX_ESTATE otherwise. */
+npx_status npx_sur_grad(npx_sur* s, const float* x, int64_t ldx, const float* y, int64_t ldy,
+                        const int32_t* rows, int64_t batch, float* loss, float* grad,
+                        void* stream);
+/* npx_sur_grad, then one Adam step of size lr on the FP32 master weights. */
+npx_status npx_sur_train_step(npx_sur* s, const float* x, int64_t ldx, const float* y,
+                              int64_t ldy, const int32_t* rows, int64_t batch, double lr,
+                              float* loss, void* stream);
+/* Column means and population standard deviations (FP64 accumulation) of a
+ * device matrix x [rows][ldx], first `cols` columns, into device arrays
+ * mean, std [cols].  Synchronises `stream`. */
+npx_status npx_sur_norm_stats(const float* x, int64_t ldx, int64_t rows, int32_t cols,
+                              float* mean, float* std, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

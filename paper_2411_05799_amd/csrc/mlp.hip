@@ -1,0 +1,960 @@
+// The surrogate network of the batched simulator: a plain MLP
+// (n_in -> n_hidden x n_hidden_layers -> n_out, SiLU between layers) trained on
+// transitions the simulator generates, with hand-written matrix-core kernels
+// for gfx950.
+//
+// Every product is one kernel form, C[M x N] = A[M x K] * B[N x K]^T with both
+// operands k-contiguous, so that each lane's MFMA fragment is one 16-byte load:
+//   forward   Z_l  = H_{l-1} * W_l^T          (A = activations, B = W_l)
+//   input     dH   = dZ_l * W_l               (A = dZ_l, B = W_l^T copy)
+//   weights   dW_l = dZ_l^T * H_{l-1}         (A = dZ_l^T, B = H_{l-1}^T), split over K
+// Epilogues therefore also write the transposed copies the next product reads.
+// BF16 operands with FP32 accumulation (v_mfma_f32_16x16x32_bf16) and FP32
+// master weights, or FP32 operands throughout (v_mfma_f32_16x16x4f32) for
+// checking gradients tightly.  Dimensions are padded to multiples of 64 with
+// zeros that stay zero under training (their gradients vanish identically).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "npx.h"
+#include "npx_internal.h"
+
+using npx::fail;
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(NPX_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));            \
+  } while (0)
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int TILE = 64;     // block tile edge (rows and columns)
+constexpr int KSTEP = 32;    // k consumed per MFMA round
+
+// ---- MFMA operand traits --------------------------------------------------
+// A 16x16 output block is accumulated from 16-row slices of A and B: lane l
+// supplies row (l mod 16) and the k-slice 8*(l/16) .. +8 of both operands; the
+// result lands as D[4*(l/16)+e][l mod 16], e = 0..3.
+template <class T>
+struct Mfma;
+
+template <>
+struct Mfma<__bf16> {
+  using frag = bf16x8;
+  static __device__ __forceinline__ frag load(const __bf16* p) {
+    return *reinterpret_cast<const bf16x8*>(p);
+  }
+  static __device__ __forceinline__ void mma(const frag& a, const frag& b, f32x4& c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Mfma<float> {
+  struct frag {
+    float4 lo, hi;
+  };
+  static __device__ __forceinline__ frag load(const float* p) {
+    frag f;
+    f.lo = *reinterpret_cast<const float4*>(p);
+    f.hi = *reinterpret_cast<const float4*>(p + 4);
+    return f;
+  }
+  // Eight k=4 products; in product j lane group g supplies k = 8g + j, so the
+  // eight together cover the same 32 k values as one BF16 product.
+  static __device__ __forceinline__ void mma(const frag& a, const frag& b, f32x4& c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.lo.x, b.lo.x, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.lo.y, b.lo.y, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.lo.z, b.lo.z, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.lo.w, b.lo.w, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.hi.x, b.hi.x, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.hi.y, b.hi.y, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.hi.z, b.hi.z, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.hi.w, b.hi.w, c, 0, 0, 0);
+  }
+};
+
+template <class T>
+__device__ __forceinline__ T to_t(float x) {
+  return static_cast<T>(x);
+}
+
+__device__ __forceinline__ float sigmoid(float z) { return 1.0f / (1.0f + __expf(-z)); }
+
+enum Epi { EPI_HID = 0, EPI_OUT = 1, EPI_DX = 2, EPI_DW = 3 };
+
+template <class T>
+struct GemmArgs {
+  const T* A;
+  const T* B;
+  int64_t lda, ldb;
+  int M, N, K;       // multiples of 64, 64, 32
+  int k_split;       // K per grid.y slice (multiple of 32)
+  const float* bias; // EPI_HID, EPI_OUT: [N]
+  float* C;          // EPI_HID: pre-activations Z; EPI_OUT: output; EPI_DW: partial dW slices
+  int64_t ldc;
+  T* H;              // EPI_HID: activations; EPI_DX: dZ of the layer below
+  int64_t ldh;
+  T* HT;             // transposed copy of H (may be null)
+  int64_t ldht;
+  const float* Zin;  // EPI_DX: pre-activations of the layer below
+  int64_t ldz;
+  float* colsum;     // EPI_DX: per-64-row-tile column sums of dZ, [M/64][N]
+  const float* scale;  // EPI_OUT: optional de-normalisation y*scale + shift
+  const float* shift;
+  int n_valid;       // EPI_OUT: columns written
+  int m_valid;       // EPI_OUT: rows written
+};
+
+// One block = 4 waves = one 64x64 output tile; wave w owns the 32x32 quadrant
+// (w/2, w%2) as 2x2 MFMA blocks.  Blocks are renumbered so that the blocks one
+// XCD receives (hardware deals them round-robin over 8 XCDs) are consecutive
+// tiles, which share the A rows in that XCD's L2.
+template <class T, int EPI>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<T> g) {
+  using M = Mfma<T>;
+  __shared__ float red[64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tiles_n = g.N / TILE;
+  int tile = blockIdx.x;
+  const int nb = gridDim.x;
+  if ((nb & 7) == 0) tile = (tile & 7) * (nb >> 3) + (tile >> 3);
+  const int mt = tile / tiles_n;
+  const int m0 = mt * TILE + (wave >> 1) * 32;
+  const int n0 = (tile % tiles_n) * TILE + (wave & 1) * 32;
+  const int kb = blockIdx.y * g.k_split;
+  const int ke = min(g.K, kb + g.k_split);
+  const int r16 = lane & 15, grp = lane >> 4;
+
+  const T* a0 = g.A + (int64_t)(m0 + r16) * g.lda + grp * 8;
+  const T* a1 = a0 + 16 * g.lda;
+  const T* b0 = g.B + (int64_t)(n0 + r16) * g.ldb + grp * 8;
+  const T* b1 = b0 + 16 * g.ldb;
+
+  f32x4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  if (kb < ke) {
+    auto fa0 = M::load(a0 + kb), fa1 = M::load(a1 + kb);
+    auto fb0 = M::load(b0 + kb), fb1 = M::load(b1 + kb);
+    for (int k = kb + KSTEP; k < ke; k += KSTEP) {
+      auto na0 = M::load(a0 + k), na1 = M::load(a1 + k);
+      auto nb0 = M::load(b0 + k), nb1 = M::load(b1 + k);
+      M::mma(fa0, fb0, acc[0][0]);
+      M::mma(fa0, fb1, acc[0][1]);
+      M::mma(fa1, fb0, acc[1][0]);
+      M::mma(fa1, fb1, acc[1][1]);
+      fa0 = na0; fa1 = na1; fb0 = nb0; fb1 = nb1;
+    }
+    M::mma(fa0, fb0, acc[0][0]);
+    M::mma(fa0, fb1, acc[0][1]);
+    M::mma(fa1, fb0, acc[1][0]);
+    M::mma(fa1, fb1, acc[1][1]);
+  }
+
+  // ---- epilogue: acc[i][j][e] is C[m0 + 16i + 4 grp + e][n0 + 16j + r16]
+  float csum[2] = {0.f, 0.f};
+  for (int i = 0; i < 2; ++i) {
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + 16 * j + r16;
+      const int row = m0 + 16 * i + 4 * grp;
+      float v[4];
+      for (int e = 0; e < 4; ++e) v[e] = acc[i][j][e];
+      if constexpr (EPI == EPI_DW) {
+        float* c = g.C + (int64_t)blockIdx.y * g.M * g.ldc;
+        for (int e = 0; e < 4; ++e) c[(int64_t)(row + e) * g.ldc + col] = v[e];
+      } else if constexpr (EPI == EPI_OUT) {
+        if (col < g.n_valid) {
+          const float b = g.bias[col];
+          float sc = 1.f, sh = 0.f;
+          if (g.scale) {
+            sc = g.scale[col];
+            sh = g.shift[col];
+          }
+          for (int e = 0; e < 4; ++e)
+            if (row + e < g.m_valid) g.C[(int64_t)(row + e) * g.ldc + col] = (v[e] + b) * sc + sh;
+        }
+      } else {
+        T out[4];
+        if constexpr (EPI == EPI_HID) {
+          const float b = g.bias[col];
+          for (int e = 0; e < 4; ++e) {
+            const float z = v[e] + b;
+            if (g.C) g.C[(int64_t)(row + e) * g.ldc + col] = z;
+            out[e] = to_t<T>(z * sigmoid(z));
+          }
+        } else {  // EPI_DX: dz = dh * silu'(z) with silu'(z) = s (1 + z (1 - s))
+          for (int e = 0; e < 4; ++e) {
+            const float z = g.Zin[(int64_t)(row + e) * g.ldz + col];
+            const float s = sigmoid(z);
+            const float dz = v[e] * (s * (1.f + z * (1.f - s)));
+            csum[j] += dz;
+            out[e] = to_t<T>(dz);
+          }
+        }
+        for (int e = 0; e < 4; ++e) g.H[(int64_t)(row + e) * g.ldh + col] = out[e];
+        if (g.HT) {
+          T* ht = g.HT + (int64_t)col * g.ldht + row;
+          for (int e = 0; e < 4; ++e) ht[e] = out[e];
+        }
+      }
+    }
+  }
+  if constexpr (EPI == EPI_DX) {
+    // column sums over the 64-row tile: 4 rows per lane, 4 lane groups, 2 waves
+    for (int j = 0; j < 2; ++j) {
+      csum[j] += __shfl_xor(csum[j], 16);
+      csum[j] += __shfl_xor(csum[j], 32);
+    }
+    if ((wave >> 1) == 1 && grp == 0)
+      for (int j = 0; j < 2; ++j) red[(wave & 1) * 32 + 16 * j + r16] = csum[j];
+    __syncthreads();
+    if ((wave >> 1) == 0 && grp == 0)
+      for (int j = 0; j < 2; ++j) {
+        const int col = n0 + 16 * j + r16;
+        g.colsum[(int64_t)mt * g.N + col] = csum[j] + red[(wave & 1) * 32 + 16 * j + r16];
+      }
+  }
+}
+
+// ---- layer-0 input: gather rows, standardise, pad, write X and X^T ---------
+// Block: 64 rows x 64 columns through an LDS tile.
+template <class T>
+__global__ __launch_bounds__(256) void pack_input_kernel(
+    const float* __restrict__ x, int64_t ldx, const int* __restrict__ rows, int batch, int n_in,
+    const float* __restrict__ mean, const float* __restrict__ inv_std, T* X, int64_t ldX, T* XT,
+    int64_t ldXT) {
+  __shared__ float tile[64][65];
+  const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+  const int tc = threadIdx.x & 63, tr = threadIdx.x >> 6;
+  for (int rr = tr; rr < 64; rr += 4) {
+    const int r = r0 + rr, c = c0 + tc;
+    float v = 0.f;
+    if (r < batch && c < n_in) {
+      const int64_t src = rows ? (int64_t)rows[r] : (int64_t)r;
+      v = (x[src * ldx + c] - mean[c]) * inv_std[c];
+    }
+    tile[rr][tc] = v;
+    X[(int64_t)r * ldX + c] = to_t<T>(v);
+  }
+  if (!XT) return;
+  __syncthreads();
+  for (int cc = tr; cc < 64; cc += 4) XT[(int64_t)(c0 + cc) * ldXT + r0 + tc] = to_t<T>(tile[tc][cc]);
+}
+
+// ---- loss: L = mean over valid rows and the n_out columns of (yhat - y_n)^2,
+// y_n = (y - mean) / std.  Writes dL/dyhat (and its transpose), per-tile column
+// sums of it (the output bias gradient) and per-block partial losses.  Block:
+// 64 rows x 64 columns.
+template <class T>
+__global__ __launch_bounds__(256) void loss_kernel(
+    const float* __restrict__ yhat, int64_t ldyh, const float* __restrict__ y, int64_t ldy,
+    const int* __restrict__ rows, int batch, int n_out, const float* __restrict__ y_mean,
+    const float* __restrict__ y_inv_std, float grad_scale, T* dY, int64_t lddy, T* dYT,
+    int64_t lddyt, float* colsum, int ncols, double* partial) {
+  __shared__ float tile[64][65];
+  __shared__ double lsum[256];
+  const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+  const int tc = threadIdx.x & 63, tr = threadIdx.x >> 6;
+  const int c = c0 + tc;
+  double l2 = 0.0;
+  for (int rr = tr; rr < 64; rr += 4) {
+    const int r = r0 + rr;
+    float d = 0.f;
+    if (r < batch && c < n_out) {
+      const int64_t src = rows ? (int64_t)rows[r] : (int64_t)r;
+      const float yn = (y[src * ldy + c] - y_mean[c]) * y_inv_std[c];
+      const float e = yhat[(int64_t)r * ldyh + c] - yn;
+      l2 += (double)e * e;
+      d = grad_scale * e;
+    }
+    tile[rr][tc] = d;
+    dY[(int64_t)r * lddy + c] = to_t<T>(d);
+  }
+  lsum[threadIdx.x] = l2;
+  __syncthreads();
+  for (int cc = tr; cc < 64; cc += 4) dYT[(int64_t)(c0 + cc) * lddyt + r0 + tc] = to_t<T>(tile[tc][cc]);
+  if (threadIdx.x < 64) {
+    float sum = 0.f;
+    for (int rr = 0; rr < 64; ++rr) sum += tile[rr][threadIdx.x];
+    colsum[(int64_t)blockIdx.x * ncols + c0 + threadIdx.x] = sum;
+  }
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) lsum[threadIdx.x] += lsum[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = lsum[0];
+}
+
+__global__ void loss_final_kernel(const double* partial, int n, double inv_count, float* out) {
+  __shared__ double s[256];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) a += partial[i];
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = (float)(s[0] * inv_count);
+}
+
+// ---- parameter-vector kernels ----------------------------------------------
+// The padded parameter vector holds, per layer, W [out_p][in_p] then b [out_p].
+constexpr int MAX_LAYERS = 8;
+struct LayerTable {
+  int n_layers;
+  int64_t off[MAX_LAYERS + 1];  // start of each layer's block in the padded vector
+  int in_p[MAX_LAYERS], out_p[MAX_LAYERS];
+  int in_r[MAX_LAYERS], out_r[MAX_LAYERS];       // real sizes
+  int64_t off_r[MAX_LAYERS + 1];                 // same in the unpadded vector
+  int64_t woff[MAX_LAYERS];      // start of each layer's operand copy W (and W^T)
+  const float* dwp[MAX_LAYERS];  // split-K weight-gradient slices [slices][out_p][in_p]
+  int dw_slices[MAX_LAYERS];
+  const float* dbp[MAX_LAYERS];  // bias-gradient tile sums [tiles][out_p]
+  int db_tiles;
+};
+
+__device__ __forceinline__ int layer_of(const LayerTable& t, int64_t p) {
+  int l = 0;
+  while (l + 1 < t.n_layers && p >= t.off[l + 1]) ++l;
+  return l;
+}
+
+// g[p] = sum of the partial gradients of parameter p (fixed order).
+__global__ void grad_reduce_kernel(LayerTable t, float* g) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= t.off[t.n_layers]) return;
+  const int l = layer_of(t, p);
+  const int64_t q = p - t.off[l];
+  const int64_t nw = (int64_t)t.out_p[l] * t.in_p[l];
+  float s = 0.f;
+  if (q < nw) {
+    for (int k = 0; k < t.dw_slices[l]; ++k) s += t.dwp[l][(int64_t)k * nw + q];
+  } else {
+    const int o = (int)(q - nw);
+    for (int k = 0; k < t.db_tiles; ++k) s += t.dbp[l][(int64_t)k * t.out_p[l] + o];
+  }
+  g[p] = s;
+}
+
+// Adam on the FP32 master vector (update != 0), then the operand copies of
+// the weights, W [out_p][in_p] and W^T [in_p][out_p], from the master values.
+template <class T>
+__global__ void adam_kernel(LayerTable t, int update, float* P, const float* G, float* Mom,
+                            float* Vel, float lr, float b1, float b2, float eps, float c1, float c2,
+                            T* Wc, T* WTc) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= t.off[t.n_layers]) return;
+  float w = P[p];
+  if (update) {
+    const float gr = G[p];
+    const float m = b1 * Mom[p] + (1.f - b1) * gr;
+    const float v = b2 * Vel[p] + (1.f - b2) * gr * gr;
+    Mom[p] = m;
+    Vel[p] = v;
+    w -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+    P[p] = w;
+  }
+  const int l = layer_of(t, p);
+  const int64_t q = p - t.off[l];
+  const int64_t nw = (int64_t)t.out_p[l] * t.in_p[l];
+  if (q < nw) {
+    const int o = (int)(q / t.in_p[l]), i = (int)(q % t.in_p[l]);
+    Wc[t.woff[l] + q] = to_t<T>(w);
+    WTc[t.woff[l] + (int64_t)i * t.out_p[l] + o] = to_t<T>(w);
+  }
+}
+
+// Between the padded vector and the unpadded flat order (per layer W [out][in]
+// row-major, then b [out]).  dir 0: padded -> flat, 1: flat -> padded.
+__global__ void repack_kernel(LayerTable t, int dir, float* padded, float* flat) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= t.off[t.n_layers]) return;
+  const int l = layer_of(t, p);
+  const int64_t q = p - t.off[l];
+  const int64_t nw = (int64_t)t.out_p[l] * t.in_p[l];
+  int64_t f = -1;
+  if (q < nw) {
+    const int o = (int)(q / t.in_p[l]), i = (int)(q % t.in_p[l]);
+    if (o < t.out_r[l] && i < t.in_r[l]) f = t.off_r[l] + (int64_t)o * t.in_r[l] + i;
+  } else {
+    const int o = (int)(q - nw);
+    if (o < t.out_r[l]) f = t.off_r[l] + (int64_t)t.out_r[l] * t.in_r[l] + o;
+  }
+  if (dir == 0) {
+    if (f >= 0) flat[f] = padded[p];
+  } else {
+    padded[p] = f >= 0 ? flat[f] : 0.f;
+  }
+}
+
+// ---- column statistics (FP64 accumulation) ---------------------------------
+// partial[b][c] = sum over rows [b*chunk, (b+1)*chunk) of (x - shift[c])^pow
+__global__ void colstat_kernel(const float* __restrict__ x, int64_t ldx, int64_t rows, int cols,
+                               int64_t chunk, const double* shift, int pw, double* partial) {
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  const int64_t r1 = min(rows, r0 + chunk);
+  for (int c = threadIdx.x; c < cols; c += blockDim.x) {
+    const double sh = shift ? shift[c] : 0.0;
+    double s = 0.0;
+    for (int64_t r = r0; r < r1; ++r) {
+      const double d = (double)x[r * ldx + c] - sh;
+      s += pw == 1 ? d : d * d;
+    }
+    partial[(int64_t)blockIdx.x * cols + c] = s;
+  }
+}
+
+__global__ void colstat_final_kernel(const double* partial, int nb, int cols, double inv_rows,
+                                     int take_sqrt, double* out, float* out_f) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += partial[(int64_t)b * cols + c];
+  s *= inv_rows;
+  if (take_sqrt) s = sqrt(s);
+  out[c] = s;
+  out_f[c] = (float)s;
+}
+
+}  // namespace
+
+// ============================================================================
+// Host side
+// ============================================================================
+
+struct npx_sur {
+  int device = 0;
+  int n_in = 0, n_hidden = 0, n_hl = 0, n_out = 0, max_batch = 0, precision = 0, training = 0;
+  int n_layers = 0, hp = 0, in_p0 = 0, out_p = 0, Mp_max = 0;
+  size_t esz = 2;  // operand element size
+  LayerTable tab{};
+  int64_t n_pad = 0, n_real = 0, n_wc = 0;
+  int step = 0;
+  double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+
+  // parameters: master, gradient, Adam moments (padded order), operand copies
+  float *P = nullptr, *G = nullptr, *Mom = nullptr, *Vel = nullptr, *flat = nullptr;
+  void *Wc = nullptr, *WTc = nullptr;
+  // standardisation
+  float *x_mean = nullptr, *x_inv = nullptr, *y_mean = nullptr, *y_inv = nullptr, *y_std = nullptr;
+  // activations
+  void* X0 = nullptr;
+  void* X0T = nullptr;
+  std::vector<void*> H, HT;
+  std::vector<float*> Z;
+  float* Yhat = nullptr;
+  void *dA = nullptr, *dAT = nullptr, *dB = nullptr, *dBT = nullptr;
+  std::vector<float*> dwp, dbp;
+  double* loss_part = nullptr;
+  float* loss_tmp = nullptr;
+  std::vector<void*> owned;
+};
+
+namespace {
+
+constexpr int MAX_SLICES = 32;
+
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+template <class P>
+hipError_t sur_alloc(npx_sur* s, P** p, size_t bytes) {
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, bytes ? bytes : 1);
+  if (e == hipSuccess) {
+    s->owned.push_back(q);
+    *p = static_cast<P*>(q);
+  }
+  return e;
+}
+
+void sur_free(npx_sur* s) {
+  for (void* q : s->owned) (void)hipFree(q);
+  s->owned.clear();
+}
+
+uint64_t splitmix64(uint64_t& x) {
+  uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+int k_slices(int tiles, int K) {
+  int s = std::max(1, std::min(MAX_SLICES, (512 + tiles - 1) / tiles));
+  s = std::min(s, std::max(1, K / 256));
+  return s;
+}
+
+template <class T, int EPI>
+hipError_t launch_gemm(const GemmArgs<T>& g, int slices, hipStream_t st) {
+  if (g.M % TILE || g.N % TILE || g.K % KSTEP || g.k_split % KSTEP ||
+      (int64_t)g.k_split * slices < g.K)
+    return hipErrorInvalidValue;
+  dim3 grid((g.M / TILE) * (g.N / TILE), slices);
+  hipLaunchKernelGGL((gemm_kernel<T, EPI>), grid, dim3(256), 0, st, g);
+  return hipGetLastError();
+}
+
+template <class T>
+GemmArgs<T> gemm_args(const void* A, int64_t lda, const void* B, int64_t ldb, int M, int N, int K) {
+  GemmArgs<T> g{};
+  g.A = static_cast<const T*>(A);
+  g.B = static_cast<const T*>(B);
+  g.lda = lda;
+  g.ldb = ldb;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.k_split = K;
+  return g;
+}
+
+template <class T>
+const T* wc(const npx_sur* s, int l) {
+  return static_cast<const T*>(s->Wc) + s->tab.woff[l];
+}
+template <class T>
+const T* wtc(const npx_sur* s, int l) {
+  return static_cast<const T*>(s->WTc) + s->tab.woff[l];
+}
+inline const float* bias(const npx_sur* s, int l) {
+  return s->P + s->tab.off[l] + (int64_t)s->tab.out_p[l] * s->tab.in_p[l];
+}
+
+// Forward pass over `batch` gathered rows.  final_out == nullptr: training
+// pass (pre-activations, transposed copies, normalised output in Yhat); else
+// the de-normalised prediction goes to final_out.
+template <class T>
+npx_status forward_t(npx_sur* s, const float* x, int64_t ldx, const int* rows, int batch,
+                     float* final_out, int64_t ld_out, hipStream_t st) {
+  const int Mp = round_up(batch, TILE);
+  const bool train = final_out == nullptr;
+  {
+    dim3 grid(Mp / TILE, s->in_p0 / TILE);
+    hipLaunchKernelGGL((pack_input_kernel<T>), grid, dim3(256), 0, st, x, ldx, rows, batch,
+                       s->n_in, s->x_mean, s->x_inv, static_cast<T*>(s->X0), (int64_t)s->in_p0,
+                       train ? static_cast<T*>(s->X0T) : nullptr, (int64_t)Mp);
+    HIP_TRY(hipGetLastError());
+  }
+  const void* prev = s->X0;
+  int64_t ld_prev = s->in_p0;
+  for (int l = 0; l < s->n_hl; ++l) {
+    GemmArgs<T> g = gemm_args<T>(prev, ld_prev, wc<T>(s, l), s->tab.in_p[l], Mp, s->hp,
+                                 s->tab.in_p[l]);
+    g.bias = bias(s, l);
+    g.C = train ? s->Z[l] : nullptr;
+    g.ldc = s->hp;
+    g.H = static_cast<T*>(s->H[l]);
+    g.ldh = s->hp;
+    g.HT = train ? static_cast<T*>(s->HT[l]) : nullptr;
+    g.ldht = Mp;
+    HIP_TRY((launch_gemm<T, EPI_HID>(g, 1, st)));
+    prev = s->H[l];
+    ld_prev = s->hp;
+  }
+  const int L = s->n_layers - 1;
+  GemmArgs<T> g = gemm_args<T>(prev, ld_prev, wc<T>(s, L), s->tab.in_p[L], Mp, s->out_p,
+                               s->tab.in_p[L]);
+  g.bias = bias(s, L);
+  if (train) {
+    g.C = s->Yhat;
+    g.ldc = s->out_p;
+    g.n_valid = s->out_p;
+    g.m_valid = Mp;
+  } else {
+    g.C = final_out;
+    g.ldc = ld_out;
+    g.n_valid = s->n_out;
+    g.m_valid = batch;
+    g.scale = s->y_std;
+    g.shift = s->y_mean;
+  }
+  HIP_TRY((launch_gemm<T, EPI_OUT>(g, 1, st)));
+  return NPX_OK;
+}
+
+// Loss and gradient into G (padded order); loss (mean squared error over the
+// batch and the n_out standardised outputs) to loss_out[0].
+template <class T>
+npx_status backward_t(npx_sur* s, const float* x, int64_t ldx, const float* y, int64_t ldy,
+                      const int* rows, int batch, float* loss_out, hipStream_t st) {
+  npx_status r = forward_t<T>(s, x, ldx, rows, batch, nullptr, 0, st);
+  if (r != NPX_OK) return r;
+  const int Mp = round_up(batch, TILE);
+  const int tiles_m = Mp / TILE;
+  const int L = s->n_layers - 1;
+  {
+    const float scale = 2.0f / ((float)batch * (float)s->n_out);
+    hipLaunchKernelGGL((loss_kernel<T>), dim3(tiles_m, s->out_p / TILE), dim3(256), 0, st, s->Yhat,
+                       (int64_t)s->out_p, y, ldy, rows, batch, s->n_out, s->y_mean, s->y_inv,
+                       scale, static_cast<T*>(s->dA), (int64_t)s->out_p, static_cast<T*>(s->dAT),
+                       (int64_t)Mp, s->dbp[L], s->out_p, s->loss_part);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, st, s->loss_part,
+                       tiles_m * (s->out_p / TILE),
+                       1.0 / ((double)batch * s->n_out), loss_out ? loss_out : s->loss_tmp);
+    HIP_TRY(hipGetLastError());
+  }
+  void *cur = s->dA, *curT = s->dAT, *nxt = s->dB, *nxtT = s->dBT;
+  for (int l = L; l >= 0; --l) {
+    const int out_p = s->tab.out_p[l], in_p = s->tab.in_p[l];
+    // dW_l = dZ_l^T * H_{l-1}, split over the batch
+    const void* hprevT = l == 0 ? s->X0T : s->HT[l - 1];
+    GemmArgs<T> gw = gemm_args<T>(curT, Mp, hprevT, Mp, out_p, in_p, Mp);
+    const int tiles = (out_p / TILE) * (in_p / TILE);
+    const int sl = k_slices(tiles, Mp);
+    gw.k_split = round_up((Mp + sl - 1) / sl, KSTEP);
+    const int used = (Mp + gw.k_split - 1) / gw.k_split;
+    gw.C = s->dwp[l];
+    gw.ldc = in_p;
+    HIP_TRY((launch_gemm<T, EPI_DW>(gw, used, st)));
+    s->tab.dw_slices[l] = used;
+    if (l == 0) break;
+    // dZ_{l-1} = (dZ_l * W_l) . silu'(Z_{l-1})
+    GemmArgs<T> gx = gemm_args<T>(cur, out_p, wtc<T>(s, l), out_p, Mp, in_p, out_p);
+    gx.Zin = s->Z[l - 1];
+    gx.ldz = s->hp;
+    gx.H = static_cast<T*>(nxt);
+    gx.ldh = in_p;
+    gx.HT = static_cast<T*>(nxtT);
+    gx.ldht = Mp;
+    gx.colsum = s->dbp[l - 1];
+    HIP_TRY((launch_gemm<T, EPI_DX>(gx, 1, st)));
+    std::swap(cur, nxt);
+    std::swap(curT, nxtT);
+  }
+  s->tab.db_tiles = tiles_m;
+  for (int l = 0; l <= L; ++l) {
+    s->tab.dwp[l] = s->dwp[l];
+    s->tab.dbp[l] = s->dbp[l];
+  }
+  const int blocks = (int)((s->n_pad + 255) / 256);
+  hipLaunchKernelGGL(grad_reduce_kernel, dim3(blocks), dim3(256), 0, st, s->tab, s->G);
+  HIP_TRY(hipGetLastError());
+  return NPX_OK;
+}
+
+template <class T>
+hipError_t refresh_t(npx_sur* s, int update, float lr, hipStream_t st) {
+  const int blocks = (int)((s->n_pad + 255) / 256);
+  float c1 = 1.f, c2 = 1.f;
+  if (update) {
+    c1 = (float)(1.0 - std::pow(s->b1, s->step));
+    c2 = (float)(1.0 - std::pow(s->b2, s->step));
+  }
+  hipLaunchKernelGGL((adam_kernel<T>), dim3(blocks), dim3(256), 0, st, s->tab, update, s->P,
+                     s->G, s->Mom, s->Vel, lr, (float)s->b1, (float)s->b2, (float)s->eps, c1, c2,
+                     static_cast<T*>(s->Wc), static_cast<T*>(s->WTc));
+  return hipGetLastError();
+}
+
+hipError_t refresh(npx_sur* s, int update, float lr, hipStream_t st) {
+  return s->precision == NPX_SUR_FP32 ? refresh_t<float>(s, update, lr, st)
+                                      : refresh_t<__bf16>(s, update, lr, st);
+}
+
+npx_status check_io(const npx_sur* s, const float* x, int64_t ldx, int64_t batch) {
+  if (!s) return fail(NPX_EINVAL, "null surrogate handle");
+  if (batch < 0 || batch > s->max_batch)
+    return fail(NPX_EINVAL, "batch %lld outside [0, %d]", (long long)batch, s->max_batch);
+  if (batch > 0 && !x) return fail(NPX_EINVAL, "null input");
+  if (ldx < s->n_in) return fail(NPX_EINVAL, "input row stride %lld < n_in %d", (long long)ldx, s->n_in);
+  return NPX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+npx_status npx_sur_create(const npx_sur_desc* d, npx_sur** out) {
+  if (!d || !out) return fail(NPX_EINVAL, "null argument");
+  *out = nullptr;
+  if (d->n_in < 1 || d->n_hidden < 1 || d->n_out < 1 || d->n_hidden_layers < 1 ||
+      d->n_hidden_layers >= MAX_LAYERS || d->max_batch < 1 || d->max_batch > (1 << 24))
+    return fail(NPX_EINVAL, "bad network shape or batch limit");
+  if (d->precision != NPX_SUR_BF16 && d->precision != NPX_SUR_FP32)
+    return fail(NPX_EINVAL, "precision must be NPX_SUR_BF16 or NPX_SUR_FP32");
+  npx_sur* s = new npx_sur();
+  (void)hipGetDevice(&s->device);
+  s->n_in = d->n_in;
+  s->n_hidden = d->n_hidden;
+  s->n_hl = d->n_hidden_layers;
+  s->n_out = d->n_out;
+  s->max_batch = d->max_batch;
+  s->precision = d->precision;
+  s->training = d->training != 0;
+  s->esz = s->precision == NPX_SUR_FP32 ? 4 : 2;
+  s->n_layers = s->n_hl + 1;
+  s->hp = round_up(s->n_hidden, TILE);
+  s->in_p0 = round_up(s->n_in, TILE);
+  s->out_p = round_up(s->n_out, TILE);
+  s->Mp_max = round_up(s->max_batch, TILE);
+  LayerTable& t = s->tab;
+  t.n_layers = s->n_layers;
+  int64_t off = 0, off_r = 0, woff = 0;
+  for (int l = 0; l < s->n_layers; ++l) {
+    t.in_p[l] = l == 0 ? s->in_p0 : s->hp;
+    t.out_p[l] = l == s->n_layers - 1 ? s->out_p : s->hp;
+    t.in_r[l] = l == 0 ? s->n_in : s->n_hidden;
+    t.out_r[l] = l == s->n_layers - 1 ? s->n_out : s->n_hidden;
+    t.off[l] = off;
+    t.off_r[l] = off_r;
+    t.woff[l] = woff;
+    off += (int64_t)t.out_p[l] * (t.in_p[l] + 1);
+    off_r += (int64_t)t.out_r[l] * (t.in_r[l] + 1);
+    woff += (int64_t)t.out_p[l] * t.in_p[l];
+  }
+  t.off[s->n_layers] = off;
+  t.off_r[s->n_layers] = off_r;
+  s->n_pad = off;
+  s->n_real = off_r;
+  s->n_wc = woff;
+
+  // initial weights and biases: U(-1/sqrt(fan_in), 1/sqrt(fan_in)), padding 0
+  std::vector<float> hostP((size_t)s->n_pad, 0.f);
+  uint64_t rs = d->seed;
+  for (int l = 0; l < s->n_layers; ++l) {
+    const double bound = 1.0 / std::sqrt((double)t.in_r[l]);
+    float* w = hostP.data() + t.off[l];
+    for (int o = 0; o < t.out_r[l]; ++o)
+      for (int i = 0; i < t.in_r[l]; ++i)
+        w[(int64_t)o * t.in_p[l] + i] =
+            (float)(bound * (2.0 * ((splitmix64(rs) >> 11) * 0x1.0p-53) - 1.0));
+    float* b = w + (int64_t)t.out_p[l] * t.in_p[l];
+    for (int o = 0; o < t.out_r[l]; ++o)
+      b[o] = (float)(bound * (2.0 * ((splitmix64(rs) >> 11) * 0x1.0p-53) - 1.0));
+  }
+
+  const size_t Mp = (size_t)s->Mp_max;
+  hipError_t e = hipSuccess;
+  auto A = [&](auto** p, size_t bytes) {
+    if (e == hipSuccess) e = sur_alloc(s, p, bytes);
+  };
+  A(&s->P, s->n_pad * 4);
+  A(&s->G, s->n_pad * 4);
+  A(&s->Mom, s->n_pad * 4);
+  A(&s->Vel, s->n_pad * 4);
+  A(&s->flat, s->n_real * 4);
+  A(&s->Wc, s->n_wc * s->esz);
+  A(&s->WTc, s->n_wc * s->esz);
+  A(&s->x_mean, s->n_in * 4);
+  A(&s->x_inv, s->n_in * 4);
+  A(&s->y_mean, s->n_out * 4);
+  A(&s->y_inv, s->n_out * 4);
+  A(&s->y_std, s->n_out * 4);
+  A(&s->X0, Mp * s->in_p0 * s->esz);
+  s->H.assign(s->n_hl, nullptr);
+  for (int l = 0; l < s->n_hl; ++l) A(&s->H[l], Mp * s->hp * s->esz);
+  if (s->training) {
+    const size_t wmax = (size_t)std::max(s->hp, s->out_p);
+    A(&s->X0T, Mp * s->in_p0 * s->esz);
+    s->HT.assign(s->n_hl, nullptr);
+    s->Z.assign(s->n_hl, nullptr);
+    for (int l = 0; l < s->n_hl; ++l) {
+      A(&s->HT[l], Mp * s->hp * s->esz);
+      A(&s->Z[l], Mp * s->hp * 4);
+    }
+    A(&s->Yhat, Mp * s->out_p * 4);
+    A(&s->dA, Mp * wmax * s->esz);
+    A(&s->dAT, Mp * wmax * s->esz);
+    A(&s->dB, Mp * wmax * s->esz);
+    A(&s->dBT, Mp * wmax * s->esz);
+    s->dwp.assign(s->n_layers, nullptr);
+    s->dbp.assign(s->n_layers, nullptr);
+    for (int l = 0; l < s->n_layers; ++l) {
+      A(&s->dwp[l], (size_t)MAX_SLICES * t.out_p[l] * t.in_p[l] * 4);
+      A(&s->dbp[l], (Mp / TILE) * t.out_p[l] * 4);
+    }
+    A(&s->loss_part, (Mp / TILE) * (s->out_p / TILE) * 8);
+    A(&s->loss_tmp, 4);
+  }
+  if (e != hipSuccess) {
+    sur_free(s);
+    delete s;
+    return fail(NPX_ENOMEM, "device allocation for the surrogate failed: %s", hipGetErrorString(e));
+  }
+  std::vector<float> zero_in(s->n_in, 0.f), one_in(s->n_in, 1.f);
+  std::vector<float> zero_out(s->n_out, 0.f), one_out(s->n_out, 1.f);
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    if (e == hipSuccess) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+  };
+  up(s->P, hostP.data(), s->n_pad * 4);
+  up(s->x_mean, zero_in.data(), s->n_in * 4);
+  up(s->x_inv, one_in.data(), s->n_in * 4);
+  up(s->y_mean, zero_out.data(), s->n_out * 4);
+  up(s->y_inv, one_out.data(), s->n_out * 4);
+  up(s->y_std, one_out.data(), s->n_out * 4);
+  if (e == hipSuccess) e = hipMemset(s->G, 0, s->n_pad * 4);
+  if (e == hipSuccess) e = hipMemset(s->Mom, 0, s->n_pad * 4);
+  if (e == hipSuccess) e = hipMemset(s->Vel, 0, s->n_pad * 4);
+  if (e == hipSuccess) e = refresh(s, 0, 0.f, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    sur_free(s);
+    delete s;
+    return fail(NPX_EHIP, "surrogate initialisation failed: %s", hipGetErrorString(e));
+  }
+  *out = s;
+  return NPX_OK;
+}
+
+void npx_sur_destroy(npx_sur* s) {
+  if (!s) return;
+  (void)hipDeviceSynchronize();
+  sur_free(s);
+  delete s;
+}
+
+npx_status npx_sur_param_count(const npx_sur* s, int64_t* n) {
+  if (!s || !n) return fail(NPX_EINVAL, "null argument");
+  *n = s->n_real;
+  return NPX_OK;
+}
+
+npx_status npx_sur_get_params(npx_sur* s, float* dst, int64_t n, int on_device) {
+  if (!s || !dst) return fail(NPX_EINVAL, "null argument");
+  if (n != s->n_real) return fail(NPX_EINVAL, "expected %lld parameters", (long long)s->n_real);
+  HIP_TRY(hipDeviceSynchronize());
+  const int blocks = (int)((s->n_pad + 255) / 256);
+  hipLaunchKernelGGL(repack_kernel, dim3(blocks), dim3(256), 0, nullptr, s->tab, 0, s->P, s->flat);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpy(dst, s->flat, n * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+  return NPX_OK;
+}
+
+npx_status npx_sur_set_params(npx_sur* s, const float* src, int64_t n, int on_device) {
+  if (!s || !src) return fail(NPX_EINVAL, "null argument");
+  if (n != s->n_real) return fail(NPX_EINVAL, "expected %lld parameters", (long long)s->n_real);
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(s->flat, src, n * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+  const int blocks = (int)((s->n_pad + 255) / 256);
+  hipLaunchKernelGGL(repack_kernel, dim3(blocks), dim3(256), 0, nullptr, s->tab, 1, s->P, s->flat);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemset(s->Mom, 0, s->n_pad * 4));
+  HIP_TRY(hipMemset(s->Vel, 0, s->n_pad * 4));
+  s->step = 0;
+  HIP_TRY(refresh(s, 0, 0.f, nullptr));
+  HIP_TRY(hipDeviceSynchronize());
+  return NPX_OK;
+}
+
+npx_status npx_sur_set_norm(npx_sur* s, const float* x_mean, const float* x_std,
+                            const float* y_mean, const float* y_std) {
+  if (!s || !x_mean || !x_std || !y_mean || !y_std) return fail(NPX_EINVAL, "null argument");
+  std::vector<float> xi(s->n_in), yi(s->n_out), ys(s->n_out);
+  for (int c = 0; c < s->n_in; ++c) {
+    if (!(x_std[c] >= 0.f) || !std::isfinite(x_mean[c]))
+      return fail(NPX_EINVAL, "input statistics of column %d are not finite", c);
+    xi[c] = x_std[c] > 1e-12f ? 1.f / x_std[c] : 1.f;
+  }
+  for (int c = 0; c < s->n_out; ++c) {
+    if (!(y_std[c] >= 0.f) || !std::isfinite(y_mean[c]))
+      return fail(NPX_EINVAL, "output statistics of column %d are not finite", c);
+    ys[c] = y_std[c] > 1e-12f ? y_std[c] : 1.f;
+    yi[c] = 1.f / ys[c];
+  }
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(s->x_mean, x_mean, s->n_in * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(s->x_inv, xi.data(), s->n_in * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(s->y_mean, y_mean, s->n_out * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(s->y_inv, yi.data(), s->n_out * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(s->y_std, ys.data(), s->n_out * 4, hipMemcpyHostToDevice));
+  return NPX_OK;
+}
+
+npx_status npx_sur_set_adam(npx_sur* s, double beta1, double beta2, double eps) {
+  if (!s) return fail(NPX_EINVAL, "null surrogate handle");
+  if (!(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+    return fail(NPX_EINVAL, "Adam needs 0 <= beta < 1 and eps > 0");
+  s->b1 = beta1;
+  s->b2 = beta2;
+  s->eps = eps;
+  return NPX_OK;
+}
+
+npx_status npx_sur_forward(npx_sur* s, const float* x, int64_t ldx, const int32_t* rows,
+                           int64_t batch, float* y, int64_t ldy, void* stream) {
+  npx_status r = check_io(s, x, ldx, batch);
+  if (r != NPX_OK) return r;
+  if (batch == 0) return NPX_OK;
+  if (!y || ldy < s->n_out) return fail(NPX_EINVAL, "bad output buffer or stride");
+  hipStream_t st = (hipStream_t)stream;
+  return s->precision == NPX_SUR_FP32
+             ? forward_t<float>(s, x, ldx, rows, (int)batch, y, ldy, st)
+             : forward_t<__bf16>(s, x, ldx, rows, (int)batch, y, ldy, st);
+}
+
+npx_status npx_sur_grad(npx_sur* s, const float* x, int64_t ldx, const float* y, int64_t ldy,
+                        const int32_t* rows, int64_t batch, float* loss, float* grad,
+                        void* stream) {
+  npx_status r = check_io(s, x, ldx, batch);
+  if (r != NPX_OK) return r;
+  if (!s->training) return fail(NPX_ESTATE, "surrogate was created without training buffers");
+  if (batch < 1) return fail(NPX_EINVAL, "empty batch");
+  if (!y || ldy < s->n_out) return fail(NPX_EINVAL, "bad target buffer or stride");
+  hipStream_t st = (hipStream_t)stream;
+  r = s->precision == NPX_SUR_FP32
+          ? backward_t<float>(s, x, ldx, y, ldy, rows, (int)batch, loss, st)
+          : backward_t<__bf16>(s, x, ldx, y, ldy, rows, (int)batch, loss, st);
+  if (r != NPX_OK || !grad) return r;
+  const int blocks = (int)((s->n_pad + 255) / 256);
+  hipLaunchKernelGGL(repack_kernel, dim3(blocks), dim3(256), 0, st, s->tab, 0, s->G, grad);
+  HIP_TRY(hipGetLastError());
+  return NPX_OK;
+}
+
+npx_status npx_sur_train_step(npx_sur* s, const float* x, int64_t ldx, const float* y,
+                              int64_t ldy, const int32_t* rows, int64_t batch, double lr,
+                              float* loss, void* stream) {
+  if (!(lr >= 0)) return fail(NPX_EINVAL, "learning rate must be >= 0");
+  npx_status r = npx_sur_grad(s, x, ldx, y, ldy, rows, batch, loss, nullptr, stream);
+  if (r != NPX_OK) return r;
+  s->step += 1;
+  HIP_TRY(refresh(s, 1, (float)lr, (hipStream_t)stream));
+  return NPX_OK;
+}
+
+npx_status npx_sur_norm_stats(const float* x, int64_t ldx, int64_t rows, int32_t cols,
+                              float* mean, float* std_out, void* stream) {
+  if (!x || !mean || !std_out || rows < 1 || cols < 1 || ldx < cols)
+    return fail(NPX_EINVAL, "bad statistics arguments");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t chunk = std::max<int64_t>(256, (rows + 1023) / 1024);
+  const int nb = (int)((rows + chunk - 1) / chunk);
+  double *part = nullptr, *mu = nullptr, *sd = nullptr;
+  HIP_TRY(hipMalloc(&part, (size_t)nb * cols * 8));
+  hipError_t e = hipMalloc(&mu, (size_t)cols * 8);
+  if (e == hipSuccess) e = hipMalloc(&sd, (size_t)cols * 8);
+  const int fb = (cols + 255) / 256;
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(colstat_kernel, dim3(nb), dim3(256), 0, st, x, ldx, rows, cols, chunk,
+                       (const double*)nullptr, 1, part);
+    hipLaunchKernelGGL(colstat_final_kernel, dim3(fb), dim3(256), 0, st, part, nb, cols,
+                       1.0 / (double)rows, 0, mu, mean);
+    hipLaunchKernelGGL(colstat_kernel, dim3(nb), dim3(256), 0, st, x, ldx, rows, cols, chunk,
+                       (const double*)mu, 2, part);
+    hipLaunchKernelGGL(colstat_final_kernel, dim3(fb), dim3(256), 0, st, part, nb, cols,
+                       1.0 / (double)rows, 1, sd, std_out);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(part);
+  if (mu) (void)hipFree(mu);
+  if (sd) (void)hipFree(sd);
+  if (e != hipSuccess) return fail(NPX_EHIP, "column statistics failed: %s", hipGetErrorString(e));
+  return NPX_OK;
+}
+
+}  // extern "C"

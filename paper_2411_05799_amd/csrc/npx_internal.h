@@ -5,7 +5,12 @@
 
 #include <cstdint>
 
+#include "npx.h"
+
 namespace npx {
+
+// Records the message returned by npx_last_error and returns s.
+npx_status fail(npx_status s, const char* fmt, ...);
 
 // Link table row (LINK_F floats): hinge anchor [0..2], axis [3..5], lower and
 // upper limit [6..7], link mass [8], link CoG in the construction frame

@@ -18,9 +18,10 @@
 #include "npx_internal.h"
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
+namespace npx {
 npx_status fail(npx_status s, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -30,6 +31,10 @@ npx_status fail(npx_status s, const char* fmt, ...) {
   g_err = buf;
   return s;
 }
+}  // namespace npx
+
+namespace {
+using npx::fail;
 
 #define HIP_TRY(expr)                                                                  \
   do {                                                                                 \

@@ -56,6 +56,15 @@ class Launch(C.Structure):
 _lib = None
 
 
+class SurDesc(C.Structure):
+    _fields_ = [("n_in", C.c_int32), ("n_hidden", C.c_int32), ("n_hidden_layers", C.c_int32),
+                ("n_out", C.c_int32), ("max_batch", C.c_int32), ("precision", C.c_int32),
+                ("training", C.c_int32), ("seed", C.c_uint64)]
+
+
+SUR_BF16, SUR_FP32 = 0, 1
+
+
 def lib():
     """The HIP library; raises if it has not been built (no fallback exists)."""
     global _lib
@@ -63,6 +72,14 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise NpxError(f"{LIB_PATH} is missing: build it with "
                            "`python -m paper_2411_05799_amd.build`")
+        # torch's bundled HIP runtime is asked for as libamdhip64.so, which
+        # does not match an already loaded /opt/rocm libamdhip64.so.7; loading
+        # torch first makes its runtime the process's only one, which this
+        # library then binds to (same soname).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         vp = C.c_void_p
         L.npx_last_error.restype = C.c_char_p
@@ -107,6 +124,24 @@ def lib():
                      "npx_connect_bodies", "npx_create_joint", "npx_set_joint_limits",
                      "npx_move_body", "npx_rotate_body", "npx_get_max_body_id",
                      "npx_finalize_construction", "npx_morph_get_tables", "npx_morph_joint_index"):
+            getattr(L, name).restype = C.c_int
+        i64, pi64 = C.c_int64, C.POINTER(C.c_int64)
+        L.npx_sur_create.argtypes = [C.POINTER(SurDesc), C.POINTER(vp)]
+        L.npx_sur_destroy.argtypes = [vp]
+        L.npx_sur_destroy.restype = None
+        L.npx_sur_param_count.argtypes = [vp, pi64]
+        L.npx_sur_get_params.argtypes = [vp, vp, i64, C.c_int]
+        L.npx_sur_set_params.argtypes = [vp, vp, i64, C.c_int]
+        L.npx_sur_set_norm.argtypes = [vp, vp, vp, vp, vp]
+        L.npx_sur_set_adam.argtypes = [vp, d, d, d]
+        L.npx_sur_forward.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp]
+        L.npx_sur_grad.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp, vp, vp]
+        L.npx_sur_train_step.argtypes = [vp, vp, i64, vp, i64, vp, i64, d, vp, vp]
+        L.npx_sur_norm_stats.argtypes = [vp, i64, i64, C.c_int32, vp, vp, vp]
+        for name in ("npx_sur_create", "npx_sur_param_count", "npx_sur_get_params",
+                     "npx_sur_set_params", "npx_sur_set_norm", "npx_sur_set_adam",
+                     "npx_sur_forward", "npx_sur_grad", "npx_sur_train_step",
+                     "npx_sur_norm_stats"):
             getattr(L, name).restype = C.c_int
         for name in ("npx_create_world", "npx_world_dims", "npx_set_controller", "npx_step_n",
                      "npx_read_state", "npx_write_state", "npx_read_points", "npx_get_launch",
@@ -391,6 +426,94 @@ def _stream_handle(stream):
     if hasattr(stream, "cuda_stream"):
         return int(stream.cuda_stream)
     return int(stream)
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (None -> NULL)."""
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+class Surrogate:
+    """The surrogate network (npx_sur_create ... npx_sur_destroy).  Device
+    buffers are torch tensors on the current HIP device: x [rows, >= n_in]
+    float32, y [rows, >= n_out] float32, rows int32."""
+
+    def __init__(self, n_in, n_hidden, n_hidden_layers, n_out, max_batch, precision=SUR_BF16,
+                 training=True, seed=0):
+        d = SurDesc(n_in, n_hidden, n_hidden_layers, n_out, max_batch, precision,
+                    1 if training else 0, seed)
+        h = C.c_void_p()
+        check(lib().npx_sur_create(C.byref(d), C.byref(h)))
+        self.h = h
+        self.n_in, self.n_out, self.max_batch = n_in, n_out, max_batch
+        self.shapes = [(n_hidden, n_in)] + [(n_hidden, n_hidden)] * (n_hidden_layers - 1) + \
+                      [(n_out, n_hidden)]
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().npx_sur_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def param_count(self):
+        n = C.c_int64()
+        check(lib().npx_sur_param_count(self.h, C.byref(n)))
+        return n.value
+
+    def get_params(self):
+        a = np.empty(self.param_count(), dtype=np.float32)
+        check(lib().npx_sur_get_params(self.h, a.ctypes.data_as(C.c_void_p), a.size, 0))
+        return a
+
+    def set_params(self, p):
+        if hasattr(p, "data_ptr"):
+            check(lib().npx_sur_set_params(self.h, _ptr(p), p.numel(), 1))
+            return
+        a = _f32(p)
+        check(lib().npx_sur_set_params(self.h, a.ctypes.data_as(C.c_void_p), a.size, 0))
+
+    def set_norm(self, x_mean, x_std, y_mean, y_std):
+        a = [_f32(v) for v in (x_mean, x_std, y_mean, y_std)]
+        check(lib().npx_sur_set_norm(self.h, *[v.ctypes.data_as(C.c_void_p) for v in a]))
+
+    def set_adam(self, beta1=0.9, beta2=0.999, eps=1e-8):
+        check(lib().npx_sur_set_adam(self.h, beta1, beta2, eps))
+
+    def forward(self, x, out, rows=None, batch=None, stream=None):
+        b = x.shape[0] if rows is None else rows.shape[0]
+        b = b if batch is None else batch
+        check(lib().npx_sur_forward(self.h, _ptr(x), x.stride(0), _ptr(rows), b, _ptr(out),
+                                    out.stride(0), C.c_void_p(_stream_handle(stream))))
+        return out
+
+    def grad(self, x, y, loss=None, grad=None, rows=None, batch=None, stream=None):
+        b = x.shape[0] if rows is None else rows.shape[0]
+        b = b if batch is None else batch
+        check(lib().npx_sur_grad(self.h, _ptr(x), x.stride(0), _ptr(y), y.stride(0), _ptr(rows),
+                                 b, _ptr(loss), _ptr(grad), C.c_void_p(_stream_handle(stream))))
+
+    def train_step(self, x, y, lr, loss=None, rows=None, batch=None, stream=None):
+        b = x.shape[0] if rows is None else rows.shape[0]
+        b = b if batch is None else batch
+        check(lib().npx_sur_train_step(self.h, _ptr(x), x.stride(0), _ptr(y), y.stride(0),
+                                       _ptr(rows), b, float(lr), _ptr(loss),
+                                       C.c_void_p(_stream_handle(stream))))
+
+
+def norm_stats(x, cols=None, stream=None):
+    """Column means and standard deviations of a device matrix (torch tensors out)."""
+    import torch
+    cols = x.shape[1] if cols is None else cols
+    mean = torch.empty(cols, dtype=torch.float32, device=x.device)
+    std = torch.empty(cols, dtype=torch.float32, device=x.device)
+    check(lib().npx_sur_norm_stats(_ptr(x), x.stride(0), x.shape[0], cols, _ptr(mean), _ptr(std),
+                                   C.c_void_p(_stream_handle(stream))))
+    return mean, std
 
 
 def exported_symbols():

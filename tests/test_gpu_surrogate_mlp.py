@@ -1,0 +1,246 @@
+"""GPU parity of the surrogate network's kernels (forward, loss, gradient, Adam,
+column statistics) against the FP64 network oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from oracle import mlp_oracle as M
+
+pytestmark = pytest.mark.gpu
+
+SHAPE = dict(n_in=293, n_hidden=256, n_hidden_layers=3, n_out=49)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def bf16_round(a):
+    """Round to the nearest BF16 value (ties to even), returned as float64."""
+    f = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    f = (f + 0x7FFF + ((f >> 16) & 1)) & 0xFFFF0000
+    return f.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _make(precision, max_batch=1024, seed=11, training=True):
+    from paper_2411_05799_amd import native as N
+    return N.Surrogate(max_batch=max_batch, precision=precision, training=training, seed=seed,
+                       **SHAPE)
+
+
+def _data(rng, rows, bf16=False):
+    x = rng.normal(0.3, 1.7, size=(rows, SHAPE["n_in"]))
+    y = rng.normal(-0.2, 0.8, size=(rows, SHAPE["n_out"]))
+    xm, xs = x.mean(0), x.std(0)
+    ym, ys = y.mean(0), y.std(0)
+    if bf16:   # identity standardisation so that the BF16 operands are the inputs themselves
+        x = bf16_round(x)
+        xm, xs = np.zeros(SHAPE["n_in"]), np.ones(SHAPE["n_in"])
+    return x.astype(np.float32), y.astype(np.float32), xm, xs, ym, ys
+
+
+def _dev(a, dtype=None):
+    torch = _torch()
+    return torch.tensor(a, device="cuda", dtype=dtype)
+
+
+def _shapes():
+    return M.layer_shapes(SHAPE["n_in"], SHAPE["n_hidden"], SHAPE["n_hidden_layers"], SHAPE["n_out"])
+
+
+def test_initial_params_are_uniform_in_fan_in_bounds():
+    from paper_2411_05799_amd import native as N
+    s = _make(N.SUR_FP32, max_batch=64)
+    p = s.get_params().astype(np.float64)
+    assert p.size == M.param_count(_shapes()) == 219441
+    for (W, b), (o, i) in zip(M.unflatten(p, _shapes()), _shapes()):
+        bnd = 1 / np.sqrt(i)
+        assert np.abs(W).max() <= bnd and np.abs(b).max() <= bnd
+        assert abs(W.std() - bnd / np.sqrt(3)) < 0.05 * bnd
+    q = np.random.default_rng(0).normal(size=p.size).astype(np.float32)
+    s.set_params(q)
+    np.testing.assert_array_equal(s.get_params(), q)
+    s.close()
+
+
+@pytest.mark.parametrize("batch", [1, 37, 300, 1024])
+def test_forward_fp32_matches_oracle(batch):
+    from paper_2411_05799_amd import native as N
+    torch = _torch()
+    rng = np.random.default_rng(batch)
+    x, y, xm, xs, ym, ys = _data(rng, 1500)
+    s = _make(N.SUR_FP32)
+    s.set_norm(xm, xs, ym, ys)
+    p = s.get_params().astype(np.float64)
+    rows = rng.choice(1500, batch, replace=False).astype(np.int32)
+    out = torch.full((batch, 64), 7.0, device="cuda")
+    s.forward(_dev(x), out[:, :49], rows=_dev(rows))
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    ref = M.predict(p, _shapes(), x[rows].astype(np.float64), xm.astype(np.float32),
+                    xs.astype(np.float32), ym.astype(np.float32), ys.astype(np.float32))
+    err = np.abs(got[:, :49] - ref).max() / np.abs(ref).max()
+    assert err <= 1e-5, err
+    assert np.all(got[:, 49:] == 7.0)        # columns past n_out untouched
+    s.close()
+
+
+def _grad_case(precision, batch, seed):
+    from paper_2411_05799_amd import native as N
+    torch = _torch()
+    bf16 = precision == N.SUR_BF16
+    rng = np.random.default_rng(seed)
+    x, y, xm, xs, ym, ys = _data(rng, batch, bf16=bf16)
+    s = _make(precision)
+    if bf16:
+        s.set_params(bf16_round(s.get_params()))
+    s.set_norm(xm, xs, ym, ys)
+    p = s.get_params().astype(np.float64)
+    loss = torch.zeros(1, device="cuda")
+    g = torch.zeros(p.size, device="cuda")
+    s.grad(_dev(x), _dev(y), loss=loss, grad=g)
+    torch.cuda.synchronize()
+    f32 = np.float32
+    xn = M.standardise(x.astype(np.float64), xm.astype(f32), xs.astype(f32))
+    yn = M.standardise(y.astype(np.float64), ym.astype(f32), ys.astype(f32))
+    l_ref, g_ref = M.loss_and_grad(p, _shapes(), xn, yn)
+    s.close()
+    return float(loss.item()), l_ref, g.cpu().numpy().astype(np.float64), g_ref
+
+
+@pytest.mark.parametrize("batch", [64, 200, 1024])
+def test_gradient_fp32_matches_oracle(batch):
+    from paper_2411_05799_amd import native as N
+    l, l_ref, g, g_ref = _grad_case(N.SUR_FP32, batch, 5 + batch)
+    assert abs(l - l_ref) <= 1e-6 * l_ref
+    rel = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    assert rel <= 1e-5, rel
+    # per layer too, so that a small layer's error is not hidden by a large one
+    for (Wg, bg), (Wr, br) in zip(M.unflatten(g, _shapes()), M.unflatten(g_ref, _shapes())):
+        assert np.linalg.norm(Wg - Wr) <= 1e-5 * np.linalg.norm(Wr)
+        assert np.linalg.norm(bg - br) <= 1e-5 * np.linalg.norm(br)
+
+
+def test_gradient_bf16_within_1e_2_of_oracle():
+    from paper_2411_05799_amd import native as N
+    l, l_ref, g, g_ref = _grad_case(N.SUR_BF16, 1000, 3)
+    assert abs(l - l_ref) <= 1e-2 * l_ref
+    for (Wg, bg), (Wr, br) in zip(M.unflatten(g, _shapes()), M.unflatten(g_ref, _shapes())):
+        assert np.linalg.norm(Wg - Wr) <= 1e-2 * np.linalg.norm(Wr)
+        assert np.linalg.norm(bg - br) <= 1e-2 * np.linalg.norm(br)
+
+
+def test_forward_bf16_within_1e_2_of_oracle():
+    from paper_2411_05799_amd import native as N
+    torch = _torch()
+    rng = np.random.default_rng(8)
+    x, y, xm, xs, ym, ys = _data(rng, 500, bf16=True)
+    s = _make(N.SUR_BF16)
+    s.set_params(bf16_round(s.get_params()))
+    s.set_norm(xm, xs, ym, ys)
+    p = s.get_params().astype(np.float64)
+    out = torch.zeros((500, 49), device="cuda")
+    s.forward(_dev(x), out)
+    torch.cuda.synchronize()
+    f32 = np.float32
+    ref = M.predict(p, _shapes(), x.astype(np.float64), xm, xs, ym.astype(f32), ys.astype(f32))
+    got = out.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(got - ref) <= 1e-2 * np.linalg.norm(ref - ym.astype(f32))
+    s.close()
+
+
+def test_adam_step_fp32_matches_oracle():
+    from paper_2411_05799_amd import native as N
+    torch = _torch()
+    rng = np.random.default_rng(21)
+    x, y, xm, xs, ym, ys = _data(rng, 512)
+    s = _make(N.SUR_FP32)
+    s.set_norm(xm, xs, ym, ys)
+    p = s.get_params().astype(np.float64)
+    f32 = np.float32
+    xn = M.standardise(x.astype(np.float64), xm.astype(f32), xs.astype(f32))
+    yn = M.standardise(y.astype(np.float64), ym.astype(f32), ys.astype(f32))
+    opt = M.Adam(p.size, 1e-3)
+    lrs = [1e-3, 5e-4, 2e-4]
+    xd, yd = _dev(x), _dev(y)
+    for lr in lrs:
+        _, g_ref = M.loss_and_grad(p, _shapes(), xn, yn)
+        p_new = opt.step(p, g_ref, lr=lr)
+        s.train_step(xd, yd, lr)
+        got = s.get_params().astype(np.float64)
+        # Adam's step is insensitive to gradient error except where |g| is near eps
+        big = np.abs(g_ref) > 1e-4 * np.abs(g_ref).max()
+        assert np.abs((got - p_new)[big]).max() <= 2e-3 * lr
+        assert np.abs(got - p_new).max() <= 2.0 * lr + 1e-6
+        p = got     # continue both from the GPU's parameters
+        opt_state = opt
+    del opt_state
+    s.close()
+
+
+def test_training_reduces_loss_and_is_deterministic():
+    from paper_2411_05799_amd import native as N
+    torch = _torch()
+    rng = np.random.default_rng(4)
+    n = 8192
+    x = rng.normal(size=(n, SHAPE["n_in"])).astype(np.float32)
+    A = rng.normal(size=(SHAPE["n_in"], SHAPE["n_out"])) / np.sqrt(SHAPE["n_in"])
+    y = np.tanh(x @ A).astype(np.float32)
+    xd, yd = _dev(x), _dev(y)
+    xm, xs = norm_stats_host(x)
+    ym, ys = norm_stats_host(y)
+    losses, params = [], []
+    for rep in range(2):
+        s = _make(N.SUR_BF16, max_batch=1024, seed=3)
+        s.set_norm(xm, xs, ym, ys)
+        loss = torch.zeros(1, device="cuda")
+        g = torch.Generator().manual_seed(0)
+        hist = []
+        for it in range(150):
+            rows = torch.randint(0, n, (1024,), generator=g, dtype=torch.int32).cuda()
+            s.train_step(xd, yd, 2e-3, loss=loss, rows=rows)
+            hist.append(loss.item())
+        losses.append(hist)
+        params.append(s.get_params())
+        s.close()
+    assert np.mean(losses[0][-10:]) < 0.25 * np.mean(losses[0][:3]), (losses[0][:3], losses[0][-10:])
+    np.testing.assert_array_equal(params[0], params[1])
+    assert losses[0] == losses[1]
+
+
+def norm_stats_host(a):
+    m, s = M.column_stats(a)
+    return m.astype(np.float32), s.astype(np.float32)
+
+
+def test_norm_stats_match_numpy():
+    from paper_2411_05799_amd import native as N
+    torch = _torch()
+    rng = np.random.default_rng(9)
+    rows, ld, cols = 100003, 345, 342
+    a = rng.normal(2.0, 3.0, size=(rows, ld)).astype(np.float32)
+    a[:, 5] = 1.25
+    m, s = N.norm_stats(_dev(a), cols=cols)
+    mr, sr = M.column_stats(a[:, :cols].astype(np.float64))
+    np.testing.assert_allclose(m.cpu().numpy(), mr, rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(s.cpu().numpy(), sr, rtol=1e-6, atol=1e-7)
+    assert s[5].item() == 0.0
+
+
+def test_edge_cases_and_errors():
+    from paper_2411_05799_amd import native as N
+    torch = _torch()
+    s = _make(N.SUR_BF16, max_batch=100, training=False)
+    x = torch.zeros((200, SHAPE["n_in"]), device="cuda")
+    out = torch.zeros((200, 49), device="cuda")
+    s.forward(x, out, batch=0)                      # empty batch: no work
+    with pytest.raises(N.NpxError):
+        s.forward(x, out)                           # 200 > max_batch
+    with pytest.raises(N.NpxError):
+        s.grad(x[:10], out[:10])                    # no training buffers
+    s.forward(x[:100], out[:100])                   # exactly max_batch
+    torch.cuda.synchronize()
+    assert torch.isfinite(out[:100]).all() and (out[100:] == 0).all()
+    s.close()
+    with pytest.raises(N.NpxError):
+        N.Surrogate(n_in=3, n_hidden=8, n_hidden_layers=0, n_out=1, max_batch=4)
