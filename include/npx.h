@@ -301,6 +301,54 @@ npx_status npx_sur_train_step(npx_sur* s, const float* x, int64_t ldx, const flo
 npx_status npx_sur_norm_stats(const float* x, int64_t ldx, int64_t rows, int32_t cols,
                               float* mean, float* std, void* stream);
 
+/* ---- The simulator side of the surrogate ------------------------------------
+ * State row of an instance, width 13 + 2 J (J = the world's joint stride, the
+ * largest joint count over its morphologies): c (3, world CoG), Q (4, w x y z),
+ * v (3), omega (3), q (J), q_prev (J); joints past an instance's own count are
+ * 0.  Network input, width 13 + 12 J + 64:
+ *   [0, 13)          0, 0, c_z - h(c_x, c_y), Q, v, omega
+ *   [13, 13 + J)     q;   [13 + J, 13 + 2 J)   (q - q_prev) / dt
+ *   [13 + 2 J, 13 + 12 J)   the clamped commanded angles the next 10 frames
+ *                    apply, frames n .. n + 9, frame-major
+ *   [13 + 12 J, +64) an 8 x 8 patch of the height map at 0.08 m spacing,
+ *                    centred on the CoG and turned with the torso heading (the
+ *                    torso x axis on the ground plane), each sample minus
+ *                    h(c_x, c_y); index 8 a + b, a along the heading, b to its left.
+ * Frame n is the frame about to be stepped.  All buffers are device pointers,
+ * row-major with the given row stride (in floats); calls are asynchronous on
+ * `stream` and are ordered after earlier work on the world only through it. */
+npx_status npx_sur_widths(const npx_world* w, int32_t* state_width, int32_t* feature_width);
+/* s[i] = state row of instance i. */
+npx_status npx_world_rows(npx_world* w, float* s, int64_t lds, void* stream);
+/* x[i] = network input of instance i, from the state rows s (s != NULL, at
+ * frame `frame` >= 0) or from the world's own state and step counters (s ==
+ * NULL), with the world's controllers and height map. */
+npx_status npx_sur_features(npx_world* w, const float* s, int64_t lds, int64_t frame, float* x,
+                            int64_t ldx, void* stream);
+/* y[i] = (world state row of i) - s0[i]: the training target after stepping. */
+npx_status npx_sur_delta(npx_world* w, const float* s0, int64_t lds, float* y, int64_t ldy,
+                         void* stream);
+/* Rollout update of rows s at frame n: the body rows gain dy (Q renormalised),
+ * q and q_prev become the clamped commands of frames n + 9 and n + 8 (what the
+ * step sets).  Needs joint_interval == 1 (NPX_EUNSUPPORTED otherwise). */
+npx_status npx_sur_advance(npx_world* w, float* s, int64_t lds, const float* dy, int64_t lddy,
+                           int64_t frame, void* stream);
+/* Joint-torque proxy of the controller-search fitness: each point carries its
+ * weight m_k g; the points less than 0.002 m above the height map share the
+ * robot's weight M |g| as an upward load; the torque of joint j is the moment
+ * of the loads on all points distal to it, about its anchor, on its axis.
+ * acc[i] (+)= mean over the instance's joints of |tau_j|, from rows s or (s ==
+ * NULL) the world's state.  Up to 64 links. */
+npx_status npx_sur_torque(npx_world* w, const float* s, int64_t lds, float* acc, int accumulate,
+                          void* stream);
+/* n_calls surrogate calls from rows s at frame frame0: per call the inputs
+ * (into x_work [I][ldx]), the network (into y_work [I][ldy]), the update of s,
+ * and (tau_acc != NULL) the torque proxy added to tau_acc[i].  The network's
+ * widths must match the world's and its max_batch must cover the instances. */
+npx_status npx_sur_rollout(npx_sur* net, npx_world* w, float* s, int64_t lds, int64_t frame0,
+                           int32_t n_calls, float* x_work, int64_t ldx, float* y_work,
+                           int64_t ldy, float* tau_acc, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

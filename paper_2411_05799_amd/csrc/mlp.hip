@@ -676,6 +676,14 @@ npx_status check_io(const npx_sur* s, const float* x, int64_t ldx, int64_t batch
 
 }  // namespace
 
+namespace npx {
+void sur_dims(const npx_sur* s, int* n_in, int* n_out, int* max_batch) {
+  *n_in = s->n_in;
+  *n_out = s->n_out;
+  *max_batch = s->max_batch;
+}
+}  // namespace npx
+
 extern "C" {
 
 npx_status npx_sur_create(const npx_sur_desc* d, npx_sur** out) {

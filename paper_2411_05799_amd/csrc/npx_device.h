@@ -1,0 +1,49 @@
+// Device helpers shared by the step kernel and the surrogate's kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace npx {
+
+constexpr float kTwoPi = 6.28318530717958647692f;
+constexpr double kInvTwoPi = 0.15915494309189533577;
+
+// sin and cos of one angle. Quadrant reduction x = k pi/2 + r, |r| <= pi/4, with
+// pi/2 split in two parts and fused multiply-adds (Cody & Waite), then the
+// minimax polynomials of the Cephes library (S. L. Moshier) on the reduced
+// range. About 1 ulp for |x| < 1e4 rad; every angle of the step is far below.
+__device__ __forceinline__ void sin_cos(float x, float* s, float* c) {
+  const float k = rintf(x * 0.636619772367581343f);
+  float r = fmaf(-k, 1.57079637050628662109375f, x);
+  r = fmaf(-k, -4.37113900018624283e-8f, r);
+  const float r2 = r * r;
+  const float sr = fmaf(r * r2, fmaf(r2, fmaf(r2, -1.9515295891e-4f, 8.3321608736e-3f),
+                                     -1.6666654611e-1f), r);
+  const float cr = fmaf(r2 * r2, fmaf(r2, fmaf(r2, 2.443315711809948e-5f, -1.388731625493765e-3f),
+                                      4.166664568298827e-2f), fmaf(-0.5f, r2, 1.f));
+  const int q = (int)k;
+  const float ss = (q & 1) ? cr : sr;
+  const float cc = (q & 1) ? sr : cr;
+  *s = (q & 2) ? -ss : ss;
+  *c = ((q + 1) & 2) ? -cc : cc;
+}
+
+__device__ __forceinline__ void quat_to_mat(float w, float x, float y, float z, float R[9]) {
+  float xx = x * x, yy = y * y, zz = z * z;
+  float xy = x * y, xz = x * z, yz = y * z, wx = w * x, wy = w * y, wz = w * z;
+  R[0] = 1.f - 2.f * (yy + zz); R[1] = 2.f * (xy - wz);       R[2] = 2.f * (xz + wy);
+  R[3] = 2.f * (xy + wz);       R[4] = 1.f - 2.f * (xx + zz); R[5] = 2.f * (yz - wx);
+  R[6] = 2.f * (xz - wy);       R[7] = 2.f * (yz + wx);       R[8] = 1.f - 2.f * (xx + yy);
+}
+
+// Height-map look-up (Sec. III-A): floor(s (x - x0)) clamped onto the table;
+// fmaxf maps a NaN coordinate to cell 0.
+__device__ __forceinline__ float hf_lookup(const float* hf, int nx, int ny, float x0, float y0,
+                                           float s, float x, float y) {
+  float u = fminf(fmaxf((x - x0) * s, 0.f), (float)(nx - 1));
+  float w = fminf(fmaxf((y - y0) * s, 0.f), (float)(ny - 1));
+  int i = (int)u, j = (int)w;
+  return hf[j * nx + i];
+}
+
+}  // namespace npx

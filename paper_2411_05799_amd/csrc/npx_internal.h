@@ -74,4 +74,19 @@ hipError_t launch_zero(int* p, hipStream_t stream);
 // Max resident blocks of one wave per CU for a shape (occupancy query).
 int resident_blocks_per_cu(const Shape& s);
 
+// What the surrogate's kernels read of a world: the step arguments (tables,
+// state, height map, controller) and the points of each link grouped together.
+struct WorldView {
+  StepArgs a;
+  const int* lp_off;  // [total links + 1]
+  const int* lp_idx;  // [total points]
+  int n_max, l_max;
+};
+WorldView world_view(const npx_world* w);
+// Records the stream of work that touched the world's state (read_state waits on it).
+void note_stream(npx_world* w, hipStream_t s);
+
+// Shape of a surrogate network (defined with the network).
+void sur_dims(const npx_sur* s, int* n_in, int* n_out, int* max_batch);
+
 }  // namespace npx

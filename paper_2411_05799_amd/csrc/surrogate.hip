@@ -1,0 +1,446 @@
+// The simulator side of the learned surrogate: state rows, network inputs,
+// 10-frame state deltas, the rollout update and the quasi-static joint-torque
+// proxy of the controller-search fitness, for every instance of a world.
+//
+// State row of an instance (width 13 + 2 J, J = the world's joint stride):
+//   c (3, world CoG), Q (4, w x y z), v (3), omega (3), q (J), q_prev (J).
+// Network input (width 13 + 12 J + 64):
+//   [0, 13)          0, 0, c_z - h(c_x, c_y), Q, v, omega   (position made
+//                    translation-invariant: only the height above the ground)
+//   [13, 13+J)       q
+//   [13+J, 13+2J)    (q - q_prev) / dt
+//   [13+2J, 13+12J)  the clamped commanded angles the next 10 frames apply,
+//                    frame n+k for k = 0..9, k-major
+//   [13+12J, +64)    8 x 8 height-map patch at 0.08 m spacing, centred on the
+//                    CoG and turned with the torso heading, relative to h(c);
+//                    index 8 a + b with a along the heading, b to its left
+// Joints past an instance's own count read 0.  Frame n of the controller is
+// the frame about to be stepped (the world's step counter).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "npx.h"
+#include "npx_device.h"
+#include "npx_internal.h"
+
+using npx::fail;
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(NPX_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));            \
+  } while (0)
+
+namespace {
+
+using npx::LINK_F;
+using npx::WorldView;
+
+constexpr int HORIZON = 10;        // frames per surrogate call
+constexpr int PATCH = 8;           // patch edge (cells)
+constexpr float PATCH_STEP = 0.08f;  // m between patch samples
+constexpr float LOW_BAND = 0.002f;   // m: a point this close to the ground carries load
+
+__host__ __device__ inline int state_width(int J) { return 13 + 2 * J; }
+__host__ __device__ inline int feature_width(int J) { return 13 + 12 * J + PATCH * PATCH; }
+
+// Reads row r of instance i from a row-major state (s != null) or the world's
+// struct-of-arrays state.
+__device__ __forceinline__ float srow(const WorldView& v, const float* s, int64_t lds, int i, int r) {
+  return s ? s[(int64_t)i * lds + r] : v.a.st[(int64_t)r * v.a.n_inst + i];
+}
+
+// Commanded angle of joint j (link j + 1 of the morphology at lk_off) at frame
+// n, clamped to its limits: the step kernel's own phase and sine.
+__device__ __forceinline__ float command(const WorldView& v, int i, int lk_off, int j, int64_t n) {
+  const float* cp = v.a.ctrl + ((int64_t)i * v.a.j_max + j) * 3;
+  const float* lk = v.a.links + (int64_t)(lk_off + j + 1) * LINK_F;
+  const double t = (double)n * v.a.dt_d;
+  double ph = (double)cp[1] * t + (double)cp[2] * npx::kInvTwoPi;
+  ph -= floor(ph);
+  float sq, cq;
+  npx::sin_cos(npx::kTwoPi * (float)ph, &sq, &cq);
+  return fminf(fmaxf(cp[0] * sq, lk[6]), lk[7]);
+}
+
+__device__ __forceinline__ float hf(const WorldView& v, float x, float y) {
+  return npx::hf_lookup(v.a.hf, v.a.hf_nx, v.a.hf_ny, v.a.hf_x0, v.a.hf_y0, v.a.hf_s, x, y);
+}
+
+// ---- state rows --------------------------------------------------------------
+__global__ void rows_kernel(WorldView v, float* s, int64_t lds, int width) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int I = v.a.n_inst;
+  if (e >= (int64_t)I * width) return;
+  const int r = (int)(e / I), i = (int)(e % I);
+  s[(int64_t)i * lds + r] = v.a.st[(int64_t)r * I + i];
+}
+
+// y[i] = world state of i - s0[i]
+__global__ void delta_kernel(WorldView v, const float* s0, int64_t lds, float* y, int64_t ldy,
+                             int width) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int I = v.a.n_inst;
+  if (e >= (int64_t)I * width) return;
+  const int r = (int)(e / I), i = (int)(e % I);
+  y[(int64_t)i * ldy + r] = v.a.st[(int64_t)r * I + i] - s0[(int64_t)i * lds + r];
+}
+
+// ---- network inputs: one wave per instance, lanes over the features ---------
+__global__ __launch_bounds__(256) void features_kernel(WorldView v, const float* s, int64_t lds,
+                                                       int64_t frame, float* x, int64_t ldx) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= v.a.n_inst) return;
+  const int J = v.a.j_max;
+  const int4 mi = v.a.morph_info[v.a.inst_morph[i]];
+  const int Ji = mi.w - 1;
+  const int64_t n = frame >= 0 ? frame : (int64_t)v.a.step[i];
+  const float cx = srow(v, s, lds, i, 0), cy = srow(v, s, lds, i, 1);
+  const float h0 = hf(v, cx, cy);
+  const int nf = feature_width(J);
+  float* xr = x + (int64_t)i * ldx;
+  for (int f = lane; f < nf; f += 64) {
+    float val = 0.f;
+    if (f < 13) {
+      if (f == 2) val = srow(v, s, lds, i, 2) - h0;
+      else if (f >= 3) val = srow(v, s, lds, i, f);
+    } else if (f < 13 + J) {
+      const int j = f - 13;
+      if (j < Ji) val = srow(v, s, lds, i, 13 + j);
+    } else if (f < 13 + 2 * J) {
+      const int j = f - 13 - J;
+      if (j < Ji) val = (srow(v, s, lds, i, 13 + j) - srow(v, s, lds, i, 13 + J + j)) * v.a.inv_dt;
+    } else if (f < 13 + 12 * J) {
+      const int idx = f - 13 - 2 * J;
+      const int k = idx / J, j = idx % J;
+      if (j < Ji) val = command(v, i, mi.z, j, n + k);
+    } else {
+      const int idx = f - 13 - 12 * J;
+      const int a = idx / PATCH, b = idx % PATCH;
+      float R[9];
+      npx::quat_to_mat(srow(v, s, lds, i, 3), srow(v, s, lds, i, 4), srow(v, s, lds, i, 5),
+                       srow(v, s, lds, i, 6), R);
+      // heading: the torso x axis projected on the ground plane
+      const float hn = sqrtf(R[0] * R[0] + R[3] * R[3]);
+      const float ch = hn > 1e-6f ? R[0] / hn : 1.f, sh = hn > 1e-6f ? R[3] / hn : 0.f;
+      const float u = ((float)a - 0.5f * (PATCH - 1)) * PATCH_STEP;
+      const float w = ((float)b - 0.5f * (PATCH - 1)) * PATCH_STEP;
+      const float px = cx + (ch * u - sh * w), py = cy + (sh * u + ch * w);
+      val = hf(v, px, py) - h0;
+    }
+    xr[f] = val;
+  }
+}
+
+// ---- rollout update: one thread per instance ---------------------------------
+// s += dy on the body rows, Q renormalised; q and q_prev become what the step
+// sets after frames n .. n+9 with joints re-determined every frame.
+__global__ void advance_kernel(WorldView v, float* s, int64_t lds, const float* dy, int64_t lddy,
+                               int64_t frame) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= v.a.n_inst) return;
+  float* r = s + (int64_t)i * lds;
+  const float* d = dy + (int64_t)i * lddy;
+  for (int k = 0; k < 13; ++k) r[k] += d[k];
+  const float qn = sqrtf(r[3] * r[3] + r[4] * r[4] + r[5] * r[5] + r[6] * r[6]);
+  if (qn > 0.f)
+    for (int k = 3; k < 7; ++k) r[k] /= qn;
+  const int J = v.a.j_max;
+  const int4 mi = v.a.morph_info[v.a.inst_morph[i]];
+  const int Ji = mi.w - 1;
+  for (int j = 0; j < J; ++j) {
+    r[13 + j] = j < Ji ? command(v, i, mi.z, j, frame + HORIZON - 1) : 0.f;
+    r[13 + J + j] = j < Ji ? command(v, i, mi.z, j, frame + HORIZON - 2) : 0.f;
+  }
+}
+
+// ---- torque proxy: one wave per instance -------------------------------------
+__device__ __forceinline__ float wave_sum(float x) {
+  for (int m = 1; m < 64; m <<= 1) x += __shfl_xor(x, m);
+  return x;
+}
+
+// Quasi-static joint torque: every point carries its weight m_k g, and the
+// points within LOW_BAND of the ground share the robot's weight as an upward
+// load; joint j transmits the moment of the loads on all points distal to it
+// about its anchor, projected on its axis.  Writes (or adds) the mean of |tau_j|
+// over the instance's joints.
+__global__ __launch_bounds__(64) void torque_kernel(WorldView v, const float* s, int64_t lds,
+                                                    float* acc, int accumulate) {
+  __shared__ float T[64][12];  // link transform in the construction frame: R (row-major), t
+  __shared__ float S[64][6];   // per-link load sums: force, moment about the CoG
+  const int i = blockIdx.x;
+  const int l = threadIdx.x;
+  const int I = v.a.n_inst;
+  const int J = v.a.j_max;
+  const int4 mi = v.a.morph_info[v.a.inst_morph[i]];
+  const int N = mi.y, L = mi.w, pt0 = mi.x, lk0 = mi.z;
+  const bool own = l < L;
+  const float* lk = v.a.links + (int64_t)(lk0 + (own ? l : 0)) * LINK_F;
+
+  // joint rotation about the hinge: R_j = I + sin q [a]x + (1 - cos q) [a]x^2
+  float Rj[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, tj[3] = {0, 0, 0};
+  float an[3] = {0, 0, 0};
+  if (own && l > 0) {
+    const float o[3] = {lk[0], lk[1], lk[2]};
+    const float ax = lk[3], ay = lk[4], az = lk[5];
+    const float inv = 1.f / sqrtf(ax * ax + ay * ay + az * az);
+    an[0] = ax * inv;
+    an[1] = ay * inv;
+    an[2] = az * inv;
+    const float q = s ? s[(int64_t)i * lds + 13 + (l - 1)] : v.a.st[(int64_t)(13 + l - 1) * I + i];
+    float sq, cq;
+    npx::sin_cos(q, &sq, &cq);
+    const float C = 1.f - cq;
+    const float x = an[0], y = an[1], z = an[2];
+    Rj[0] = cq + C * x * x;     Rj[1] = C * x * y - sq * z; Rj[2] = C * x * z + sq * y;
+    Rj[3] = C * x * y + sq * z; Rj[4] = cq + C * y * y;     Rj[5] = C * y * z - sq * x;
+    Rj[6] = C * x * z - sq * y; Rj[7] = C * y * z + sq * x; Rj[8] = cq + C * z * z;
+    for (int r = 0; r < 3; ++r) tj[r] = o[r] - (Rj[3 * r] * o[0] + Rj[3 * r + 1] * o[1] + Rj[3 * r + 2] * o[2]);
+  }
+  const int depth = own ? v.a.link_depth[lk0 + l] : -1;
+  const int parent = own && l > 0 ? v.a.link_parent[lk0 + l] : 0;
+  for (int d = 0; d <= v.a.max_depth; ++d) {
+    if (depth == d) {
+      if (d == 0) {
+        for (int k = 0; k < 9; ++k) T[l][k] = Rj[k];
+        for (int k = 0; k < 3; ++k) T[l][9 + k] = 0.f;
+      } else {
+        float Rp[9], tp[3];
+        for (int k = 0; k < 9; ++k) Rp[k] = T[parent][k];
+        for (int k = 0; k < 3; ++k) tp[k] = T[parent][9 + k];
+        for (int r = 0; r < 3; ++r) {
+          for (int c = 0; c < 3; ++c)
+            T[l][3 * r + c] = Rp[3 * r] * Rj[c] + Rp[3 * r + 1] * Rj[3 + c] + Rp[3 * r + 2] * Rj[6 + c];
+          T[l][9 + r] = Rp[3 * r] * tj[0] + Rp[3 * r + 1] * tj[1] + Rp[3 * r + 2] * tj[2] + tp[r];
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // body CoG in the construction frame from the link masses and link CoGs
+  float gb[3] = {0, 0, 0};
+  {
+    float m = own ? lk[npx::LK_MASS] : 0.f;
+    float wc[3] = {0, 0, 0};
+    if (own) {
+      const float* cg = lk + npx::LK_COG;
+      for (int r = 0; r < 3; ++r)
+        wc[r] = m * (T[l][3 * r] * cg[0] + T[l][3 * r + 1] * cg[1] + T[l][3 * r + 2] * cg[2] + T[l][9 + r]);
+    }
+    const float M = v.a.morph_mass[v.a.inst_morph[i]];
+    for (int r = 0; r < 3; ++r) gb[r] = wave_sum(wc[r]) / M;
+  }
+  float c[3], R[9];
+  for (int r = 0; r < 3; ++r) c[r] = s ? s[(int64_t)i * lds + r] : v.a.st[(int64_t)r * I + i];
+  {
+    float q4[4];
+    for (int r = 0; r < 4; ++r) q4[r] = s ? s[(int64_t)i * lds + 3 + r] : v.a.st[(int64_t)(3 + r) * I + i];
+    npx::quat_to_mat(q4[0], q4[1], q4[2], q4[3], R);
+  }
+  // arm about the CoG (world axes) of a construction-frame point p on link k
+  auto arm = [&](const float4& p, int k, float out[3]) __attribute__((always_inline)) {
+    float y[3];
+    for (int r = 0; r < 3; ++r)
+      y[r] = T[k][3 * r] * p.x + T[k][3 * r + 1] * p.y + T[k][3 * r + 2] * p.z + T[k][9 + r] - gb[r];
+    for (int r = 0; r < 3; ++r) out[r] = R[3 * r] * y[0] + R[3 * r + 1] * y[1] + R[3 * r + 2] * y[2];
+  };
+  auto is_low = [&](const float a[3]) __attribute__((always_inline)) {
+    const float px = c[0] + a[0], py = c[1] + a[1], pz = c[2] + a[2];
+    return pz - hf(v, px, py) < LOW_BAND;
+  };
+
+  // points carrying load
+  float nlow = 0.f;
+  for (int k = l; k < N; k += 64) {
+    float a[3];
+    arm(v.a.pts[pt0 + k], v.a.pt_link[pt0 + k], a);  // link index local to the morphology
+    nlow += is_low(a) ? 1.f : 0.f;
+  }
+  nlow = wave_sum(nlow);
+  const float M = v.a.morph_mass[v.a.inst_morph[i]];
+  const float f_up = nlow > 0.f ? -M * v.a.gz / nlow : 0.f;
+
+  // per-link sums of the loads and their moments about the CoG
+  float F[3] = {0, 0, 0}, Mo[3] = {0, 0, 0};
+  if (own && l > 0) {
+    const int b = v.lp_off[lk0 + l], e = v.lp_off[lk0 + l + 1];
+    for (int idx = b; idx < e; ++idx) {
+      const int kk = v.lp_idx[idx];
+      const float4 p = v.a.pts[kk];
+      float a[3];
+      arm(p, l, a);
+      const float fk[3] = {p.w * v.a.gx, p.w * v.a.gy, p.w * v.a.gz + (is_low(a) ? f_up : 0.f)};
+      for (int r = 0; r < 3; ++r) F[r] += fk[r];
+      Mo[0] += a[1] * fk[2] - a[2] * fk[1];
+      Mo[1] += a[2] * fk[0] - a[0] * fk[2];
+      Mo[2] += a[0] * fk[1] - a[1] * fk[0];
+    }
+  }
+  if (own) {
+    for (int r = 0; r < 3; ++r) {
+      S[l][r] = F[r];
+      S[l][3 + r] = Mo[r];
+    }
+  }
+  __syncthreads();
+  // subtree sums, children before parents (links are stored parents first)
+  if (l == 0)
+    for (int k = L - 1; k >= 1; --k) {
+      const int p = v.a.link_parent[lk0 + k];
+      if (p >= 1)
+        for (int r = 0; r < 6; ++r) S[p][r] += S[k][r];
+    }
+  __syncthreads();
+  float tau = 0.f;
+  if (own && l > 0) {
+    // the hinge anchor moves with the link (it is fixed by the joint rotation)
+    const float4 o = make_float4(lk[0], lk[1], lk[2], 0.f);
+    float ao[3], aw[3], ab[3];
+    arm(o, l, ao);
+    for (int r = 0; r < 3; ++r) ab[r] = T[l][3 * r] * an[0] + T[l][3 * r + 1] * an[1] + T[l][3 * r + 2] * an[2];
+    for (int r = 0; r < 3; ++r) aw[r] = R[3 * r] * ab[0] + R[3 * r + 1] * ab[1] + R[3 * r + 2] * ab[2];
+    const float* Sl = S[l];
+    const float m0 = Sl[3] - (ao[1] * Sl[2] - ao[2] * Sl[1]);
+    const float m1 = Sl[4] - (ao[2] * Sl[0] - ao[0] * Sl[2]);
+    const float m2 = Sl[5] - (ao[0] * Sl[1] - ao[1] * Sl[0]);
+    tau = fabsf(aw[0] * m0 + aw[1] * m1 + aw[2] * m2);
+  }
+  tau = wave_sum(tau);
+  if (l == 0) {
+    const float mean = L > 1 ? tau / (float)(L - 1) : 0.f;
+    acc[i] = accumulate ? acc[i] + mean : mean;
+  }
+  (void)J;
+}
+
+npx_status check_world(const npx_world* w) {
+  if (!w) return fail(NPX_EINVAL, "null world");
+  return NPX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+npx_status npx_sur_widths(const npx_world* w, int32_t* state_w, int32_t* feature_w) {
+  npx_status r = check_world(w);
+  if (r != NPX_OK) return r;
+  const WorldView v = npx::world_view(w);
+  if (state_w) *state_w = state_width(v.a.j_max);
+  if (feature_w) *feature_w = feature_width(v.a.j_max);
+  return NPX_OK;
+}
+
+npx_status npx_world_rows(npx_world* w, float* s, int64_t lds, void* stream) {
+  npx_status r = check_world(w);
+  if (r != NPX_OK) return r;
+  const WorldView v = npx::world_view(w);
+  const int width = state_width(v.a.j_max);
+  if (!s || lds < width) return fail(NPX_EINVAL, "bad state buffer or stride");
+  const int64_t n = (int64_t)v.a.n_inst * width;
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(rows_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v, s, lds,
+                     width);
+  HIP_TRY(hipGetLastError());
+  npx::note_stream(w, st);
+  return NPX_OK;
+}
+
+npx_status npx_sur_features(npx_world* w, const float* s, int64_t lds, int64_t frame, float* x,
+                            int64_t ldx, void* stream) {
+  npx_status r = check_world(w);
+  if (r != NPX_OK) return r;
+  const WorldView v = npx::world_view(w);
+  if (!x || ldx < feature_width(v.a.j_max)) return fail(NPX_EINVAL, "bad input buffer or stride");
+  if (s && lds < state_width(v.a.j_max)) return fail(NPX_EINVAL, "state stride too small");
+  if (s && frame < 0) return fail(NPX_EINVAL, "state rows need a frame >= 0");
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(features_kernel, dim3((unsigned)((v.a.n_inst + 3) / 4)), dim3(256), 0, st, v,
+                     s, lds, s ? frame : (int64_t)-1, x, ldx);
+  HIP_TRY(hipGetLastError());
+  npx::note_stream(w, st);
+  return NPX_OK;
+}
+
+npx_status npx_sur_delta(npx_world* w, const float* s0, int64_t lds, float* y, int64_t ldy,
+                         void* stream) {
+  npx_status r = check_world(w);
+  if (r != NPX_OK) return r;
+  const WorldView v = npx::world_view(w);
+  const int width = state_width(v.a.j_max);
+  if (!s0 || !y || lds < width || ldy < width) return fail(NPX_EINVAL, "bad buffers or strides");
+  const int64_t n = (int64_t)v.a.n_inst * width;
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(delta_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v, s0, lds,
+                     y, ldy, width);
+  HIP_TRY(hipGetLastError());
+  npx::note_stream(w, st);
+  return NPX_OK;
+}
+
+npx_status npx_sur_advance(npx_world* w, float* s, int64_t lds, const float* dy, int64_t lddy,
+                           int64_t frame, void* stream) {
+  npx_status r = check_world(w);
+  if (r != NPX_OK) return r;
+  const WorldView v = npx::world_view(w);
+  const int width = state_width(v.a.j_max);
+  if (!s || !dy || lds < width || lddy < width || frame < 0)
+    return fail(NPX_EINVAL, "bad buffers, strides or frame");
+  if (v.a.K != 1) return fail(NPX_EUNSUPPORTED, "the rollout update assumes joints set every frame");
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(advance_kernel, dim3((unsigned)((v.a.n_inst + 255) / 256)), dim3(256), 0, st,
+                     v, s, lds, dy, lddy, frame);
+  HIP_TRY(hipGetLastError());
+  npx::note_stream(w, st);
+  return NPX_OK;
+}
+
+npx_status npx_sur_torque(npx_world* w, const float* s, int64_t lds, float* acc, int accumulate,
+                          void* stream) {
+  npx_status r = check_world(w);
+  if (r != NPX_OK) return r;
+  const WorldView v = npx::world_view(w);
+  if (!acc) return fail(NPX_EINVAL, "null output");
+  if (s && lds < state_width(v.a.j_max)) return fail(NPX_EINVAL, "state stride too small");
+  if (v.l_max > 64) return fail(NPX_EUNSUPPORTED, "more than 64 links");
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(torque_kernel, dim3((unsigned)v.a.n_inst), dim3(64), 0, st, v, s, lds, acc,
+                     accumulate ? 1 : 0);
+  HIP_TRY(hipGetLastError());
+  npx::note_stream(w, st);
+  return NPX_OK;
+}
+
+npx_status npx_sur_rollout(npx_sur* net, npx_world* w, float* s, int64_t lds, int64_t frame0,
+                           int32_t n_calls, float* x_work, int64_t ldx, float* y_work,
+                           int64_t ldy, float* tau_acc, void* stream) {
+  npx_status r = check_world(w);
+  if (r != NPX_OK) return r;
+  if (!net) return fail(NPX_EINVAL, "null surrogate");
+  const WorldView v = npx::world_view(w);
+  int n_in = 0, n_out = 0, max_batch = 0;
+  npx::sur_dims(net, &n_in, &n_out, &max_batch);
+  if (n_in != feature_width(v.a.j_max) || n_out != state_width(v.a.j_max))
+    return fail(NPX_EINVAL, "network shape %d -> %d does not fit this world (%d -> %d)", n_in,
+                n_out, feature_width(v.a.j_max), state_width(v.a.j_max));
+  if (max_batch < v.a.n_inst)
+    return fail(NPX_EINVAL, "network batch limit %d < %d instances", max_batch, v.a.n_inst);
+  if (n_calls < 0 || frame0 < 0) return fail(NPX_EINVAL, "negative call count or frame");
+  if (!y_work || ldy < n_out) return fail(NPX_EINVAL, "bad output workspace");
+  for (int c = 0; c < n_calls; ++c) {
+    const int64_t frame = frame0 + (int64_t)c * HORIZON;
+    if ((r = npx_sur_features(w, s, lds, frame, x_work, ldx, stream)) != NPX_OK) return r;
+    if ((r = npx_sur_forward(net, x_work, ldx, nullptr, v.a.n_inst, y_work, ldy, stream)) != NPX_OK)
+      return r;
+    if ((r = npx_sur_advance(w, s, lds, y_work, ldy, frame, stream)) != NPX_OK) return r;
+    if (tau_acc && (r = npx_sur_torque(w, s, lds, tau_acc, 1, stream)) != NPX_OK) return r;
+  }
+  return NPX_OK;
+}
+
+}  // extern "C"

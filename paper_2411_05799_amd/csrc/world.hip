@@ -77,6 +77,8 @@ struct npx_world {
   float* hf = nullptr;
   int* order = nullptr;
   int* queue = nullptr;
+  int* lp_off = nullptr;   // [total links + 1] point range of each link in lp_idx
+  int* lp_idx = nullptr;   // [total points] point indices grouped by link
 
   npx::StepArgs args{};
   npx_launch launch{64, 0, 100, 1, 8};
@@ -225,6 +227,23 @@ npx_status check_tables(const npx_morph_tables& m, int idx) {
 
 }  // namespace
 
+namespace npx {
+WorldView world_view(const npx_world* w) {
+  WorldView v;
+  v.a = w->args;
+  v.lp_off = w->lp_off;
+  v.lp_idx = w->lp_idx;
+  v.n_max = w->n_max;
+  v.l_max = w->l_max;
+  return v;
+}
+
+void note_stream(npx_world* w, hipStream_t s) {
+  w->last_stream = s;
+  w->has_last_stream = true;
+}
+}  // namespace npx
+
 extern "C" {
 
 const char* npx_last_error(void) { return g_err.c_str(); }
@@ -321,6 +340,17 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
     }
   }
   w->j_max = std::max(1, w->l_max - 1);
+  // points grouped by link (stable), for per-link sums outside the step kernel
+  std::vector<int> lpo(1, 0), lpi;
+  for (int mi = 0; mi < d->n_morphs; ++mi) {
+    const npx_morph_tables& m = d->morphs[mi];
+    const int p0 = info[mi].x;
+    for (int l = 0; l < m.n_links; ++l) {
+      for (int k = 0; k < m.n_points; ++k)
+        if (m.pt_link[k] == l) lpi.push_back(p0 + k);
+      lpo.push_back((int)lpi.size());
+    }
+  }
   if (!shape_for(w, 64, &w->shape)) {
     delete w;
     return fail(NPX_EUNSUPPORTED, "no kernel shape for %d points / %d links", w->n_max, w->l_max);
@@ -351,6 +381,8 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   ALLOC(w->hf, (size_t)d->hf_nx * d->hf_ny);
   ALLOC(w->order, I);
   ALLOC(w->queue, 1);
+  ALLOC(w->lp_off, lpo.size());
+  ALLOC(w->lp_idx, lpi.size());
 #undef ALLOC
 
   auto h2d = [&](void* dst, const void* src, size_t bytes) {
@@ -367,6 +399,8 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   H2D(w->links, lk.data(), lk.size() * sizeof(float));
   H2D(w->link_parent, par.data(), par.size() * sizeof(int));
   H2D(w->link_depth, dep.data(), dep.size() * sizeof(int));
+  H2D(w->lp_off, lpo.data(), lpo.size() * sizeof(int));
+  H2D(w->lp_idx, lpi.data(), lpi.size() * sizeof(int));
   H2D(w->hf, d->hf_heights, (size_t)d->hf_nx * d->hf_ny * sizeof(float));
   std::vector<int> ord = task_order(w);
   H2D(w->order, ord.data(), I * sizeof(int));
@@ -461,7 +495,8 @@ void npx_destroy_world(npx_world* w) {
   if (w->capture_stream) (void)hipStreamDestroy(w->capture_stream);
   void* bufs[] = {w->st, w->step, w->flags, w->tele, w->inst_morph_d, w->morph_info,
                   w->morph_mass, w->pts, w->pt_link, w->links, w->link_parent,
-                  w->link_depth, w->ctrl, w->hf, w->order, w->queue};
+                  w->link_depth, w->ctrl, w->hf, w->order, w->queue, w->lp_off,
+                  w->lp_idx};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete w;

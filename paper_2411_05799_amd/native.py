@@ -138,6 +138,16 @@ def lib():
         L.npx_sur_grad.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp, vp, vp]
         L.npx_sur_train_step.argtypes = [vp, vp, i64, vp, i64, vp, i64, d, vp, vp]
         L.npx_sur_norm_stats.argtypes = [vp, i64, i64, C.c_int32, vp, vp, vp]
+        L.npx_sur_widths.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.npx_world_rows.argtypes = [vp, vp, i64, vp]
+        L.npx_sur_features.argtypes = [vp, vp, i64, i64, vp, i64, vp]
+        L.npx_sur_delta.argtypes = [vp, vp, i64, vp, i64, vp]
+        L.npx_sur_advance.argtypes = [vp, vp, i64, vp, i64, i64, vp]
+        L.npx_sur_torque.argtypes = [vp, vp, i64, vp, C.c_int, vp]
+        L.npx_sur_rollout.argtypes = [vp, vp, vp, i64, i64, C.c_int32, vp, i64, vp, i64, vp, vp]
+        for name in ("npx_sur_widths", "npx_world_rows", "npx_sur_features", "npx_sur_delta",
+                     "npx_sur_advance", "npx_sur_torque", "npx_sur_rollout"):
+            getattr(L, name).restype = C.c_int
         for name in ("npx_sur_create", "npx_sur_param_count", "npx_sur_get_params",
                      "npx_sur_set_params", "npx_sur_set_norm", "npx_sur_set_adam",
                      "npx_sur_forward", "npx_sur_grad", "npx_sur_train_step",
@@ -326,6 +336,47 @@ class World:
             with open(cache, "w") as f:
                 json.dump(known, f, indent=1, sort_keys=True)
         return rec
+
+    # -- the simulator side of the surrogate (device tensors) --------------------
+    def sur_widths(self):
+        a, b = C.c_int32(), C.c_int32()
+        check(lib().npx_sur_widths(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def rows(self, out, stream=None):
+        """State rows [I, >= 13 + 2 J] of every instance into a device tensor."""
+        check(lib().npx_world_rows(self.h, _ptr(out), out.stride(0),
+                                   C.c_void_p(_stream_handle(stream))))
+        return out
+
+    def sur_features(self, x, s=None, frame=-1, stream=None):
+        """Network inputs into x [I, >= width]: from rows s at `frame`, or from
+        the world's own state (s None)."""
+        check(lib().npx_sur_features(self.h, _ptr(s), 0 if s is None else s.stride(0), int(frame),
+                                     _ptr(x), x.stride(0), C.c_void_p(_stream_handle(stream))))
+        return x
+
+    def sur_delta(self, s0, y, stream=None):
+        check(lib().npx_sur_delta(self.h, _ptr(s0), s0.stride(0), _ptr(y), y.stride(0),
+                                  C.c_void_p(_stream_handle(stream))))
+        return y
+
+    def sur_advance(self, s, dy, frame, stream=None):
+        check(lib().npx_sur_advance(self.h, _ptr(s), s.stride(0), _ptr(dy), dy.stride(0),
+                                    int(frame), C.c_void_p(_stream_handle(stream))))
+        return s
+
+    def sur_torque(self, acc, s=None, accumulate=False, stream=None):
+        check(lib().npx_sur_torque(self.h, _ptr(s), 0 if s is None else s.stride(0), _ptr(acc),
+                                   1 if accumulate else 0, C.c_void_p(_stream_handle(stream))))
+        return acc
+
+    def sur_rollout(self, net, s, frame0, n_calls, x_work, y_work, tau_acc=None, stream=None):
+        check(lib().npx_sur_rollout(net.h, self.h, _ptr(s), s.stride(0), int(frame0),
+                                    int(n_calls), _ptr(x_work), x_work.stride(0), _ptr(y_work),
+                                    y_work.stride(0), _ptr(tau_acc),
+                                    C.c_void_p(_stream_handle(stream))))
+        return s
 
     def flops_per_step(self, i=None):
         """Algorithmic FP32 operations of one frame (instance i, or summed over all)."""
