@@ -305,8 +305,12 @@ npx_status npx_sur_norm_stats(const float* x, int64_t ldx, int64_t rows, int32_t
  * State row of an instance, width 13 + 2 J (J = the world's joint stride, the
  * largest joint count over its morphologies): c (3, world CoG), Q (4, w x y z),
  * v (3), omega (3), q (J), q_prev (J); joints past an instance's own count are
- * 0.  Network input, width 13 + 12 J + 64:
- *   [0, 13)          0, 0, c_z - h(c_x, c_y), Q, v, omega
+ * 0.  The heading frame of a state: psi is the heading of the torso x axis on
+ * the ground plane; vectors are turned by -psi about z and orientations are
+ * left-multiplied by the yaw quaternion of -psi, negated if that leaves w < 0
+ * (the sign chosen for the state's own orientation also applies to changes of
+ * it).  Network input, width 13 + 12 J + 64:
+ *   [0, 13)          0, 0, c_z - h(c_x, c_y), then Q, v, omega in the heading frame
  *   [13, 13 + J)     q;   [13 + J, 13 + 2 J)   (q - q_prev) / dt
  *   [13 + 2 J, 13 + 12 J)   the clamped commanded angles the next 10 frames
  *                    apply, frames n .. n + 9, frame-major
@@ -325,10 +329,12 @@ npx_status npx_world_rows(npx_world* w, float* s, int64_t lds, void* stream);
  * NULL), with the world's controllers and height map. */
 npx_status npx_sur_features(npx_world* w, const float* s, int64_t lds, int64_t frame, float* x,
                             int64_t ldx, void* stream);
-/* y[i] = (world state row of i) - s0[i]: the training target after stepping. */
+/* y[i] = (world state row of i) - s0[i], the body entries turned into the heading
+ * frame of s0[i]: the training target after stepping.  y may alias s0. */
 npx_status npx_sur_delta(npx_world* w, const float* s0, int64_t lds, float* y, int64_t ldy,
                          void* stream);
-/* Rollout update of rows s at frame n: the body rows gain dy (Q renormalised),
+/* Rollout update of rows s at frame n: the body rows gain dy turned back from the
+ * heading frame of s (Q renormalised),
  * q and q_prev become the clamped commands of frames n + 9 and n + 8 (what the
  * step sets).  Needs joint_interval == 1 (NPX_EUNSUPPORTED otherwise). */
 npx_status npx_sur_advance(npx_world* w, float* s, int64_t lds, const float* dy, int64_t lddy,

@@ -7,14 +7,20 @@ library never does.
 
 Definitions (the same ones the library documents):
   state row (width 13 + 2 J): c, Q (w x y z), v, omega, q [J], q_prev [J]
+  heading frame of a state: psi = heading of the torso x axis on the ground
+    plane; vectors turned by -psi about z; orientations left-multiplied by the
+    yaw quaternion of -psi, negated if that leaves w < 0 (the sign chosen for
+    the state's own orientation is used for its changes too)
   input (width 13 + 12 J + 64):
-    0, 0, c_z - h(c_xy), Q, v, omega | q | (q - q_prev)/dt |
+    0, 0, c_z - h(c_xy), then Q, v, omega in the heading frame | q | (q - q_prev)/dt |
     clamped commands of frames n .. n+9 (frame-major) |
     8 x 8 patch at 0.08 m, centred on the CoG, turned with the heading (torso x
     axis on the ground plane), minus h(c_xy); index 8 a + b, a along the
     heading, b to its left, offsets (a - 3.5) 0.08 and (b - 3.5) 0.08
-  rollout update at frame n: body rows + delta, Q normalised, q = command(n+9),
-    q_prev = command(n+8)
+  target: the state change over 10 frames, body rows in the heading frame of
+    the first state
+  rollout update at frame n: body rows + the delta turned back from the heading
+    frame of the current state, Q normalised, q = command(n+9), q_prev = command(n+8)
   torque proxy: loads m_k g on every point plus an upward share M |g| / n_low on
     the n_low points less than 0.002 m above the height map; tau_j = axis_j .
     sum over points distal to joint j of (P_k - anchor_j) x load_k; the mean of
@@ -40,6 +46,43 @@ def quat_mat(Q):
     return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
                      [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
                      [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def quat_mul(a, b):
+    aw, av = a[0], np.asarray(a[1:], np.float64)
+    bw, bv = b[0], np.asarray(b[1:], np.float64)
+    return np.concatenate([[aw * bw - av @ bv], aw * bv + bw * av + np.cross(av, bv)])
+
+
+class HeadingFrame:
+    """The heading frame of a state with orientation Q."""
+
+    def __init__(self, Q):
+        R = quat_mat(Q)
+        hn = math.hypot(R[0, 0], R[1, 0])
+        self.psi = math.atan2(R[1, 0], R[0, 0]) if hn > 1e-6 else 0.0
+        c, s = math.cos(self.psi), math.sin(self.psi)
+        self.Rz = np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+        self.q_minus = np.array([math.cos(-self.psi / 2), 0.0, 0.0, math.sin(-self.psi / 2)])
+        self.q_plus = np.array([math.cos(self.psi / 2), 0.0, 0.0, math.sin(self.psi / 2)])
+        self.sign = 1.0 if quat_mul(self.q_minus, Q)[0] >= 0 else -1.0
+
+    def to_frame(self, b):
+        """13 body entries (c, Q, v, omega or their changes) world -> heading frame."""
+        b = np.asarray(b, np.float64)
+        out = np.empty(13)
+        for k in (0, 7, 10):
+            out[k:k + 3] = self.Rz.T @ b[k:k + 3]
+        out[3:7] = self.sign * quat_mul(self.q_minus, b[3:7])
+        return out
+
+    def from_frame(self, b):
+        b = np.asarray(b, np.float64)
+        out = np.empty(13)
+        for k in (0, 7, 10):
+            out[k:k + 3] = self.Rz @ b[k:k + 3]
+        out[3:7] = self.sign * quat_mul(self.q_plus, b[3:7])
+        return out
 
 
 def rodrigues(axis, angle):
@@ -108,14 +151,10 @@ class SurrogateOracle:
     def near_edge(self, x, y, tol=1e-3):
         return edge_distance(self.w.hf, x, y) < tol
 
-    def heading(self, Q):
-        R = quat_mat(Q)
-        hn = math.hypot(R[0, 0], R[1, 0])
-        return (R[0, 0] / hn, R[1, 0] / hn) if hn > 1e-6 else (1.0, 0.0)
-
     def patch_points(self, row):
         c = row[:3]
-        ch, sh = self.heading(row[3:7])
+        psi = HeadingFrame(row[3:7]).psi
+        ch, sh = math.cos(psi), math.sin(psi)
         pts = []
         for a in range(PATCH):
             for b in range(PATCH):
@@ -131,7 +170,7 @@ class SurrogateOracle:
         x = np.zeros(13 + 12 * J + PATCH * PATCH)
         h0 = self.h(row[0], row[1])
         x[2] = row[2] - h0
-        x[3:13] = row[3:13]
+        x[3:13] = HeadingFrame(row[3:7]).to_frame(row[:13])[3:13]
         x[13:13 + J] = row[13:13 + J]
         x[13 + J:13 + 2 * J] = (row[13:13 + J] - row[13 + J:13 + 2 * J]) / self.dt
         for k in range(HORIZON):
@@ -142,10 +181,16 @@ class SurrogateOracle:
             x[base + idx] = self.h(px, py) - h0
         return x
 
+    def delta(self, row0, row1):
+        """Training target: row1 - row0, the body entries in the heading frame of row0."""
+        d = np.asarray(row1, np.float64) - np.asarray(row0, np.float64)
+        d[:13] = HeadingFrame(row0[3:7]).to_frame(d[:13])
+        return d
+
     def advance(self, i, row, dy, frame):
         J, m, ctrl = self.J, self.morph(i), self.w.ctrl[i]
         out = np.array(row, dtype=np.float64)
-        out[:13] += dy[:13]
+        out[:13] += HeadingFrame(row[3:7]).from_frame(dy[:13])
         out[3:7] /= np.linalg.norm(out[3:7])
         out[13:] = 0.0
         for j in range(m.n_links - 1):

@@ -80,6 +80,7 @@ struct WorldView {
   StepArgs a;
   const int* lp_off;  // [total links + 1]
   const int* lp_idx;  // [total points]
+  const unsigned long long* sub_mask;  // [total links] bit k: link k is in the subtree
   int n_max, l_max;
 };
 WorldView world_view(const npx_world* w);

@@ -4,8 +4,13 @@
 //
 // State row of an instance (width 13 + 2 J, J = the world's joint stride):
 //   c (3, world CoG), Q (4, w x y z), v (3), omega (3), q (J), q_prev (J).
+// Heading frame: psi is the heading of the torso x axis on the ground plane;
+// vectors are turned by -psi about z, and the orientation is left-multiplied by
+// the yaw quaternion of -psi, its sign chosen so that the w component is >= 0.
+// Inputs and targets are expressed in the heading frame at the current frame,
+// which makes the map independent of where the robot faces.
 // Network input (width 13 + 12 J + 64):
-//   [0, 13)          0, 0, c_z - h(c_x, c_y), Q, v, omega   (position made
+//   [0, 13)          0, 0, c_z - h(c_x, c_y), Q_h, v_h, omega_h  (position made
 //                    translation-invariant: only the height above the ground)
 //   [13, 13+J)       q
 //   [13+J, 13+2J)    (q - q_prev) / dt
@@ -69,6 +74,67 @@ __device__ __forceinline__ float hf(const WorldView& v, float x, float y) {
   return npx::hf_lookup(v.a.hf, v.a.hf_nx, v.a.hf_ny, v.a.hf_x0, v.a.hf_y0, v.a.hf_s, x, y);
 }
 
+// ---- heading frame -------------------------------------------------------------
+struct Heading {
+  float ch, sh;  // cos, sin of the heading
+  float hw, hz;  // yaw quaternion of -psi: (hw, 0, 0, hz)
+  float sgn;     // +-1: makes the w component of the turned orientation >= 0
+};
+
+__device__ __forceinline__ Heading heading_of(float qw, float qx, float qy, float qz) {
+  float R[9];
+  npx::quat_to_mat(qw, qx, qy, qz, R);
+  const float hn = sqrtf(R[0] * R[0] + R[3] * R[3]);
+  Heading h;
+  h.ch = hn > 1e-6f ? R[0] / hn : 1.f;
+  h.sh = hn > 1e-6f ? R[3] / hn : 0.f;
+  const float c2 = sqrtf(fmaxf(0.f, 0.5f * (1.f + h.ch)));
+  const float s2 = copysignf(sqrtf(fmaxf(0.f, 0.5f * (1.f - h.ch))), h.sh);
+  h.hw = c2;
+  h.hz = -s2;
+  h.sgn = h.hw * qw - h.hz * qz >= 0.f ? 1.f : -1.f;
+  return h;
+}
+
+// world -> heading frame of a vector's x, y (z is unchanged)
+__device__ __forceinline__ void to_heading(const Heading& h, float x, float y, float* ox, float* oy) {
+  *ox = h.ch * x + h.sh * y;
+  *oy = -h.sh * x + h.ch * y;
+}
+__device__ __forceinline__ void from_heading(const Heading& h, float x, float y, float* ox, float* oy) {
+  *ox = h.ch * x - h.sh * y;
+  *oy = h.sh * x + h.ch * y;
+}
+// sgn * q_z(-psi) (x) b  and its inverse  sgn * q_z(psi) (x) b
+__device__ __forceinline__ void quat_to_heading(const Heading& h, const float b[4], float o[4]) {
+  o[0] = h.sgn * (h.hw * b[0] - h.hz * b[3]);
+  o[1] = h.sgn * (h.hw * b[1] - h.hz * b[2]);
+  o[2] = h.sgn * (h.hw * b[2] + h.hz * b[1]);
+  o[3] = h.sgn * (h.hw * b[3] + h.hz * b[0]);
+}
+__device__ __forceinline__ void quat_from_heading(const Heading& h, const float b[4], float o[4]) {
+  o[0] = h.sgn * (h.hw * b[0] + h.hz * b[3]);
+  o[1] = h.sgn * (h.hw * b[1] + h.hz * b[2]);
+  o[2] = h.sgn * (h.hw * b[2] - h.hz * b[1]);
+  o[3] = h.sgn * (h.hw * b[3] - h.hz * b[0]);
+}
+
+// The 13 body entries of a world-frame vector (a state or a state change)
+// expressed in the heading frame h, or back (inverse = true).
+template <bool INVERSE>
+__device__ __forceinline__ void body_frame(const Heading& h, const float in[13], float out[13]) {
+  auto vec = [&](int k) __attribute__((always_inline)) {
+    if (INVERSE) from_heading(h, in[k], in[k + 1], &out[k], &out[k + 1]);
+    else to_heading(h, in[k], in[k + 1], &out[k], &out[k + 1]);
+    out[k + 2] = in[k + 2];
+  };
+  vec(0);
+  if (INVERSE) quat_from_heading(h, in + 3, out + 3);
+  else quat_to_heading(h, in + 3, out + 3);
+  vec(7);
+  vec(10);
+}
+
 // ---- state rows --------------------------------------------------------------
 __global__ void rows_kernel(WorldView v, float* s, int64_t lds, int width) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -78,14 +144,29 @@ __global__ void rows_kernel(WorldView v, float* s, int64_t lds, int width) {
   s[(int64_t)i * lds + r] = v.a.st[(int64_t)r * I + i];
 }
 
-// y[i] = world state of i - s0[i]
-__global__ void delta_kernel(WorldView v, const float* s0, int64_t lds, float* y, int64_t ldy,
-                             int width) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// y[i] = (world state of i) - s0[i], the body entries in the heading frame of
+// s0[i].  One wave per instance, lanes over the columns.
+__global__ __launch_bounds__(256) void delta_kernel(WorldView v, const float* s0, int64_t lds,
+                                                    float* y, int64_t ldy, int width) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int I = v.a.n_inst;
-  if (e >= (int64_t)I * width) return;
-  const int r = (int)(e / I), i = (int)(e % I);
-  y[(int64_t)i * ldy + r] = v.a.st[(int64_t)r * I + i] - s0[(int64_t)i * lds + r];
+  if (i >= I) return;
+  const float* r0 = s0 + (int64_t)i * lds;
+  float d[13], b[13];
+  for (int k = 0; k < 13; ++k) d[k] = v.a.st[(int64_t)k * I + i] - r0[k];
+  const Heading h = heading_of(r0[3], r0[4], r0[5], r0[6]);
+  body_frame<false>(h, d, b);
+  for (int c = lane; c < width; c += 64) {
+    float val = 0.f;
+    if (c < 13) {
+#pragma unroll
+      for (int k = 0; k < 13; ++k) val = c == k ? b[k] : val;
+    } else {
+      val = v.a.st[(int64_t)c * I + i] - r0[c];
+    }
+    y[(int64_t)i * ldy + c] = val;
+  }
 }
 
 // ---- network inputs: one wave per instance, lanes over the features ---------
@@ -105,8 +186,15 @@ __global__ __launch_bounds__(256) void features_kernel(WorldView v, const float*
   for (int f = lane; f < nf; f += 64) {
     float val = 0.f;
     if (f < 13) {
-      if (f == 2) val = srow(v, s, lds, i, 2) - h0;
-      else if (f >= 3) val = srow(v, s, lds, i, f);
+      if (f == 2) {
+        val = srow(v, s, lds, i, 2) - h0;
+      } else if (f >= 3) {
+        float in[13], out[13];
+        for (int k = 0; k < 13; ++k) in[k] = srow(v, s, lds, i, k);
+        body_frame<false>(heading_of(in[3], in[4], in[5], in[6]), in, out);
+#pragma unroll
+        for (int k = 3; k < 13; ++k) val = f == k ? out[k] : val;
+      }
     } else if (f < 13 + J) {
       const int j = f - 13;
       if (j < Ji) val = srow(v, s, lds, i, 13 + j);
@@ -120,12 +208,9 @@ __global__ __launch_bounds__(256) void features_kernel(WorldView v, const float*
     } else {
       const int idx = f - 13 - 12 * J;
       const int a = idx / PATCH, b = idx % PATCH;
-      float R[9];
-      npx::quat_to_mat(srow(v, s, lds, i, 3), srow(v, s, lds, i, 4), srow(v, s, lds, i, 5),
-                       srow(v, s, lds, i, 6), R);
-      // heading: the torso x axis projected on the ground plane
-      const float hn = sqrtf(R[0] * R[0] + R[3] * R[3]);
-      const float ch = hn > 1e-6f ? R[0] / hn : 1.f, sh = hn > 1e-6f ? R[3] / hn : 0.f;
+      const Heading hd = heading_of(srow(v, s, lds, i, 3), srow(v, s, lds, i, 4),
+                                    srow(v, s, lds, i, 5), srow(v, s, lds, i, 6));
+      const float ch = hd.ch, sh = hd.sh;
       const float u = ((float)a - 0.5f * (PATCH - 1)) * PATCH_STEP;
       const float w = ((float)b - 0.5f * (PATCH - 1)) * PATCH_STEP;
       const float px = cx + (ch * u - sh * w), py = cy + (sh * u + ch * w);
@@ -135,25 +220,44 @@ __global__ __launch_bounds__(256) void features_kernel(WorldView v, const float*
   }
 }
 
-// ---- rollout update: one thread per instance ---------------------------------
-// s += dy on the body rows, Q renormalised; q and q_prev become what the step
-// sets after frames n .. n+9 with joints re-determined every frame.
-__global__ void advance_kernel(WorldView v, float* s, int64_t lds, const float* dy, int64_t lddy,
-                               int64_t frame) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// ---- rollout update: one wave per instance, lanes over the columns ----------
+// The body rows gain dy turned back from the heading frame of s (Q renormalised);
+// q and q_prev become what the step sets after frames n .. n+9 with joints
+// re-determined every frame.
+__global__ __launch_bounds__(256) void advance_kernel(WorldView v, float* s, int64_t lds,
+                                                      const float* dy, int64_t lddy,
+                                                      int64_t frame) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= v.a.n_inst) return;
   float* r = s + (int64_t)i * lds;
   const float* d = dy + (int64_t)i * lddy;
-  for (int k = 0; k < 13; ++k) r[k] += d[k];
-  const float qn = sqrtf(r[3] * r[3] + r[4] * r[4] + r[5] * r[5] + r[6] * r[6]);
+  float cur[13], dh[13], dw[13];
+  for (int k = 0; k < 13; ++k) {
+    cur[k] = r[k];
+    dh[k] = d[k];
+  }
+  body_frame<true>(heading_of(cur[3], cur[4], cur[5], cur[6]), dh, dw);
+  for (int k = 0; k < 13; ++k) cur[k] += dw[k];
+  const float qn = sqrtf(cur[3] * cur[3] + cur[4] * cur[4] + cur[5] * cur[5] + cur[6] * cur[6]);
   if (qn > 0.f)
-    for (int k = 3; k < 7; ++k) r[k] /= qn;
+    for (int k = 3; k < 7; ++k) cur[k] /= qn;
   const int J = v.a.j_max;
   const int4 mi = v.a.morph_info[v.a.inst_morph[i]];
   const int Ji = mi.w - 1;
-  for (int j = 0; j < J; ++j) {
-    r[13 + j] = j < Ji ? command(v, i, mi.z, j, frame + HORIZON - 1) : 0.f;
-    r[13 + J + j] = j < Ji ? command(v, i, mi.z, j, frame + HORIZON - 2) : 0.f;
+  for (int c = lane; c < 13 + 2 * J; c += 64) {
+    float val = 0.f;
+    if (c < 13) {
+#pragma unroll
+      for (int k = 0; k < 13; ++k) val = c == k ? cur[k] : val;
+    } else if (c < 13 + J) {
+      const int j = c - 13;
+      val = j < Ji ? command(v, i, mi.z, j, frame + HORIZON - 1) : 0.f;
+    } else {
+      const int j = c - 13 - J;
+      val = j < Ji ? command(v, i, mi.z, j, frame + HORIZON - 2) : 0.f;
+    }
+    r[c] = val;
   }
 }
 
@@ -168,18 +272,30 @@ __device__ __forceinline__ float wave_sum(float x) {
 // load; joint j transmits the moment of the loads on all points distal to it
 // about its anchor, projected on its axis.  Writes (or adds) the mean of |tau_j|
 // over the instance's joints.
+//
+// The loads are linear, so a link's sums split into its weight (from the link
+// mass and CoG: no per-point work) plus f_up times the count and the summed
+// arms of its points in the band.  Those per-point sums are 64-bit fixed-point
+// integers (2^-30 m) added with LDS atomics, which makes them exact and
+// independent of timing.
+constexpr double FIX = 1073741824.0;
+
 __global__ __launch_bounds__(64) void torque_kernel(WorldView v, const float* s, int64_t lds,
                                                     float* acc, int accumulate) {
   __shared__ float T[64][12];  // link transform in the construction frame: R (row-major), t
   __shared__ float S[64][6];   // per-link load sums: force, moment about the CoG
+  __shared__ int low_n[64];
+  __shared__ unsigned long long low_x[64], low_y[64];
   const int i = blockIdx.x;
   const int l = threadIdx.x;
   const int I = v.a.n_inst;
-  const int J = v.a.j_max;
   const int4 mi = v.a.morph_info[v.a.inst_morph[i]];
   const int N = mi.y, L = mi.w, pt0 = mi.x, lk0 = mi.z;
   const bool own = l < L;
   const float* lk = v.a.links + (int64_t)(lk0 + (own ? l : 0)) * LINK_F;
+  low_n[l] = 0;
+  low_x[l] = 0ull;
+  low_y[l] = 0ull;
 
   // joint rotation about the hinge: R_j = I + sin q [a]x + (1 - cos q) [a]x^2
   float Rj[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, tj[3] = {0, 0, 0};
@@ -223,18 +339,16 @@ __global__ __launch_bounds__(64) void torque_kernel(WorldView v, const float* s,
   }
 
   // body CoG in the construction frame from the link masses and link CoGs
-  float gb[3] = {0, 0, 0};
-  {
-    float m = own ? lk[npx::LK_MASS] : 0.f;
-    float wc[3] = {0, 0, 0};
-    if (own) {
-      const float* cg = lk + npx::LK_COG;
-      for (int r = 0; r < 3; ++r)
-        wc[r] = m * (T[l][3 * r] * cg[0] + T[l][3 * r + 1] * cg[1] + T[l][3 * r + 2] * cg[2] + T[l][9 + r]);
-    }
-    const float M = v.a.morph_mass[v.a.inst_morph[i]];
-    for (int r = 0; r < 3; ++r) gb[r] = wave_sum(wc[r]) / M;
+  const float ml = own ? lk[npx::LK_MASS] : 0.f;
+  float yc[3] = {0, 0, 0};  // this link's CoG at the current joint angles
+  if (own) {
+    const float* cg = lk + npx::LK_COG;
+    for (int r = 0; r < 3; ++r)
+      yc[r] = T[l][3 * r] * cg[0] + T[l][3 * r + 1] * cg[1] + T[l][3 * r + 2] * cg[2] + T[l][9 + r];
   }
+  const float M = v.a.morph_mass[v.a.inst_morph[i]];
+  float gb[3];
+  for (int r = 0; r < 3; ++r) gb[r] = wave_sum(ml * yc[r]) / M;
   float c[3], R[9];
   for (int r = 0; r < 3; ++r) c[r] = s ? s[(int64_t)i * lds + r] : v.a.st[(int64_t)r * I + i];
   {
@@ -243,71 +357,69 @@ __global__ __launch_bounds__(64) void torque_kernel(WorldView v, const float* s,
     npx::quat_to_mat(q4[0], q4[1], q4[2], q4[3], R);
   }
   // arm about the CoG (world axes) of a construction-frame point p on link k
-  auto arm = [&](const float4& p, int k, float out[3]) __attribute__((always_inline)) {
+  auto arm = [&](float px, float py, float pz, int k, float out[3]) __attribute__((always_inline)) {
     float y[3];
     for (int r = 0; r < 3; ++r)
-      y[r] = T[k][3 * r] * p.x + T[k][3 * r + 1] * p.y + T[k][3 * r + 2] * p.z + T[k][9 + r] - gb[r];
+      y[r] = T[k][3 * r] * px + T[k][3 * r + 1] * py + T[k][3 * r + 2] * pz + T[k][9 + r] - gb[r];
     for (int r = 0; r < 3; ++r) out[r] = R[3 * r] * y[0] + R[3 * r + 1] * y[1] + R[3 * r + 2] * y[2];
   };
-  auto is_low = [&](const float a[3]) __attribute__((always_inline)) {
-    const float px = c[0] + a[0], py = c[1] + a[1], pz = c[2] + a[2];
-    return pz - hf(v, px, py) < LOW_BAND;
-  };
 
-  // points carrying load
-  float nlow = 0.f;
+  // points in the load band: count and summed horizontal arms per link
+#pragma unroll 2
   for (int k = l; k < N; k += 64) {
+    const float4 p = v.a.pts[pt0 + k];
+    const int kl = v.a.pt_link[pt0 + k];  // link index local to the morphology
     float a[3];
-    arm(v.a.pts[pt0 + k], v.a.pt_link[pt0 + k], a);  // link index local to the morphology
-    nlow += is_low(a) ? 1.f : 0.f;
-  }
-  nlow = wave_sum(nlow);
-  const float M = v.a.morph_mass[v.a.inst_morph[i]];
-  const float f_up = nlow > 0.f ? -M * v.a.gz / nlow : 0.f;
-
-  // per-link sums of the loads and their moments about the CoG
-  float F[3] = {0, 0, 0}, Mo[3] = {0, 0, 0};
-  if (own && l > 0) {
-    const int b = v.lp_off[lk0 + l], e = v.lp_off[lk0 + l + 1];
-    for (int idx = b; idx < e; ++idx) {
-      const int kk = v.lp_idx[idx];
-      const float4 p = v.a.pts[kk];
-      float a[3];
-      arm(p, l, a);
-      const float fk[3] = {p.w * v.a.gx, p.w * v.a.gy, p.w * v.a.gz + (is_low(a) ? f_up : 0.f)};
-      for (int r = 0; r < 3; ++r) F[r] += fk[r];
-      Mo[0] += a[1] * fk[2] - a[2] * fk[1];
-      Mo[1] += a[2] * fk[0] - a[0] * fk[2];
-      Mo[2] += a[0] * fk[1] - a[1] * fk[0];
+    arm(p.x, p.y, p.z, kl, a);
+    if (c[2] + a[2] - hf(v, c[0] + a[0], c[1] + a[1]) < LOW_BAND) {
+      atomicAdd(&low_n[kl], 1);
+      atomicAdd(&low_x[kl], (unsigned long long)__double2ll_rn((double)a[0] * FIX));
+      atomicAdd(&low_y[kl], (unsigned long long)__double2ll_rn((double)a[1] * FIX));
     }
   }
+  __syncthreads();
+  const float nlow = wave_sum(own ? (float)low_n[l] : 0.f);
+  const float f_up = nlow > 0.f ? -M * v.a.gz / nlow : 0.f;
+
+  // this link's load sums: weight m_l g at its CoG, plus f_up on each band point
   if (own) {
+    const float y[3] = {yc[0] - gb[0], yc[1] - gb[1], yc[2] - gb[2]};
+    float ac[3], F[3], Mo[3];
+    for (int r = 0; r < 3; ++r) ac[r] = R[3 * r] * y[0] + R[3 * r + 1] * y[1] + R[3 * r + 2] * y[2];
+    F[0] = ml * v.a.gx;
+    F[1] = ml * v.a.gy;
+    F[2] = ml * v.a.gz;
+    Mo[0] = ac[1] * F[2] - ac[2] * F[1];
+    Mo[1] = ac[2] * F[0] - ac[0] * F[2];
+    Mo[2] = ac[0] * F[1] - ac[1] * F[0];
+    // f_up z at arms a: force f_up n, moment f_up (sum a_y, -sum a_x, 0)
+    const float sx = (float)((double)(long long)low_x[l] / FIX);
+    const float sy = (float)((double)(long long)low_y[l] / FIX);
+    F[2] += f_up * (float)low_n[l];
+    Mo[0] += f_up * sy;
+    Mo[1] -= f_up * sx;
     for (int r = 0; r < 3; ++r) {
       S[l][r] = F[r];
       S[l][3 + r] = Mo[r];
     }
   }
   __syncthreads();
-  // subtree sums, children before parents (links are stored parents first)
-  if (l == 0)
-    for (int k = L - 1; k >= 1; --k) {
-      const int p = v.a.link_parent[lk0 + k];
-      if (p >= 1)
-        for (int r = 0; r < 6; ++r) S[p][r] += S[k][r];
-    }
-  __syncthreads();
   float tau = 0.f;
   if (own && l > 0) {
-    // the hinge anchor moves with the link (it is fixed by the joint rotation)
-    const float4 o = make_float4(lk[0], lk[1], lk[2], 0.f);
-    float ao[3], aw[3], ab[3];
-    arm(o, l, ao);
+    // sums over the subtree, in link order
+    const unsigned long long sub = v.sub_mask[lk0 + l];
+    float St[6] = {0, 0, 0, 0, 0, 0};
+    for (int k = l; k < L; ++k)
+      if ((sub >> k) & 1ull)
+        for (int r = 0; r < 6; ++r) St[r] += S[k][r];
+    // the hinge anchor moves with the link (the joint rotation fixes it)
+    float ao[3], ab[3], aw[3];
+    arm(lk[0], lk[1], lk[2], l, ao);
     for (int r = 0; r < 3; ++r) ab[r] = T[l][3 * r] * an[0] + T[l][3 * r + 1] * an[1] + T[l][3 * r + 2] * an[2];
     for (int r = 0; r < 3; ++r) aw[r] = R[3 * r] * ab[0] + R[3 * r + 1] * ab[1] + R[3 * r + 2] * ab[2];
-    const float* Sl = S[l];
-    const float m0 = Sl[3] - (ao[1] * Sl[2] - ao[2] * Sl[1]);
-    const float m1 = Sl[4] - (ao[2] * Sl[0] - ao[0] * Sl[2]);
-    const float m2 = Sl[5] - (ao[0] * Sl[1] - ao[1] * Sl[0]);
+    const float m0 = St[3] - (ao[1] * St[2] - ao[2] * St[1]);
+    const float m1 = St[4] - (ao[2] * St[0] - ao[0] * St[2]);
+    const float m2 = St[5] - (ao[0] * St[1] - ao[1] * St[0]);
     tau = fabsf(aw[0] * m0 + aw[1] * m1 + aw[2] * m2);
   }
   tau = wave_sum(tau);
@@ -315,7 +427,6 @@ __global__ __launch_bounds__(64) void torque_kernel(WorldView v, const float* s,
     const float mean = L > 1 ? tau / (float)(L - 1) : 0.f;
     acc[i] = accumulate ? acc[i] + mean : mean;
   }
-  (void)J;
 }
 
 npx_status check_world(const npx_world* w) {
@@ -374,10 +485,9 @@ npx_status npx_sur_delta(npx_world* w, const float* s0, int64_t lds, float* y, i
   const WorldView v = npx::world_view(w);
   const int width = state_width(v.a.j_max);
   if (!s0 || !y || lds < width || ldy < width) return fail(NPX_EINVAL, "bad buffers or strides");
-  const int64_t n = (int64_t)v.a.n_inst * width;
   hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL(delta_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v, s0, lds,
-                     y, ldy, width);
+  hipLaunchKernelGGL(delta_kernel, dim3((unsigned)((v.a.n_inst + 3) / 4)), dim3(256), 0, st, v, s0,
+                     lds, y, ldy, width);
   HIP_TRY(hipGetLastError());
   npx::note_stream(w, st);
   return NPX_OK;
@@ -393,8 +503,8 @@ npx_status npx_sur_advance(npx_world* w, float* s, int64_t lds, const float* dy,
     return fail(NPX_EINVAL, "bad buffers, strides or frame");
   if (v.a.K != 1) return fail(NPX_EUNSUPPORTED, "the rollout update assumes joints set every frame");
   hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL(advance_kernel, dim3((unsigned)((v.a.n_inst + 255) / 256)), dim3(256), 0, st,
-                     v, s, lds, dy, lddy, frame);
+  hipLaunchKernelGGL(advance_kernel, dim3((unsigned)((v.a.n_inst + 3) / 4)), dim3(256), 0, st, v,
+                     s, lds, dy, lddy, frame);
   HIP_TRY(hipGetLastError());
   npx::note_stream(w, st);
   return NPX_OK;

@@ -79,6 +79,7 @@ struct npx_world {
   int* queue = nullptr;
   int* lp_off = nullptr;   // [total links + 1] point range of each link in lp_idx
   int* lp_idx = nullptr;   // [total points] point indices grouped by link
+  unsigned long long* sub_mask = nullptr;  // [total links] links of each link's subtree
 
   npx::StepArgs args{};
   npx_launch launch{64, 0, 100, 1, 8};
@@ -233,6 +234,7 @@ WorldView world_view(const npx_world* w) {
   v.a = w->args;
   v.lp_off = w->lp_off;
   v.lp_idx = w->lp_idx;
+  v.sub_mask = w->sub_mask;
   v.n_max = w->n_max;
   v.l_max = w->l_max;
   return v;
@@ -351,6 +353,17 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
       lpo.push_back((int)lpi.size());
     }
   }
+  // subtree of every link as a bit mask over the morphology's links (<= 64)
+  std::vector<unsigned long long> subm;
+  for (int mi = 0; mi < d->n_morphs; ++mi) {
+    const npx_morph_tables& m = d->morphs[mi];
+    std::vector<unsigned long long> mk(m.n_links, 0ull);
+    for (int l = m.n_links - 1; l >= 0; --l) {
+      if (l < 64) mk[l] |= 1ull << l;
+      if (l > 0) mk[m.parent[l]] |= mk[l];
+    }
+    subm.insert(subm.end(), mk.begin(), mk.end());
+  }
   if (!shape_for(w, 64, &w->shape)) {
     delete w;
     return fail(NPX_EUNSUPPORTED, "no kernel shape for %d points / %d links", w->n_max, w->l_max);
@@ -383,6 +396,7 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   ALLOC(w->queue, 1);
   ALLOC(w->lp_off, lpo.size());
   ALLOC(w->lp_idx, lpi.size());
+  ALLOC(w->sub_mask, subm.size());
 #undef ALLOC
 
   auto h2d = [&](void* dst, const void* src, size_t bytes) {
@@ -401,6 +415,7 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   H2D(w->link_depth, dep.data(), dep.size() * sizeof(int));
   H2D(w->lp_off, lpo.data(), lpo.size() * sizeof(int));
   H2D(w->lp_idx, lpi.data(), lpi.size() * sizeof(int));
+  H2D(w->sub_mask, subm.data(), subm.size() * sizeof(unsigned long long));
   H2D(w->hf, d->hf_heights, (size_t)d->hf_nx * d->hf_ny * sizeof(float));
   std::vector<int> ord = task_order(w);
   H2D(w->order, ord.data(), I * sizeof(int));
@@ -496,7 +511,7 @@ void npx_destroy_world(npx_world* w) {
   void* bufs[] = {w->st, w->step, w->flags, w->tele, w->inst_morph_d, w->morph_info,
                   w->morph_mass, w->pts, w->pt_link, w->links, w->link_parent,
                   w->link_depth, w->ctrl, w->hf, w->order, w->queue, w->lp_off,
-                  w->lp_idx};
+                  w->lp_idx, w->sub_mask};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete w;

@@ -62,7 +62,7 @@ def test_features_match_reference(walked):
         ref = so.features(i, r[i], 300)
         got = a[i, :293].astype(np.float64)
         np.testing.assert_allclose(got[:13][[0, 1]], 0.0)
-        np.testing.assert_allclose(got[3:13], ref[3:13], rtol=0, atol=0)
+        np.testing.assert_allclose(got[3:13], ref[3:13], rtol=1e-5, atol=1e-5)
         np.testing.assert_allclose(got[13:13 + J], ref[13:13 + J], rtol=0, atol=0)
         np.testing.assert_allclose(got[13 + J:13 + 2 * J], ref[13 + J:13 + 2 * J], atol=1e-4)
         np.testing.assert_allclose(got[13 + 2 * J:13 + 12 * J], ref[13 + 2 * J:13 + 12 * J],
@@ -94,7 +94,12 @@ def test_delta_and_advance(walked):
     after = torch.zeros_like(rows)
     gw2.rows(after)
     torch.cuda.synchronize()
-    np.testing.assert_array_equal(y.cpu().numpy(), (after - rows).cpu().numpy())
+    so = SO.SurrogateOracle(w)
+    yd, ad, rd = y.cpu().numpy(), after.cpu().numpy(), rows.cpu().numpy()
+    np.testing.assert_array_equal(yd[:, 13:], ad[:, 13:] - rd[:, 13:])
+    for i in range(N_INST):   # body rows in the heading frame of the first state
+        ref = so.delta(rd[i].astype(np.float64), ad[i].astype(np.float64))
+        np.testing.assert_allclose(yd[i, :13], ref[:13], rtol=1e-5, atol=1e-6)
     # the update with the true delta lands on the stepped state; q, q_prev exactly
     s = rows.clone()
     gw2.sur_advance(s, y, 300)
@@ -103,7 +108,6 @@ def test_delta_and_advance(walked):
     np.testing.assert_array_equal(got[:, 13:], want[:, 13:])
     np.testing.assert_allclose(got[:, :13], want[:, :13], atol=2e-6)
     # and matches the FP64 update on the same inputs
-    so = SO.SurrogateOracle(w)
     r, d = rows.cpu().numpy().astype(np.float64), y.cpu().numpy().astype(np.float64)
     for i in range(0, N_INST, 7):
         ref = so.advance(i, r[i], d[i], 300)

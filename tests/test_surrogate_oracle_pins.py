@@ -144,6 +144,46 @@ def test_targets_and_rollout_update_match_the_oracle_step():
         np.testing.assert_allclose(x[13 + 2 * so.J + k * so.J:13 + 2 * so.J + k * so.J + Jn], q,
                                    rtol=0, atol=1e-15)
     row10 = S.state_row(st, Jn, so.J)
-    out = so.advance(0, row0, row10 - row0, n)
+    out = so.advance(0, row0, so.delta(row0, row10), n)
     np.testing.assert_allclose(out[:13], row10[:13], atol=1e-12)
     np.testing.assert_array_equal(out[13:], row10[13:])
+
+
+def _yawed(row, yaw):
+    """The same state turned by yaw about the world z axis through the origin."""
+    Rz = np.array([[math.cos(yaw), -math.sin(yaw), 0], [math.sin(yaw), math.cos(yaw), 0], [0, 0, 1]])
+    out = np.array(row, dtype=np.float64)
+    for k in (0, 7, 10):
+        out[k:k + 3] = Rz @ row[k:k + 3]
+    out[3:7] = S.quat_mul([math.cos(yaw / 2), 0, 0, math.sin(yaw / 2)], row[3:7])
+    return out
+
+
+def test_heading_frame_inputs_do_not_depend_on_yaw():
+    w = W.config1(seed=2)
+    so = S.SurrogateOracle(w)
+    ow = O.OracleWorld(w)
+    st = ow.init_state(0)
+    ow.run(0, st, 400)
+    row = S.state_row(st, 18, so.J)
+    base = so.features(0, row, 400)
+    for yaw in (0.7, -2.9, 3.1):
+        np.testing.assert_allclose(so.features(0, _yawed(row, yaw), 400), base, atol=1e-12)
+    # a negated orientation quaternion is the same state
+    neg = np.array(row)
+    neg[3:7] *= -1
+    np.testing.assert_allclose(so.features(0, neg, 400), base, atol=1e-15)
+
+
+def test_heading_frame_closed_form_and_round_trip():
+    hf = S.HeadingFrame([math.cos(math.pi / 4), 0, 0, math.sin(math.pi / 4)])   # facing +y
+    b = np.zeros(13)
+    b[3], b[7:10], b[10:13] = 1.0, [0, 1.0, 0.25], [0.5, 0, 2.0]
+    out = hf.to_frame(b)
+    np.testing.assert_allclose(out[7:10], [1.0, 0, 0.25], atol=1e-15)      # moving forward
+    np.testing.assert_allclose(out[10:13], [0, -0.5, 2.0], atol=1e-15)     # rolling to the right
+    np.testing.assert_allclose(hf.from_frame(out), b, atol=1e-15)
+    # the orientation itself becomes level and unturned, w >= 0
+    Q = np.array([-math.cos(1.2), 0, 0, -math.sin(1.2)])
+    h = S.HeadingFrame(Q)
+    np.testing.assert_allclose(h.sign * S.quat_mul(h.q_minus, Q), [1, 0, 0, 0], atol=1e-15)
