@@ -91,14 +91,26 @@ __device__ __forceinline__ float hf_at(const StepArgs& a, float x, float y) {
   return hf_lookup(a.hf, a.hf_nx, a.hf_ny, a.hf_x0, a.hf_y0, a.hf_s, x, y);
 }
 
+// The bits of a wave-wide lane mask that belong to segment `seg` (G lanes),
+// shifted down to bit 0.
+template <int G>
+__device__ __forceinline__ unsigned long long seg_bits(unsigned long long m, int seg) {
+  if constexpr (G == 64) {
+    (void)seg;
+    return m;
+  } else {
+    return (m >> (seg * G)) & ((1ull << G) - 1ull);
+  }
+}
+
 enum Mode { kStep = 0, kPlace = 1, kPoints = 2 };
 
 // LDS rows of one link: [R row 0 | t0], [R row 1 | t1], [R row 2 | t2].
 using LinkT = float4[3];
 
 template <int G, int PPL, int LPL, int MODE>
-__device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT, int tb,
-                                          int seg, int sl) {
+__device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT, int* cand,
+                                          int tb, int seg, int sl) {
   constexpr int IPW = 64 / G;
   const int I = a.n_inst;
   const int task = tb * IPW + seg;
@@ -129,6 +141,41 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
     qp[l] = lj[l] ? st[(size_t)(BODY_ROWS + a.j_max + j) * I + inst] : 0.f;
   }
 
+  // ---- this lane's link constants, read once per launch: hinge anchor and
+  // unit axis, limits, mass, CoG and inertia, tree depth and parent, and the
+  // joint's controller (amplitude, frequency, phase in turns)
+  float k_ao[LPL][3], k_ax[LPL][3], k_lo[LPL], k_hi[LPL], k_m[LPL], k_c[LPL][3], k_I[LPL][6];
+  float k_A[LPL], k_f[LPL];
+  double k_ph[LPL];
+  int k_dep[LPL], k_par[LPL];
+#pragma unroll
+  for (int l = 0; l < LPL; ++l) {
+    const float* lk = a.links + (size_t)lrow[l] * LINK_F;
+    float x = lk[3], y = lk[4], z = lk[5];
+    const float n2 = x * x + y * y + z * z;
+    const float inv = n2 > 0.f ? __builtin_amdgcn_rsqf(n2) : 0.f;
+    k_ax[l][0] = x * inv;
+    k_ax[l][1] = y * inv;
+    k_ax[l][2] = z * inv;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      k_ao[l][i] = lk[i];
+      k_c[l][i] = lk[LK_COG + i];
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) k_I[l][i] = lk[LK_INERTIA + i];
+    k_lo[l] = lk[6];
+    k_hi[l] = lk[7];
+    k_m[l] = lk[LK_MASS];
+    k_dep[l] = lv[l] ? a.link_depth[lrow[l]] : -1;
+    k_par[l] = a.link_parent[lrow[l]];
+    const int li = sl + l * G;
+    const float* cp = a.ctrl + ((size_t)inst * a.j_max + (lj[l] ? li - 1 : 0)) * 3;
+    k_A[l] = cp[0];
+    k_f[l] = cp[1];
+    k_ph[l] = (double)cp[2] * kInvTwoPi;
+  }
+
   // ---- per-robot state (same value in every lane of the segment)
   float c[3], Q[4], v[3], w[3];
 #pragma unroll
@@ -145,8 +192,10 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
 #pragma unroll
   for (int i = 0; i < TELE_N; ++i) tele[i] = a.tele[(size_t)i * I + inst];
 
-  // ---- body points about the CoG, mass properties, and their increments
-  float rx[PPL], ry[PPL], rz[PPL];
+  // ---- mass properties and their increments; body points about the CoG are
+  // not kept: a point is rebuilt from its construction-frame position and its
+  // link's transform in LDS where it is needed, which keeps the registers of a
+  // lane independent of its point count
   float gb[3], dgb[3], Ib[6], Iinv[6];
 
   // Forward kinematics at angles q, with the increment from angles q - dql
@@ -155,14 +204,8 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
     float Rj[LPL][9], tj[LPL][3], dRj[LPL][9], dtj[LPL][3];
 #pragma unroll
     for (int l = 0; l < LPL; ++l) {
-      const float* lk = a.links + (size_t)lrow[l] * LINK_F;
-      const float ao[3] = {lk[0], lk[1], lk[2]};
-      float x = lk[3], y = lk[4], z = lk[5];
-      const float n2 = x * x + y * y + z * z;
-      const float inv = n2 > 0.f ? __builtin_amdgcn_rsqf(n2) : 0.f;
-      x *= inv;
-      y *= inv;
-      z *= inv;
+      const float ao[3] = {k_ao[l][0], k_ao[l][1], k_ao[l][2]};
+      const float x = k_ax[l][0], y = k_ax[l][1], z = k_ax[l][2];
       // Rj = cos 1 + sin K + (1 - cos) a a^T with K = [a]x (Rodrigues)
       float s, co;
       sin_cos(q[l], &s, &co);
@@ -207,8 +250,8 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
       __syncthreads();
 #pragma unroll
       for (int l = 0; l < LPL; ++l) {
-        if (lv[l] && a.link_depth[lrow[l]] == lev) {
-          const int par = a.link_parent[lrow[l]];
+        if (k_dep[l] == lev) {
+          const int par = k_par[l];
           const float4 p0 = T[par][0], p1 = T[par][1], p2 = T[par][2];
           const float4 d0 = dT[par][0], d1 = dT[par][1], d2 = dT[par][2];
           const float Rp[9] = {p0.x, p0.y, p0.z, p1.x, p1.y, p1.z, p2.x, p2.y, p2.z};
@@ -256,9 +299,8 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
         const float4 r0 = T[li][0], r1 = T[li][1], r2 = T[li][2];
         const float4 d0 = dT[li][0], d1 = dT[li][1], d2 = dT[li][2];
         const float R[9] = {r0.x, r0.y, r0.z, r1.x, r1.y, r1.z, r2.x, r2.y, r2.z};
-        const float* lk = a.links + (size_t)lrow[l] * LINK_F;
-        const float lc[3] = {lk[LK_COG], lk[LK_COG + 1], lk[LK_COG + 2]};
-        const float m = lk[LK_MASS];
+        const float lc[3] = {k_c[l][0], k_c[l][1], k_c[l][2]};
+        const float m = k_m[l];
         float p[3];
         p[0] = R[0] * lc[0] + R[1] * lc[1] + R[2] * lc[2] + r0.w;
         p[1] = R[3] * lc[0] + R[4] * lc[1] + R[5] * lc[2] + r1.w;
@@ -270,7 +312,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
         acc[10] += m * (d1.x * lc[0] + d1.y * lc[1] + d1.z * lc[2] + d1.w);
         acc[11] += m * (d2.x * lc[0] + d2.y * lc[1] + d2.z * lc[2] + d2.w);
         // A = R I (I symmetric: xx yy zz xy xz yz)
-        const float* S = lk + LK_INERTIA;
+        const float* S = k_I[l];
         const float Ifull[9] = {S[0], S[3], S[4], S[3], S[1], S[5], S[4], S[5], S[2]};
         float A[9];
 #pragma unroll
@@ -314,37 +356,31 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
       Iinv[0] = c00 * id; Iinv[1] = c11 * id; Iinv[2] = c22 * id;
       Iinv[3] = c01 * id; Iinv[4] = c02 * id; Iinv[5] = c12 * id;
     }
-    // body points y = T_link rho, about the CoG
-#pragma unroll
-    for (int p = 0; p < PPL; ++p) {
-      const int k = sl + p * G;
-      const bool ok = k < N;
-      const int kk = pt_off + (ok ? k : 0);
-      const float4 rho = a.pts[kk];
-      const int lk = ok ? a.pt_link[kk] : 0;
-      const float4 r0 = T[lk][0], r1 = T[lk][1], r2 = T[lk][2];
-      const float yx = r0.x * rho.x + r0.y * rho.y + r0.z * rho.z + r0.w - gb[0];
-      const float yy = r1.x * rho.x + r1.y * rho.y + r1.z * rho.z + r1.w - gb[1];
-      const float yz = r2.x * rho.x + r2.y * rho.y + r2.z * rho.z + r2.w - gb[2];
-      rx[p] = ok ? yx : 0.f;
-      ry[p] = ok ? yy : 0.f;
-      rz[p] = ok ? yz : 0.f;
-      group_fence(p);
-    }
+  };
+
+  // Body point k of this robot about the CoG (construction axes) from the link
+  // transforms in T; returns false past the robot's point count.
+  auto body_point = [&](int k, float* r) __attribute__((always_inline)) {
+    const bool ok = k < N;
+    const int kk = pt_off + (ok ? k : 0);
+    const float4 rho = a.pts[kk];
+    const int lk = ok ? a.pt_link[kk] : 0;
+    const float4 r0 = T[lk][0], r1 = T[lk][1], r2 = T[lk][2];
+    r[0] = r0.x * rho.x + r0.y * rho.y + r0.z * rho.z + r0.w - gb[0];
+    r[1] = r1.x * rho.x + r1.y * rho.y + r1.z * rho.z + r1.w - gb[1];
+    r[2] = r2.x * rho.x + r2.y * rho.y + r2.z * rho.z + r2.w - gb[2];
+    return ok;
   };
 
   // S0: commanded angle of this lane's joints at frame n, clamped to the limits
   auto command = [&](int l) __attribute__((always_inline)) {
-    const int li = sl + l * G;
-    const float* cp = a.ctrl + ((size_t)inst * a.j_max + (lj[l] ? li - 1 : 0)) * 3;
-    const float* lk = a.links + (size_t)lrow[l] * LINK_F;
     const double t = (double)n * a.dt_d;
-    double ph = (double)cp[1] * t + (double)cp[2] * kInvTwoPi;
+    double ph = (double)k_f[l] * t + k_ph[l];
     ph -= floor(ph);
     float sq, cq;
     sin_cos(kTwoPi * (float)ph, &sq, &cq);
-    const float qh = cp[0] * sq;
-    return lj[l] ? fminf(fmaxf(qh, lk[6]), lk[7]) : 0.f;
+    const float qh = k_A[l] * sq;
+    return lj[l] ? fminf(fmaxf(qh, k_lo[l]), k_hi[l]) : 0.f;
   };
 
   float dql[LPL];
@@ -373,11 +409,12 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
       const int k = sl + p * G;
-      if (valid && k < N) {
+      float r[3];
+      if (body_point(k, r) && valid) {
         float* o = a.points_out + ((size_t)inst * a.n_max + k) * 3;
-        o[0] = c[0] + (R[0] * rx[p] + R[1] * ry[p] + R[2] * rz[p]);
-        o[1] = c[1] + (R[3] * rx[p] + R[4] * ry[p] + R[5] * rz[p]);
-        o[2] = c[2] + (R[6] * rx[p] + R[7] * ry[p] + R[8] * rz[p]);
+        o[0] = c[0] + (R[0] * r[0] + R[1] * r[1] + R[2] * r[2]);
+        o[1] = c[1] + (R[3] * r[0] + R[4] * r[1] + R[5] * r[2]);
+        o[2] = c[2] + (R[6] * r[0] + R[7] * r[1] + R[8] * r[2]);
       }
     }
   }
@@ -394,11 +431,13 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
       const int k = sl + p * G;
-      const float ux = R[0] * rx[p] + R[1] * ry[p] + R[2] * rz[p];
-      const float uy = R[3] * rx[p] + R[4] * ry[p] + R[5] * rz[p];
-      const float uz = R[6] * rx[p] + R[7] * ry[p] + R[8] * rz[p];
+      float r[3];
+      const bool ok = body_point(k, r);
+      const float ux = R[0] * r[0] + R[1] * r[1] + R[2] * r[2];
+      const float uy = R[3] * r[0] + R[4] * r[1] + R[5] * r[2];
+      const float uz = R[6] * r[0] + R[7] * r[1] + R[8] * r[2];
       const float Px = c[0] + ux, Py = c[1] + uy, Pz = c[2] + uz;
-      if (k < N) {
+      if (ok) {
         const float d = hf_at(a, Px, Py) - Pz;
         if (d > 0.f) {
           kap |= 1u << p;
@@ -493,46 +532,60 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
     // predicted CoG c1: source xi = P^n - c1 = R r_old - (c1 - c), slip
     // delta = P* - P^n. The normal equations (4)-(6) need n, sum xi,
     // sum |xi|^2, sum delta and sum xi x delta.
-    const float dcx = c1[0] - c[0], dcy = c1[1] - c[1];
-    float mn = 0.f, Sx = 0.f, Sy = 0.f, S2 = 0.f, Dx = 0.f, Dy = 0.f, Cd = 0.f;
+    //
+    // Only points in contact at P^n can be in the friction set, and they are
+    // few (the feet), so they are first compacted into an LDS list (slot by
+    // slot, in lane order) and the segment's lanes then share the list: one
+    // pass of G candidates instead of PPL mostly idle slots.
+    int n_cand = 0;
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
-      if (kap & (1u << p)) {
-        const float ux = R1[0] * rx[p] + R1[1] * ry[p] + R1[2] * rz[p];
-        const float uy = R1[3] * rx[p] + R1[4] * ry[p] + R1[5] * rz[p];
-        const float uz = R1[6] * rx[p] + R1[7] * ry[p] + R1[8] * rz[p];
-        const float Px = c1[0] + ux, Py = c1[1] + uy, Pz = c1[2] + uz;
-        if (hf_at(a, Px, Py) - Pz > 0.f) {
-          // body-point increment of this frame's joint update: dr = dT rho - dg_b
-          float drx = 0.f, dry = 0.f, drz = 0.f;
-          if (fk_now) {
-            const int kk = pt_off + sl + p * G;
-            const float4 rho = a.pts[kk];
-            const int lk = a.pt_link[kk];
-            const float4 d0 = dT[lk][0], d1 = dT[lk][1], d2 = dT[lk][2];
-            drx = d0.x * rho.x + d0.y * rho.y + d0.z * rho.z + d0.w - dgb[0];
-            dry = d1.x * rho.x + d1.y * rho.y + d1.z * rho.z + d1.w - dgb[1];
-            drz = d2.x * rho.x + d2.y * rho.y + d2.z * rho.z + d2.w - dgb[2];
-          }
-          const float ox = rx[p] - drx, oy = ry[p] - dry, oz = rz[p] - drz;  // r_old
-          const float Ux = R[0] * ox + R[1] * oy + R[2] * oz;
-          const float Uy = R[3] * ox + R[4] * oy + R[5] * oz;
-          const float Uz = R[6] * ox + R[7] * oy + R[8] * oz;
-          const float sx = Ux - dcx, sy = Uy - dcy;
-          const float dx = (Eb[0] * Ux + Eb[1] * Uy + Eb[2] * Uz) +
-                           (R1[0] * drx + R1[1] * dry + R1[2] * drz) + dcx;
-          const float dy = (Eb[3] * Ux + Eb[4] * Uy + Eb[5] * Uz) +
-                           (R1[3] * drx + R1[4] * dry + R1[5] * drz) + dcy;
-          mn += 1.f;
-          Sx += sx;
-          Sy += sy;
-          S2 += sx * sx + sy * sy;
-          Dx += dx;
-          Dy += dy;
-          Cd += sx * dy - sy * dx;
+      const bool hit = (kap >> p) & 1u;
+      const unsigned long long m = seg_bits<G>(__ballot(hit), seg);
+      if (hit) cand[n_cand + __popcll(m & ((1ull << sl) - 1ull))] = sl + p * G;
+      n_cand += __popcll(m);
+    }
+    __builtin_amdgcn_wave_barrier();
+    const float dcx = c1[0] - c[0], dcy = c1[1] - c[1];
+    float mn = 0.f, Sx = 0.f, Sy = 0.f, S2 = 0.f, Dx = 0.f, Dy = 0.f, Cd = 0.f;
+    for (int e = sl; e < n_cand; e += G) {
+      const int kk = pt_off + cand[e];
+      const float4 rho = a.pts[kk];
+      const int lk = a.pt_link[kk];
+      // r = T rho - g_b at the new joint angles, and its increment this frame
+      const float4 t0 = T[lk][0], t1 = T[lk][1], t2 = T[lk][2];
+      const float rx = t0.x * rho.x + t0.y * rho.y + t0.z * rho.z + t0.w - gb[0];
+      const float ry = t1.x * rho.x + t1.y * rho.y + t1.z * rho.z + t1.w - gb[1];
+      const float rz = t2.x * rho.x + t2.y * rho.y + t2.z * rho.z + t2.w - gb[2];
+      const float ux = R1[0] * rx + R1[1] * ry + R1[2] * rz;
+      const float uy = R1[3] * rx + R1[4] * ry + R1[5] * rz;
+      const float uz = R1[6] * rx + R1[7] * ry + R1[8] * rz;
+      const float Px = c1[0] + ux, Py = c1[1] + uy, Pz = c1[2] + uz;
+      if (hf_at(a, Px, Py) - Pz > 0.f) {
+        float drx = 0.f, dry = 0.f, drz = 0.f;
+        if (fk_now) {
+          const float4 d0 = dT[lk][0], d1 = dT[lk][1], d2 = dT[lk][2];
+          drx = d0.x * rho.x + d0.y * rho.y + d0.z * rho.z + d0.w - dgb[0];
+          dry = d1.x * rho.x + d1.y * rho.y + d1.z * rho.z + d1.w - dgb[1];
+          drz = d2.x * rho.x + d2.y * rho.y + d2.z * rho.z + d2.w - dgb[2];
         }
+        const float ox = rx - drx, oy = ry - dry, oz = rz - drz;  // r_old
+        const float Ux = R[0] * ox + R[1] * oy + R[2] * oz;
+        const float Uy = R[3] * ox + R[4] * oy + R[5] * oz;
+        const float Uz = R[6] * ox + R[7] * oy + R[8] * oz;
+        const float sx = Ux - dcx, sy = Uy - dcy;
+        const float dx = (Eb[0] * Ux + Eb[1] * Uy + Eb[2] * Uz) +
+                         (R1[0] * drx + R1[1] * dry + R1[2] * drz) + dcx;
+        const float dy = (Eb[3] * Ux + Eb[4] * Uy + Eb[5] * Uz) +
+                         (R1[3] * drx + R1[4] * dry + R1[5] * drz) + dcy;
+        mn += 1.f;
+        Sx += sx;
+        Sy += sy;
+        S2 += sx * sx + sy * sy;
+        Dx += dx;
+        Dy += dy;
+        Cd += sx * dy - sy * dx;
       }
-      group_fence(p);
     }
     mn = seg_sum<G>(mn);
     Sx = seg_sum<G>(Sx);
@@ -633,21 +686,24 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
   }
 }
 
-// Residency: with a 64-lane segment and at most 6 points per lane, capping the
-// kernel at 256 registers (two waves per SIMD) costs a few spills but hides
-// gather and LDS latency behind a second wave (1.6x measured on 4,096
-// hexapods). Shapes with more points per lane spill badly under the cap, so
-// they keep the compiler's choice.
-template <int G, int PPL>
-constexpr int kMinWavesPerEU = (G == 64 && PPL <= 6) ? 2 : 1;
+// Residency: capping the registers at 256 (two waves per SIMD) for the
+// one-link-per-lane shapes of a 64-lane segment with at most 6 points per lane
+// and of a 32-lane segment with at most 12 points per lane keeps two waves
+// resident to hide gather, LDS and DPP latency; with the body points rebuilt
+// from LDS these shapes fit the cap with few or no spills (on 4,096 hexapods
+// the 32-lane shape went from 16.6 to 9.1 us per frame with the cap). Larger
+// shapes would spill badly under the cap and keep the compiler's choice.
+template <int G, int PPL, int LPL>
+constexpr int kMinWavesPerEU = ((G == 64 && PPL <= 6) || (G == 32 && PPL <= 12 && LPL == 1)) ? 2 : 1;
 
 template <int G, int PPL, int LPL, int MODE>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWavesPerEU<G, PPL>, 8)))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWavesPerEU<G, PPL, LPL>, 8)))
 void step_kernel(const StepArgs a) {
   constexpr int IPW = 64 / G;
   constexpr int LMAX = G * LPL;
   __shared__ LinkT T[IPW][LMAX];
   __shared__ LinkT dT[IPW][LMAX];
+  __shared__ int cand[IPW][G * PPL];  // contact points of a frame, compacted
   const int lane = threadIdx.x;
   const int seg = lane / G;
   const int sl = lane - seg * G;
@@ -662,7 +718,7 @@ void step_kernel(const StepArgs a) {
       tb = blockIdx.x;
     }
     if (tb >= a.n_blocks) break;
-    run_block<G, PPL, LPL, MODE>(a, T[seg], dT[seg], tb, seg, sl);
+    run_block<G, PPL, LPL, MODE>(a, T[seg], dT[seg], cand[seg], tb, seg, sl);
     __syncthreads();
   }
 }
