@@ -110,7 +110,7 @@ using LinkT = float4[3];
 
 template <int G, int PPL, int LPL, int MODE>
 __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT, int* cand,
-                                          int tb, int seg, int sl) {
+                                          int* touch, int tb, int seg, int sl) {
   constexpr int IPW = 64 / G;
   const int I = a.n_inst;
   const int task = tb * IPW + seg;
@@ -145,6 +145,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
   // unit axis, limits, mass, CoG and inertia, tree depth and parent, and the
   // joint's controller (amplitude, frequency, phase in turns)
   float k_ao[LPL][3], k_ax[LPL][3], k_lo[LPL], k_hi[LPL], k_m[LPL], k_c[LPL][3], k_I[LPL][6];
+  float k_sph[LPL][4];  // bounding sphere of the link's points: centre, radius
   float k_A[LPL], k_f[LPL];
   double k_ph[LPL];
   int k_dep[LPL], k_par[LPL];
@@ -164,6 +165,8 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
     }
 #pragma unroll
     for (int i = 0; i < 6; ++i) k_I[l][i] = lk[LK_INERTIA + i];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) k_sph[l][i] = lk[LK_SPHERE + i];
     k_lo[l] = lk[6];
     k_hi[l] = lk[7];
     k_m[l] = lk[LK_MASS];
@@ -201,7 +204,9 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
   // Forward kinematics at angles q, with the increment from angles q - dql
   // (dql = 0: no joint moved). Writes T, dT for every link of the segment.
   auto forward_kinematics = [&](const float* dql) __attribute__((always_inline)) {
-    float Rj[LPL][9], tj[LPL][3], dRj[LPL][9], dtj[LPL][3];
+    // Each joint's own rotation about its hinge and its increment go into the
+    // link's LDS rows first; the level pass below then composes them in place
+    // with the parent's final transform, so they are not held in registers.
 #pragma unroll
     for (int l = 0; l < LPL; ++l) {
       const float ao[3] = {k_ao[l][0], k_ao[l][1], k_ao[l][2]};
@@ -222,20 +227,27 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
       const float E[9] = {ve * (x * x - 1.f), ve * x * y - se * z,  ve * x * z + se * y,
                           ve * y * x + se * z, ve * (y * y - 1.f),  ve * y * z - se * x,
                           ve * z * x - se * y, ve * z * y + se * x, ve * (z * z - 1.f)};
+      float dRj[9], tj[3], dtj[3];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          Rj[l][3 * i + k] = R0[3 * i + k];
-          dRj[l][3 * i + k] =
+        for (int k = 0; k < 3; ++k)
+          dRj[3 * i + k] =
               -(R0[3 * i] * E[k] + R0[3 * i + 1] * E[3 + k] + R0[3 * i + 2] * E[6 + k]);
-        }
       }
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        tj[l][i] = ao[i] - (R0[3 * i] * ao[0] + R0[3 * i + 1] * ao[1] + R0[3 * i + 2] * ao[2]);
-        dtj[l][i] = -(dRj[l][3 * i] * ao[0] + dRj[l][3 * i + 1] * ao[1] +
-                      dRj[l][3 * i + 2] * ao[2]);
+        tj[i] = ao[i] - (R0[3 * i] * ao[0] + R0[3 * i + 1] * ao[1] + R0[3 * i + 2] * ao[2]);
+        dtj[i] = -(dRj[3 * i] * ao[0] + dRj[3 * i + 1] * ao[1] + dRj[3 * i + 2] * ao[2]);
+      }
+      const int li = sl + l * G;
+      if (lj[l]) {
+        T[li][0] = make_float4(R0[0], R0[1], R0[2], tj[0]);
+        T[li][1] = make_float4(R0[3], R0[4], R0[5], tj[1]);
+        T[li][2] = make_float4(R0[6], R0[7], R0[8], tj[2]);
+        dT[li][0] = make_float4(dRj[0], dRj[1], dRj[2], dtj[0]);
+        dT[li][1] = make_float4(dRj[3], dRj[4], dRj[5], dtj[1]);
+        dT[li][2] = make_float4(dRj[6], dRj[7], dRj[8], dtj[2]);
       }
     }
     if (sl == 0) {
@@ -252,6 +264,13 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
       for (int l = 0; l < LPL; ++l) {
         if (k_dep[l] == lev) {
           const int par = k_par[l];
+          const int li = sl + l * G;
+          const float4 j0 = T[li][0], j1 = T[li][1], j2 = T[li][2];
+          const float4 e0 = dT[li][0], e1 = dT[li][1], e2 = dT[li][2];
+          const float Rj[9] = {j0.x, j0.y, j0.z, j1.x, j1.y, j1.z, j2.x, j2.y, j2.z};
+          const float tj[3] = {j0.w, j1.w, j2.w};
+          const float dRj[9] = {e0.x, e0.y, e0.z, e1.x, e1.y, e1.z, e2.x, e2.y, e2.z};
+          const float dtj[3] = {e0.w, e1.w, e2.w};
           const float4 p0 = T[par][0], p1 = T[par][1], p2 = T[par][2];
           const float4 d0 = dT[par][0], d1 = dT[par][1], d2 = dT[par][2];
           const float Rp[9] = {p0.x, p0.y, p0.z, p1.x, p1.y, p1.z, p2.x, p2.y, p2.z};
@@ -265,19 +284,18 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
                                  Rp[3 * i + 2] - dRp[3 * i + 2]};
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-              R[3 * i + k] = Rp[3 * i] * Rj[l][k] + Rp[3 * i + 1] * Rj[l][3 + k] +
-                             Rp[3 * i + 2] * Rj[l][6 + k];
-              dR[3 * i + k] = dRp[3 * i] * Rj[l][k] + dRp[3 * i + 1] * Rj[l][3 + k] +
-                              dRp[3 * i + 2] * Rj[l][6 + k] + Po[0] * dRj[l][k] +
-                              Po[1] * dRj[l][3 + k] + Po[2] * dRj[l][6 + k];
+              R[3 * i + k] = Rp[3 * i] * Rj[k] + Rp[3 * i + 1] * Rj[3 + k] +
+                             Rp[3 * i + 2] * Rj[6 + k];
+              dR[3 * i + k] = dRp[3 * i] * Rj[k] + dRp[3 * i + 1] * Rj[3 + k] +
+                              dRp[3 * i + 2] * Rj[6 + k] + Po[0] * dRj[k] +
+                              Po[1] * dRj[3 + k] + Po[2] * dRj[6 + k];
             }
-            t[i] = Rp[3 * i] * tj[l][0] + Rp[3 * i + 1] * tj[l][1] + Rp[3 * i + 2] * tj[l][2] +
+            t[i] = Rp[3 * i] * tj[0] + Rp[3 * i + 1] * tj[1] + Rp[3 * i + 2] * tj[2] +
                    tp[i];
-            dt[i] = dRp[3 * i] * tj[l][0] + dRp[3 * i + 1] * tj[l][1] +
-                    dRp[3 * i + 2] * tj[l][2] + Po[0] * dtj[l][0] + Po[1] * dtj[l][1] +
-                    Po[2] * dtj[l][2] + dtp[i];
+            dt[i] = dRp[3 * i] * tj[0] + dRp[3 * i + 1] * tj[1] +
+                    dRp[3 * i + 2] * tj[2] + Po[0] * dtj[0] + Po[1] * dtj[1] +
+                    Po[2] * dtj[2] + dtp[i];
           }
-          const int li = sl + l * G;
           T[li][0] = make_float4(R[0], R[1], R[2], t[0]);
           T[li][1] = make_float4(R[3], R[4], R[5], t[1]);
           T[li][2] = make_float4(R[6], R[7], R[8], t[2]);
@@ -394,7 +412,286 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
     }
   }
 
-  forward_kinematics(dql);
+  const float dt = a.dt, inv_dt = a.inv_dt;
+  // The frame loop is rotated so that the forward kinematics has one call site:
+  // each pass runs the pending kinematics (the launch's first, or the joint
+  // update of the frame before), then the rest of that frame (S4-S9), then the
+  // start of the next (S1-S3). A second inlined copy of the kinematics could
+  // round differently and make a trajectory depend on where launches begin.
+  bool fk_pending = true, fk_now = false;
+  unsigned kap = 0u;
+  float F = 0.f, tx = 0.f, ty = 0.f, nc = 0.f;
+  for (int s = 0;; ++s) {
+    if (fk_pending) forward_kinematics(dql);
+    fk_pending = false;
+    if (MODE == kStep && s > 0) {
+      const bool active = valid && fl == 0;
+      float R[9];
+      quat_to_mat(Q[0], Q[1], Q[2], Q[3], R);
+      // S4: trial step. Body-frame Euler equation: I_b dw_b = tau_b - w_b x I_b w_b
+      float v1[3], w1[3], c1[3], Q1[4], dq[4];
+      v1[0] = v[0] + dt * a.gx;
+      v1[1] = v[1] + dt * a.gy;
+      v1[2] = v[2] + dt * (a.gz + F * invM);
+      {
+        const float wb[3] = {R[0] * w[0] + R[3] * w[1] + R[6] * w[2],
+                             R[1] * w[0] + R[4] * w[1] + R[7] * w[2],
+                             R[2] * w[0] + R[5] * w[1] + R[8] * w[2]};
+        const float tb_[3] = {R[0] * tx + R[3] * ty, R[1] * tx + R[4] * ty, R[2] * tx + R[5] * ty};
+        const float Lb[3] = {Ib[0] * wb[0] + Ib[3] * wb[1] + Ib[4] * wb[2],
+                             Ib[3] * wb[0] + Ib[1] * wb[1] + Ib[5] * wb[2],
+                             Ib[4] * wb[0] + Ib[5] * wb[1] + Ib[2] * wb[2]};
+        const float rb[3] = {tb_[0] - (wb[1] * Lb[2] - wb[2] * Lb[1]),
+                             tb_[1] - (wb[2] * Lb[0] - wb[0] * Lb[2]),
+                             tb_[2] - (wb[0] * Lb[1] - wb[1] * Lb[0])};
+        const float ab[3] = {Iinv[0] * rb[0] + Iinv[3] * rb[1] + Iinv[4] * rb[2],
+                             Iinv[3] * rb[0] + Iinv[1] * rb[1] + Iinv[5] * rb[2],
+                             Iinv[4] * rb[0] + Iinv[5] * rb[1] + Iinv[2] * rb[2]};
+  #pragma unroll
+        for (int i = 0; i < 3; ++i)
+          w1[i] = w[i] + dt * (R[3 * i] * ab[0] + R[3 * i + 1] * ab[1] + R[3 * i + 2] * ab[2]);
+      }
+  #pragma unroll
+      for (int i = 0; i < 3; ++i) c1[i] = c[i] + dt * v1[i];
+      {
+        const float th0 = dt * w1[0], th1 = dt * w1[1], th2 = dt * w1[2];
+        const float ang2 = th0 * th0 + th1 * th1 + th2 * th2;
+        if (ang2 < 1e-24f) {
+          dq[0] = 1.f; dq[1] = 0.5f * th0; dq[2] = 0.5f * th1; dq[3] = 0.5f * th2;
+        } else {
+          const float ang = __builtin_amdgcn_sqrtf(ang2);
+          float sh, ch;
+          sin_cos(0.5f * ang, &sh, &ch);
+          const float k = sh * rcp(ang);
+          dq[0] = ch; dq[1] = k * th0; dq[2] = k * th1; dq[3] = k * th2;
+        }
+        Q1[0] = dq[0] * Q[0] - dq[1] * Q[1] - dq[2] * Q[2] - dq[3] * Q[3];
+        Q1[1] = dq[0] * Q[1] + dq[1] * Q[0] + dq[2] * Q[3] - dq[3] * Q[2];
+        Q1[2] = dq[0] * Q[2] - dq[1] * Q[3] + dq[2] * Q[0] + dq[3] * Q[1];
+        Q1[3] = dq[0] * Q[3] + dq[1] * Q[2] - dq[2] * Q[1] + dq[3] * Q[0];
+        const float inv = __builtin_amdgcn_rsqf(Q1[0] * Q1[0] + Q1[1] * Q1[1] + Q1[2] * Q1[2] +
+                                                Q1[3] * Q1[3]);
+  #pragma unroll
+        for (int i = 0; i < 4; ++i) Q1[i] *= inv;
+      }
+      float R1[9];
+      quat_to_mat(Q1[0], Q1[1], Q1[2], Q1[3], R1);
+      // R(dq) - 1 = 2 w [v]x + 2 [v]x^2 for the unit increment dq = (w, v)
+      float Eb[9];
+      {
+        const float w0 = dq[0], x = dq[1], y = dq[2], z = dq[3];
+        Eb[0] = -2.f * (y * y + z * z); Eb[1] = 2.f * (x * y - w0 * z); Eb[2] = 2.f * (x * z + w0 * y);
+        Eb[3] = 2.f * (x * y + w0 * z); Eb[4] = -2.f * (x * x + z * z); Eb[5] = 2.f * (y * z - w0 * x);
+        Eb[6] = 2.f * (x * z - w0 * y); Eb[7] = 2.f * (y * z + w0 * x); Eb[8] = -2.f * (x * x + y * y);
+      }
+
+      // S5 + S6 moments over the friction set in the ground plane about the
+      // predicted CoG c1: source xi = P^n - c1 = R r_old - (c1 - c), slip
+      // delta = P* - P^n. The normal equations (4)-(6) need n, sum xi,
+      // sum |xi|^2, sum delta and sum xi x delta.
+      //
+      // Only points in contact at P^n can be in the friction set, and they are
+      // few (the feet), so they are first compacted into an LDS list (slot by
+      // slot, in lane order) and the segment's lanes then share the list: one
+      // pass of G candidates instead of PPL mostly idle slots.
+      int n_cand = 0;
+  #pragma unroll
+      for (int p = 0; p < PPL; ++p) {
+        const bool hit = (kap >> p) & 1u;
+        const unsigned long long m = seg_bits<G>(__ballot(hit), seg);
+        if (hit) cand[n_cand + __popcll(m & ((1ull << sl) - 1ull))] = sl + p * G;
+        n_cand += __popcll(m);
+      }
+      __builtin_amdgcn_wave_barrier();
+      const float dcx = c1[0] - c[0], dcy = c1[1] - c[1];
+      float mn = 0.f, Sx = 0.f, Sy = 0.f, S2 = 0.f, Dx = 0.f, Dy = 0.f, Cd = 0.f;
+      for (int e = sl; e < n_cand; e += G) {
+        const int kk = pt_off + cand[e];
+        const float4 rho = a.pts[kk];
+        const int lk = a.pt_link[kk];
+        // r = T rho - g_b at the new joint angles, and its increment this frame
+        const float4 t0 = T[lk][0], t1 = T[lk][1], t2 = T[lk][2];
+        const float rx = t0.x * rho.x + t0.y * rho.y + t0.z * rho.z + t0.w - gb[0];
+        const float ry = t1.x * rho.x + t1.y * rho.y + t1.z * rho.z + t1.w - gb[1];
+        const float rz = t2.x * rho.x + t2.y * rho.y + t2.z * rho.z + t2.w - gb[2];
+        const float ux = R1[0] * rx + R1[1] * ry + R1[2] * rz;
+        const float uy = R1[3] * rx + R1[4] * ry + R1[5] * rz;
+        const float uz = R1[6] * rx + R1[7] * ry + R1[8] * rz;
+        const float Px = c1[0] + ux, Py = c1[1] + uy, Pz = c1[2] + uz;
+        if (hf_at(a, Px, Py) - Pz > 0.f) {
+          float drx = 0.f, dry = 0.f, drz = 0.f;
+          if (fk_now) {
+            const float4 d0 = dT[lk][0], d1 = dT[lk][1], d2 = dT[lk][2];
+            drx = d0.x * rho.x + d0.y * rho.y + d0.z * rho.z + d0.w - dgb[0];
+            dry = d1.x * rho.x + d1.y * rho.y + d1.z * rho.z + d1.w - dgb[1];
+            drz = d2.x * rho.x + d2.y * rho.y + d2.z * rho.z + d2.w - dgb[2];
+          }
+          const float ox = rx - drx, oy = ry - dry, oz = rz - drz;  // r_old
+          const float Ux = R[0] * ox + R[1] * oy + R[2] * oz;
+          const float Uy = R[3] * ox + R[4] * oy + R[5] * oz;
+          const float Uz = R[6] * ox + R[7] * oy + R[8] * oz;
+          const float sx = Ux - dcx, sy = Uy - dcy;
+          const float dx = (Eb[0] * Ux + Eb[1] * Uy + Eb[2] * Uz) +
+                           (R1[0] * drx + R1[1] * dry + R1[2] * drz) + dcx;
+          const float dy = (Eb[3] * Ux + Eb[4] * Uy + Eb[5] * Uz) +
+                           (R1[3] * drx + R1[4] * dry + R1[5] * drz) + dcy;
+          mn += 1.f;
+          Sx += sx;
+          Sy += sy;
+          S2 += sx * sx + sy * sy;
+          Dx += dx;
+          Dy += dy;
+          Cd += sx * dy - sy * dx;
+        }
+      }
+      mn = seg_sum<G>(mn);
+      Sx = seg_sum<G>(Sx);
+      Sy = seg_sum<G>(Sy);
+      S2 = seg_sum<G>(S2);
+      Dx = seg_sum<G>(Dx);
+      Dy = seg_sum<G>(Dy);
+      Cd = seg_sum<G>(Cd);
+
+      // S6 closed form of eqs. (4)-(6) and S7 static-friction cap. In these
+      // moments a3 = [sum xi x delta - (Sx Dy - Sy Dx)/n] / (sum |xi|^2 - |S|^2/n),
+      // a = (D + a3 J^T S)/n, the mean slip is D/n.
+      float a1 = 0.f, a2 = 0.f, a3 = 0.f, lam = 0.f;
+      if (mn > 0.f) {
+        const float inv_n = rcp(mn);
+        const float D = S2 - (Sx * Sx + Sy * Sy) * inv_n;
+        if (mn >= 2.f && D > mn * a.eps * a.eps) a3 = (Cd - (Sx * Dy - Sy * Dx) * inv_n) * rcp(D);
+        a1 = (Dx + Sy * a3) * inv_n;
+        a2 = (Dy - Sx * a3) * inv_n;
+        const float sbx = Dx * inv_n, sby = Dy * inv_n;
+        const float Ff = M * __builtin_amdgcn_sqrtf(sbx * sbx + sby * sby) * (inv_dt * inv_dt);
+        lam = (a.mu_inf || Ff <= a.mu * F) ? 1.f : a.mu * F * rcp(Ff);
+      }
+
+      // S8 correction and commit
+      const float alpha = asinf(fminf(fmaxf(a3, -1.f), 1.f));
+      float Q2[4];
+      {
+        float sh, ch;
+        sin_cos(-0.5f * lam * alpha, &sh, &ch);
+        Q2[0] = ch * Q1[0] - sh * Q1[3];
+        Q2[1] = ch * Q1[1] - sh * Q1[2];
+        Q2[2] = ch * Q1[2] + sh * Q1[1];
+        Q2[3] = ch * Q1[3] + sh * Q1[0];
+      }
+      const float c2[3] = {c1[0] - lam * a1, c1[1] - lam * a2, c1[2]};
+      const float v2[3] = {v1[0] - lam * a1 * inv_dt, v1[1] - lam * a2 * inv_dt, v1[2]};
+      const float w2[3] = {w1[0], w1[1], w1[2] - lam * alpha * inv_dt};
+
+      // S9 telemetry and health
+      float R2[9];
+      quat_to_mat(Q2[0], Q2[1], Q2[2], Q2[3], R2);
+      const float ox = c2[0] - (R2[0] * gb[0] + R2[1] * gb[1] + R2[2] * gb[2]);
+      const float oy = c2[1] - (R2[3] * gb[0] + R2[4] * gb[1] + R2[5] * gb[2]);
+      const float oz = c2[2] - (R2[6] * gb[0] + R2[7] * gb[1] + R2[8] * gb[2]);
+      const float th = oz - hf_at(a, ox, oy);
+      bool fin = true;
+  #pragma unroll
+      for (int i = 0; i < 3; ++i) fin = fin && isfinite(c2[i]) && isfinite(v2[i]) && isfinite(w2[i]);
+  #pragma unroll
+      for (int i = 0; i < 4; ++i) fin = fin && isfinite(Q2[i]);
+      const float vv = v2[0] * v2[0] + v2[1] * v2[1] + v2[2] * v2[2];
+      const float ww = w2[0] * w2[0] + w2[1] * w2[1] + w2[2] * w2[2];
+      const int bad = (fin ? 0 : 1) | ((vv > 2500.f || ww > 250000.f) ? 2 : 0);
+
+      if (active) {
+  #pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          c[i] = c2[i];
+          v[i] = v2[i];
+          w[i] = w2[i];
+        }
+  #pragma unroll
+        for (int i = 0; i < 4; ++i) Q[i] = Q2[i];
+        tele[0] += (double)th;
+        tele[1] += (double)nc;
+        tele[2] += (mn > 0.f && lam < 1.f) ? 1.0 : 0.0;
+        fl = bad;
+        n += 1;
+      }
+    }
+    if (MODE != kStep || s == a.n_steps) break;
+    const bool active = valid && fl == 0;
+    float R[9];
+    quat_to_mat(Q[0], Q[1], Q[2], Q[3], R);
+
+    // S1 + S2: detection at P^n and normal forces.
+    // Broad phase: a link whose bounding sphere lies wholly above the highest
+    // entry of the height map has no point in contact, so its points are not
+    // tested (they would add exactly nothing); a point slot no lane of the
+    // wave needs is skipped as a whole.
+#pragma unroll
+    for (int l = 0; l < LPL; ++l) {
+      const int li = sl + l * G;
+      if (lv[l]) {
+        const float4 r0 = T[li][0], r1 = T[li][1], r2 = T[li][2];
+        const float* sc = k_sph[l];
+        const float y0 = r0.x * sc[0] + r0.y * sc[1] + r0.z * sc[2] + r0.w - gb[0];
+        const float y1 = r1.x * sc[0] + r1.y * sc[1] + r1.z * sc[2] + r1.w - gb[1];
+        const float y2 = r2.x * sc[0] + r2.y * sc[1] + r2.z * sc[2] + r2.w - gb[2];
+        const float zc = c[2] + (R[6] * y0 + R[7] * y1 + R[8] * y2);
+        touch[li] = (zc - sc[3] <= a.hf_max + 1e-3f) ? 1 : 0;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    kap = 0u;
+    F = 0.f;
+    tx = 0.f;
+    ty = 0.f;
+    nc = 0.f;
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+      const int k = sl + p * G;
+      const bool ok = k < N;
+      const int kk = pt_off + (ok ? k : 0);
+      const int lk = ok ? a.pt_link[kk] : 0;
+      if (ok && touch[lk]) {
+        const float4 rho = a.pts[kk];
+        const float4 r0 = T[lk][0], r1 = T[lk][1], r2 = T[lk][2];
+        const float rx = r0.x * rho.x + r0.y * rho.y + r0.z * rho.z + r0.w - gb[0];
+        const float ry = r1.x * rho.x + r1.y * rho.y + r1.z * rho.z + r1.w - gb[1];
+        const float rz = r2.x * rho.x + r2.y * rho.y + r2.z * rho.z + r2.w - gb[2];
+        const float ux = R[0] * rx + R[1] * ry + R[2] * rz;
+        const float uy = R[3] * rx + R[4] * ry + R[5] * rz;
+        const float uz = R[6] * rx + R[7] * ry + R[8] * rz;
+        const float Px = c[0] + ux, Py = c[1] + uy, Pz = c[2] + uz;
+        const float d = hf_at(a, Px, Py) - Pz;
+        if (d > 0.f) {
+          kap |= 1u << p;
+          const float vz = v[2] + (w[0] * uy - w[1] * ux);
+          const float f = fmaxf(a.kn * d * (1.f - a.zeta * vz), 0.f);
+          F += f;
+          tx += uy * f;
+          ty -= ux * f;
+          nc += 1.f;
+        }
+      }
+      group_fence(p);
+    }
+    F = seg_sum<G>(F);
+    tx = seg_sum<G>(tx);
+    ty = seg_sum<G>(ty);
+    nc = seg_sum<G>(nc);
+
+    // S3: joint-angle determination every K frames (c, Q, v, w kept)
+    const bool upd = (n % a.K) == 0;
+    fk_now = __any(upd);
+    if (fk_now) {
+      const bool take = upd && active;
+#pragma unroll
+      for (int l = 0; l < LPL; ++l) {
+        const float qn = command(l);
+        dql[l] = take ? qn - q[l] : 0.f;
+        qp[l] = take ? q[l] : qp[l];
+        q[l] = take ? qn : q[l];
+      }
+      fk_pending = true;
+    }
+  }
 
   if (MODE == kPlace) {
     float R[9];
@@ -416,245 +713,6 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
         o[1] = c[1] + (R[3] * r[0] + R[4] * r[1] + R[5] * r[2]);
         o[2] = c[2] + (R[6] * r[0] + R[7] * r[1] + R[8] * r[2]);
       }
-    }
-  }
-
-  const float dt = a.dt, inv_dt = a.inv_dt;
-  for (int s = 0; s < (MODE == kStep ? a.n_steps : 0); ++s) {
-    const bool active = valid && fl == 0;
-    float R[9];
-    quat_to_mat(Q[0], Q[1], Q[2], Q[3], R);
-
-    // S1 + S2: detection at P^n and normal forces
-    unsigned kap = 0u;
-    float F = 0.f, tx = 0.f, ty = 0.f, nc = 0.f;
-#pragma unroll
-    for (int p = 0; p < PPL; ++p) {
-      const int k = sl + p * G;
-      float r[3];
-      const bool ok = body_point(k, r);
-      const float ux = R[0] * r[0] + R[1] * r[1] + R[2] * r[2];
-      const float uy = R[3] * r[0] + R[4] * r[1] + R[5] * r[2];
-      const float uz = R[6] * r[0] + R[7] * r[1] + R[8] * r[2];
-      const float Px = c[0] + ux, Py = c[1] + uy, Pz = c[2] + uz;
-      if (ok) {
-        const float d = hf_at(a, Px, Py) - Pz;
-        if (d > 0.f) {
-          kap |= 1u << p;
-          const float vz = v[2] + (w[0] * uy - w[1] * ux);
-          const float f = fmaxf(a.kn * d * (1.f - a.zeta * vz), 0.f);
-          F += f;
-          tx += uy * f;
-          ty -= ux * f;
-          nc += 1.f;
-        }
-      }
-      group_fence(p);
-    }
-    F = seg_sum<G>(F);
-    tx = seg_sum<G>(tx);
-    ty = seg_sum<G>(ty);
-    nc = seg_sum<G>(nc);
-
-    // S3: joint-angle determination every K frames (c, Q, v, w kept)
-    const bool upd = (n % a.K) == 0;
-    const bool fk_now = __any(upd);
-    if (fk_now) {
-      const bool take = upd && active;
-#pragma unroll
-      for (int l = 0; l < LPL; ++l) {
-        const float qn = command(l);
-        dql[l] = take ? qn - q[l] : 0.f;
-        qp[l] = take ? q[l] : qp[l];
-        q[l] = take ? qn : q[l];
-      }
-      forward_kinematics(dql);
-    }
-
-    // S4: trial step. Body-frame Euler equation: I_b dw_b = tau_b - w_b x I_b w_b
-    float v1[3], w1[3], c1[3], Q1[4], dq[4];
-    v1[0] = v[0] + dt * a.gx;
-    v1[1] = v[1] + dt * a.gy;
-    v1[2] = v[2] + dt * (a.gz + F * invM);
-    {
-      const float wb[3] = {R[0] * w[0] + R[3] * w[1] + R[6] * w[2],
-                           R[1] * w[0] + R[4] * w[1] + R[7] * w[2],
-                           R[2] * w[0] + R[5] * w[1] + R[8] * w[2]};
-      const float tb_[3] = {R[0] * tx + R[3] * ty, R[1] * tx + R[4] * ty, R[2] * tx + R[5] * ty};
-      const float Lb[3] = {Ib[0] * wb[0] + Ib[3] * wb[1] + Ib[4] * wb[2],
-                           Ib[3] * wb[0] + Ib[1] * wb[1] + Ib[5] * wb[2],
-                           Ib[4] * wb[0] + Ib[5] * wb[1] + Ib[2] * wb[2]};
-      const float rb[3] = {tb_[0] - (wb[1] * Lb[2] - wb[2] * Lb[1]),
-                           tb_[1] - (wb[2] * Lb[0] - wb[0] * Lb[2]),
-                           tb_[2] - (wb[0] * Lb[1] - wb[1] * Lb[0])};
-      const float ab[3] = {Iinv[0] * rb[0] + Iinv[3] * rb[1] + Iinv[4] * rb[2],
-                           Iinv[3] * rb[0] + Iinv[1] * rb[1] + Iinv[5] * rb[2],
-                           Iinv[4] * rb[0] + Iinv[5] * rb[1] + Iinv[2] * rb[2]};
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-        w1[i] = w[i] + dt * (R[3 * i] * ab[0] + R[3 * i + 1] * ab[1] + R[3 * i + 2] * ab[2]);
-    }
-#pragma unroll
-    for (int i = 0; i < 3; ++i) c1[i] = c[i] + dt * v1[i];
-    {
-      const float th0 = dt * w1[0], th1 = dt * w1[1], th2 = dt * w1[2];
-      const float ang2 = th0 * th0 + th1 * th1 + th2 * th2;
-      if (ang2 < 1e-24f) {
-        dq[0] = 1.f; dq[1] = 0.5f * th0; dq[2] = 0.5f * th1; dq[3] = 0.5f * th2;
-      } else {
-        const float ang = __builtin_amdgcn_sqrtf(ang2);
-        float sh, ch;
-        sin_cos(0.5f * ang, &sh, &ch);
-        const float k = sh * rcp(ang);
-        dq[0] = ch; dq[1] = k * th0; dq[2] = k * th1; dq[3] = k * th2;
-      }
-      Q1[0] = dq[0] * Q[0] - dq[1] * Q[1] - dq[2] * Q[2] - dq[3] * Q[3];
-      Q1[1] = dq[0] * Q[1] + dq[1] * Q[0] + dq[2] * Q[3] - dq[3] * Q[2];
-      Q1[2] = dq[0] * Q[2] - dq[1] * Q[3] + dq[2] * Q[0] + dq[3] * Q[1];
-      Q1[3] = dq[0] * Q[3] + dq[1] * Q[2] - dq[2] * Q[1] + dq[3] * Q[0];
-      const float inv = __builtin_amdgcn_rsqf(Q1[0] * Q1[0] + Q1[1] * Q1[1] + Q1[2] * Q1[2] +
-                                              Q1[3] * Q1[3]);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) Q1[i] *= inv;
-    }
-    float R1[9];
-    quat_to_mat(Q1[0], Q1[1], Q1[2], Q1[3], R1);
-    // R(dq) - 1 = 2 w [v]x + 2 [v]x^2 for the unit increment dq = (w, v)
-    float Eb[9];
-    {
-      const float w0 = dq[0], x = dq[1], y = dq[2], z = dq[3];
-      Eb[0] = -2.f * (y * y + z * z); Eb[1] = 2.f * (x * y - w0 * z); Eb[2] = 2.f * (x * z + w0 * y);
-      Eb[3] = 2.f * (x * y + w0 * z); Eb[4] = -2.f * (x * x + z * z); Eb[5] = 2.f * (y * z - w0 * x);
-      Eb[6] = 2.f * (x * z - w0 * y); Eb[7] = 2.f * (y * z + w0 * x); Eb[8] = -2.f * (x * x + y * y);
-    }
-
-    // S5 + S6 moments over the friction set in the ground plane about the
-    // predicted CoG c1: source xi = P^n - c1 = R r_old - (c1 - c), slip
-    // delta = P* - P^n. The normal equations (4)-(6) need n, sum xi,
-    // sum |xi|^2, sum delta and sum xi x delta.
-    //
-    // Only points in contact at P^n can be in the friction set, and they are
-    // few (the feet), so they are first compacted into an LDS list (slot by
-    // slot, in lane order) and the segment's lanes then share the list: one
-    // pass of G candidates instead of PPL mostly idle slots.
-    int n_cand = 0;
-#pragma unroll
-    for (int p = 0; p < PPL; ++p) {
-      const bool hit = (kap >> p) & 1u;
-      const unsigned long long m = seg_bits<G>(__ballot(hit), seg);
-      if (hit) cand[n_cand + __popcll(m & ((1ull << sl) - 1ull))] = sl + p * G;
-      n_cand += __popcll(m);
-    }
-    __builtin_amdgcn_wave_barrier();
-    const float dcx = c1[0] - c[0], dcy = c1[1] - c[1];
-    float mn = 0.f, Sx = 0.f, Sy = 0.f, S2 = 0.f, Dx = 0.f, Dy = 0.f, Cd = 0.f;
-    for (int e = sl; e < n_cand; e += G) {
-      const int kk = pt_off + cand[e];
-      const float4 rho = a.pts[kk];
-      const int lk = a.pt_link[kk];
-      // r = T rho - g_b at the new joint angles, and its increment this frame
-      const float4 t0 = T[lk][0], t1 = T[lk][1], t2 = T[lk][2];
-      const float rx = t0.x * rho.x + t0.y * rho.y + t0.z * rho.z + t0.w - gb[0];
-      const float ry = t1.x * rho.x + t1.y * rho.y + t1.z * rho.z + t1.w - gb[1];
-      const float rz = t2.x * rho.x + t2.y * rho.y + t2.z * rho.z + t2.w - gb[2];
-      const float ux = R1[0] * rx + R1[1] * ry + R1[2] * rz;
-      const float uy = R1[3] * rx + R1[4] * ry + R1[5] * rz;
-      const float uz = R1[6] * rx + R1[7] * ry + R1[8] * rz;
-      const float Px = c1[0] + ux, Py = c1[1] + uy, Pz = c1[2] + uz;
-      if (hf_at(a, Px, Py) - Pz > 0.f) {
-        float drx = 0.f, dry = 0.f, drz = 0.f;
-        if (fk_now) {
-          const float4 d0 = dT[lk][0], d1 = dT[lk][1], d2 = dT[lk][2];
-          drx = d0.x * rho.x + d0.y * rho.y + d0.z * rho.z + d0.w - dgb[0];
-          dry = d1.x * rho.x + d1.y * rho.y + d1.z * rho.z + d1.w - dgb[1];
-          drz = d2.x * rho.x + d2.y * rho.y + d2.z * rho.z + d2.w - dgb[2];
-        }
-        const float ox = rx - drx, oy = ry - dry, oz = rz - drz;  // r_old
-        const float Ux = R[0] * ox + R[1] * oy + R[2] * oz;
-        const float Uy = R[3] * ox + R[4] * oy + R[5] * oz;
-        const float Uz = R[6] * ox + R[7] * oy + R[8] * oz;
-        const float sx = Ux - dcx, sy = Uy - dcy;
-        const float dx = (Eb[0] * Ux + Eb[1] * Uy + Eb[2] * Uz) +
-                         (R1[0] * drx + R1[1] * dry + R1[2] * drz) + dcx;
-        const float dy = (Eb[3] * Ux + Eb[4] * Uy + Eb[5] * Uz) +
-                         (R1[3] * drx + R1[4] * dry + R1[5] * drz) + dcy;
-        mn += 1.f;
-        Sx += sx;
-        Sy += sy;
-        S2 += sx * sx + sy * sy;
-        Dx += dx;
-        Dy += dy;
-        Cd += sx * dy - sy * dx;
-      }
-    }
-    mn = seg_sum<G>(mn);
-    Sx = seg_sum<G>(Sx);
-    Sy = seg_sum<G>(Sy);
-    S2 = seg_sum<G>(S2);
-    Dx = seg_sum<G>(Dx);
-    Dy = seg_sum<G>(Dy);
-    Cd = seg_sum<G>(Cd);
-
-    // S6 closed form of eqs. (4)-(6) and S7 static-friction cap. In these
-    // moments a3 = [sum xi x delta - (Sx Dy - Sy Dx)/n] / (sum |xi|^2 - |S|^2/n),
-    // a = (D + a3 J^T S)/n, the mean slip is D/n.
-    float a1 = 0.f, a2 = 0.f, a3 = 0.f, lam = 0.f;
-    if (mn > 0.f) {
-      const float inv_n = rcp(mn);
-      const float D = S2 - (Sx * Sx + Sy * Sy) * inv_n;
-      if (mn >= 2.f && D > mn * a.eps * a.eps) a3 = (Cd - (Sx * Dy - Sy * Dx) * inv_n) * rcp(D);
-      a1 = (Dx + Sy * a3) * inv_n;
-      a2 = (Dy - Sx * a3) * inv_n;
-      const float sbx = Dx * inv_n, sby = Dy * inv_n;
-      const float Ff = M * __builtin_amdgcn_sqrtf(sbx * sbx + sby * sby) * (inv_dt * inv_dt);
-      lam = (a.mu_inf || Ff <= a.mu * F) ? 1.f : a.mu * F * rcp(Ff);
-    }
-
-    // S8 correction and commit
-    const float alpha = asinf(fminf(fmaxf(a3, -1.f), 1.f));
-    float Q2[4];
-    {
-      float sh, ch;
-      sin_cos(-0.5f * lam * alpha, &sh, &ch);
-      Q2[0] = ch * Q1[0] - sh * Q1[3];
-      Q2[1] = ch * Q1[1] - sh * Q1[2];
-      Q2[2] = ch * Q1[2] + sh * Q1[1];
-      Q2[3] = ch * Q1[3] + sh * Q1[0];
-    }
-    const float c2[3] = {c1[0] - lam * a1, c1[1] - lam * a2, c1[2]};
-    const float v2[3] = {v1[0] - lam * a1 * inv_dt, v1[1] - lam * a2 * inv_dt, v1[2]};
-    const float w2[3] = {w1[0], w1[1], w1[2] - lam * alpha * inv_dt};
-
-    // S9 telemetry and health
-    float R2[9];
-    quat_to_mat(Q2[0], Q2[1], Q2[2], Q2[3], R2);
-    const float ox = c2[0] - (R2[0] * gb[0] + R2[1] * gb[1] + R2[2] * gb[2]);
-    const float oy = c2[1] - (R2[3] * gb[0] + R2[4] * gb[1] + R2[5] * gb[2]);
-    const float oz = c2[2] - (R2[6] * gb[0] + R2[7] * gb[1] + R2[8] * gb[2]);
-    const float th = oz - hf_at(a, ox, oy);
-    bool fin = true;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) fin = fin && isfinite(c2[i]) && isfinite(v2[i]) && isfinite(w2[i]);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) fin = fin && isfinite(Q2[i]);
-    const float vv = v2[0] * v2[0] + v2[1] * v2[1] + v2[2] * v2[2];
-    const float ww = w2[0] * w2[0] + w2[1] * w2[1] + w2[2] * w2[2];
-    const int bad = (fin ? 0 : 1) | ((vv > 2500.f || ww > 250000.f) ? 2 : 0);
-
-    if (active) {
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        c[i] = c2[i];
-        v[i] = v2[i];
-        w[i] = w2[i];
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) Q[i] = Q2[i];
-      tele[0] += (double)th;
-      tele[1] += (double)nc;
-      tele[2] += (mn > 0.f && lam < 1.f) ? 1.0 : 0.0;
-      fl = bad;
-      n += 1;
     }
   }
 
@@ -704,6 +762,7 @@ void step_kernel(const StepArgs a) {
   __shared__ LinkT T[IPW][LMAX];
   __shared__ LinkT dT[IPW][LMAX];
   __shared__ int cand[IPW][G * PPL];  // contact points of a frame, compacted
+  __shared__ int touch[IPW][LMAX];    // links that may reach the ground this frame
   const int lane = threadIdx.x;
   const int seg = lane / G;
   const int sl = lane - seg * G;
@@ -718,7 +777,7 @@ void step_kernel(const StepArgs a) {
       tb = blockIdx.x;
     }
     if (tb >= a.n_blocks) break;
-    run_block<G, PPL, LPL, MODE>(a, T[seg], dT[seg], cand[seg], tb, seg, sl);
+    run_block<G, PPL, LPL, MODE>(a, T[seg], dT[seg], cand[seg], touch[seg], tb, seg, sl);
     __syncthreads();
   }
 }

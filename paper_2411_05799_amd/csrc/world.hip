@@ -338,6 +338,26 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
       row[npx::LK_MASS] = (float)lm[l];
       for (int i = 0; i < 3; ++i) row[npx::LK_COG + i] = (float)lc[3 * l + i];
       for (int i = 0; i < 6; ++i) row[npx::LK_INERTIA + i] = (float)lI[6 * l + i];
+      // bounding sphere of the link's points about their mean (radius rounded up)
+      {
+        double cen[3] = {0, 0, 0};
+        int cnt = 0;
+        for (int k = 0; k < m.n_points; ++k)
+          if (m.pt_link[k] == l) {
+            for (int i = 0; i < 3; ++i) cen[i] += m.points[4 * k + i];
+            ++cnt;
+          }
+        for (int i = 0; i < 3; ++i) cen[i] = cnt ? cen[i] / cnt : 0.0;
+        double rad = 0.0;
+        for (int k = 0; k < m.n_points; ++k)
+          if (m.pt_link[k] == l) {
+            double d2 = 0.0;
+            for (int i = 0; i < 3; ++i) d2 += (m.points[4 * k + i] - cen[i]) * (m.points[4 * k + i] - cen[i]);
+            rad = std::max(rad, std::sqrt(d2));
+          }
+        for (int i = 0; i < 3; ++i) row[npx::LK_SPHERE + i] = (float)cen[i];
+        row[npx::LK_SPHERE + 3] = (float)(rad * (1.0 + 1e-6) + 1e-6);
+      }
       lk.insert(lk.end(), row, row + npx::LINK_F);
     }
   }
@@ -463,6 +483,8 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   a.hf_s = (float)d->hf_s;
   a.hf_x0 = (float)d->hf_x0;
   a.hf_y0 = (float)d->hf_y0;
+  a.hf_max = -INFINITY;
+  for (size_t k = 0; k < (size_t)d->hf_nx * d->hf_ny; ++k) a.hf_max = std::max(a.hf_max, d->hf_heights[k]);
   a.st = w->st;
   a.step = w->step;
   a.flags = w->flags;
