@@ -15,10 +15,10 @@ npx_status fail(npx_status s, const char* fmt, ...);
 // Link table row (LINK_F floats): hinge anchor [0..2], axis [3..5], lower and
 // upper limit [6..7], link mass [8], link CoG in the construction frame
 // [9..11], inertia about the link CoG in construction axes [12..17]
-// (xx yy zz xy xz yz), a sphere holding all the link's points in the
-// construction frame [18..21] (centre, radius).
-constexpr int LINK_F = 22;
-constexpr int LK_MASS = 8, LK_COG = 9, LK_INERTIA = 12, LK_SPHERE = 18;
+// (xx yy zz xy xz yz), the box holding all the link's points in the
+// construction frame [18..23] (centre, half extents along x y z).
+constexpr int LINK_F = 24;
+constexpr int LK_MASS = 8, LK_COG = 9, LK_INERTIA = 12, LK_BOX = 18;
 constexpr int TELE_N = 4;
 constexpr int BODY_ROWS = 13;  // c(3) Q(4) v(3) w(3)
 

@@ -145,7 +145,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
   // unit axis, limits, mass, CoG and inertia, tree depth and parent, and the
   // joint's controller (amplitude, frequency, phase in turns)
   float k_ao[LPL][3], k_ax[LPL][3], k_lo[LPL], k_hi[LPL], k_m[LPL], k_c[LPL][3], k_I[LPL][6];
-  float k_sph[LPL][4];  // bounding sphere of the link's points: centre, radius
+  float k_box[LPL][6];  // box of the link's points: centre, half extents
   float k_A[LPL], k_f[LPL];
   double k_ph[LPL];
   int k_dep[LPL], k_par[LPL];
@@ -166,7 +166,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
 #pragma unroll
     for (int i = 0; i < 6; ++i) k_I[l][i] = lk[LK_INERTIA + i];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) k_sph[l][i] = lk[LK_SPHERE + i];
+    for (int i = 0; i < 6; ++i) k_box[l][i] = lk[LK_BOX + i];
     k_lo[l] = lk[6];
     k_hi[l] = lk[7];
     k_m[l] = lk[LK_MASS];
@@ -620,21 +620,26 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
     quat_to_mat(Q[0], Q[1], Q[2], Q[3], R);
 
     // S1 + S2: detection at P^n and normal forces.
-    // Broad phase: a link whose bounding sphere lies wholly above the highest
+    // Broad phase: a link whose box of points lies wholly above the highest
     // entry of the height map has no point in contact, so its points are not
     // tested (they would add exactly nothing); a point slot no lane of the
-    // wave needs is skipped as a whole.
+    // wave needs is skipped as a whole. The box's lowest world height is its
+    // centre's minus sum_j |w_j| e_j, w = the world z row of the link's axes.
 #pragma unroll
     for (int l = 0; l < LPL; ++l) {
       const int li = sl + l * G;
       if (lv[l]) {
         const float4 r0 = T[li][0], r1 = T[li][1], r2 = T[li][2];
-        const float* sc = k_sph[l];
-        const float y0 = r0.x * sc[0] + r0.y * sc[1] + r0.z * sc[2] + r0.w - gb[0];
-        const float y1 = r1.x * sc[0] + r1.y * sc[1] + r1.z * sc[2] + r1.w - gb[1];
-        const float y2 = r2.x * sc[0] + r2.y * sc[1] + r2.z * sc[2] + r2.w - gb[2];
+        const float* bx = k_box[l];
+        const float y0 = r0.x * bx[0] + r0.y * bx[1] + r0.z * bx[2] + r0.w - gb[0];
+        const float y1 = r1.x * bx[0] + r1.y * bx[1] + r1.z * bx[2] + r1.w - gb[1];
+        const float y2 = r2.x * bx[0] + r2.y * bx[1] + r2.z * bx[2] + r2.w - gb[2];
         const float zc = c[2] + (R[6] * y0 + R[7] * y1 + R[8] * y2);
-        touch[li] = (zc - sc[3] <= a.hf_max + 1e-3f) ? 1 : 0;
+        const float wx = R[6] * r0.x + R[7] * r1.x + R[8] * r2.x;
+        const float wy = R[6] * r0.y + R[7] * r1.y + R[8] * r2.y;
+        const float wz = R[6] * r0.z + R[7] * r1.z + R[8] * r2.z;
+        const float ez = fabsf(wx) * bx[3] + fabsf(wy) * bx[4] + fabsf(wz) * bx[5];
+        touch[li] = (zc - ez <= a.hf_max + 1e-3f) ? 1 : 0;
       }
     }
     __builtin_amdgcn_wave_barrier();

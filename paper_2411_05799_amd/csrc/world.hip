@@ -338,25 +338,20 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
       row[npx::LK_MASS] = (float)lm[l];
       for (int i = 0; i < 3; ++i) row[npx::LK_COG + i] = (float)lc[3 * l + i];
       for (int i = 0; i < 6; ++i) row[npx::LK_INERTIA + i] = (float)lI[6 * l + i];
-      // bounding sphere of the link's points about their mean (radius rounded up)
+      // box holding the link's points in the construction frame (rounded outward)
       {
-        double cen[3] = {0, 0, 0};
-        int cnt = 0;
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
         for (int k = 0; k < m.n_points; ++k)
-          if (m.pt_link[k] == l) {
-            for (int i = 0; i < 3; ++i) cen[i] += m.points[4 * k + i];
-            ++cnt;
-          }
-        for (int i = 0; i < 3; ++i) cen[i] = cnt ? cen[i] / cnt : 0.0;
-        double rad = 0.0;
-        for (int k = 0; k < m.n_points; ++k)
-          if (m.pt_link[k] == l) {
-            double d2 = 0.0;
-            for (int i = 0; i < 3; ++i) d2 += (m.points[4 * k + i] - cen[i]) * (m.points[4 * k + i] - cen[i]);
-            rad = std::max(rad, std::sqrt(d2));
-          }
-        for (int i = 0; i < 3; ++i) row[npx::LK_SPHERE + i] = (float)cen[i];
-        row[npx::LK_SPHERE + 3] = (float)(rad * (1.0 + 1e-6) + 1e-6);
+          if (m.pt_link[k] == l)
+            for (int i = 0; i < 3; ++i) {
+              lo[i] = std::min(lo[i], (double)m.points[4 * k + i]);
+              hi[i] = std::max(hi[i], (double)m.points[4 * k + i]);
+            }
+        for (int i = 0; i < 3; ++i) {
+          if (!(lo[i] <= hi[i])) lo[i] = hi[i] = 0.0;  // a link without points
+          row[npx::LK_BOX + i] = (float)(0.5 * (lo[i] + hi[i]));
+          row[npx::LK_BOX + 3 + i] = (float)(0.5 * (hi[i] - lo[i]) * (1.0 + 1e-6) + 1e-6);
+        }
       }
       lk.insert(lk.end(), row, row + npx::LINK_F);
     }
