@@ -295,6 +295,14 @@ npx_status npx_sur_grad(npx_sur* s, const float* x, int64_t ldx, const float* y,
 npx_status npx_sur_train_step(npx_sur* s, const float* x, int64_t ldx, const float* y,
                               int64_t ldy, const int32_t* rows, int64_t batch, double lr,
                               float* loss, void* stream);
+/* Training noise: while set, every npx_sur_grad / npx_sur_train_step call adds
+ * noise[b][j] (device, [batch][ldn], raw units) to input column col0 + j of
+ * batch row b and subtracts it from target column col0 + j, so that the network
+ * learns to return a perturbed state to the recorded next state (the columns
+ * must exist in both).  The caller owns the buffer and refills it between
+ * calls; noise == NULL switches it off.  Inference never sees it. */
+npx_status npx_sur_set_noise(npx_sur* s, const float* noise, int64_t ldn, int32_t col0,
+                             int32_t ncols);
 /* Column means and population standard deviations (FP64 accumulation) of a
  * device matrix x [rows][ldx], first `cols` columns, into device arrays
  * mean, std [cols].  Synchronises `stream`. */

@@ -229,11 +229,20 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<T> g) {
 
 // ---- layer-0 input: gather rows, standardise, pad, write X and X^T ---------
 // Block: 64 rows x 64 columns through an LDS tile.
+// Training noise (optional): noise[r][j] is added to input column nc0 + j of
+// batch row r before standardisation (and subtracted from the same target
+// column by the loss kernel).
+struct Noise {
+  const float* v;
+  int64_t ld;
+  int c0, n;
+};
+
 template <class T>
 __global__ __launch_bounds__(256) void pack_input_kernel(
     const float* __restrict__ x, int64_t ldx, const int* __restrict__ rows, int batch, int n_in,
     const float* __restrict__ mean, const float* __restrict__ inv_std, T* X, int64_t ldX, T* XT,
-    int64_t ldXT) {
+    int64_t ldXT, Noise nz) {
   __shared__ float tile[64][65];
   const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
   const int tc = threadIdx.x & 63, tr = threadIdx.x >> 6;
@@ -242,7 +251,9 @@ __global__ __launch_bounds__(256) void pack_input_kernel(
     float v = 0.f;
     if (r < batch && c < n_in) {
       const int64_t src = rows ? (int64_t)rows[r] : (int64_t)r;
-      v = (x[src * ldx + c] - mean[c]) * inv_std[c];
+      float xr = x[src * ldx + c];
+      if (nz.v && c >= nz.c0 && c < nz.c0 + nz.n) xr += nz.v[(int64_t)r * nz.ld + (c - nz.c0)];
+      v = (xr - mean[c]) * inv_std[c];
     }
     tile[rr][tc] = v;
     X[(int64_t)r * ldX + c] = to_t<T>(v);
@@ -261,7 +272,7 @@ __global__ __launch_bounds__(256) void loss_kernel(
     const float* __restrict__ yhat, int64_t ldyh, const float* __restrict__ y, int64_t ldy,
     const int* __restrict__ rows, int batch, int n_out, const float* __restrict__ y_mean,
     const float* __restrict__ y_inv_std, float grad_scale, T* dY, int64_t lddy, T* dYT,
-    int64_t lddyt, float* colsum, int ncols, double* partial) {
+    int64_t lddyt, float* colsum, int ncols, double* partial, Noise nz) {
   __shared__ float tile[64][65];
   __shared__ double lsum[256];
   const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
@@ -273,7 +284,9 @@ __global__ __launch_bounds__(256) void loss_kernel(
     float d = 0.f;
     if (r < batch && c < n_out) {
       const int64_t src = rows ? (int64_t)rows[r] : (int64_t)r;
-      const float yn = (y[src * ldy + c] - y_mean[c]) * y_inv_std[c];
+      float yr = y[src * ldy + c];
+      if (nz.v && c >= nz.c0 && c < nz.c0 + nz.n) yr -= nz.v[(int64_t)r * nz.ld + (c - nz.c0)];
+      const float yn = (yr - y_mean[c]) * y_inv_std[c];
       const float e = yhat[(int64_t)r * ldyh + c] - yn;
       l2 += (double)e * e;
       d = grad_scale * e;
@@ -443,6 +456,7 @@ struct npx_sur {
   int64_t n_pad = 0, n_real = 0, n_wc = 0;
   int step = 0;
   double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+  Noise noise{nullptr, 0, 0, 0};
 
   // parameters: master, gradient, Adam moments (padded order), operand copies
   float *P = nullptr, *G = nullptr, *Mom = nullptr, *Vel = nullptr, *flat = nullptr;
@@ -545,7 +559,8 @@ npx_status forward_t(npx_sur* s, const float* x, int64_t ldx, const int* rows, i
     dim3 grid(Mp / TILE, s->in_p0 / TILE);
     hipLaunchKernelGGL((pack_input_kernel<T>), grid, dim3(256), 0, st, x, ldx, rows, batch,
                        s->n_in, s->x_mean, s->x_inv, static_cast<T*>(s->X0), (int64_t)s->in_p0,
-                       train ? static_cast<T*>(s->X0T) : nullptr, (int64_t)Mp);
+                       train ? static_cast<T*>(s->X0T) : nullptr, (int64_t)Mp,
+                       train ? s->noise : Noise{nullptr, 0, 0, 0});
     HIP_TRY(hipGetLastError());
   }
   const void* prev = s->X0;
@@ -600,7 +615,7 @@ npx_status backward_t(npx_sur* s, const float* x, int64_t ldx, const float* y, i
     hipLaunchKernelGGL((loss_kernel<T>), dim3(tiles_m, s->out_p / TILE), dim3(256), 0, st, s->Yhat,
                        (int64_t)s->out_p, y, ldy, rows, batch, s->n_out, s->y_mean, s->y_inv,
                        scale, static_cast<T*>(s->dA), (int64_t)s->out_p, static_cast<T*>(s->dAT),
-                       (int64_t)Mp, s->dbp[L], s->out_p, s->loss_part);
+                       (int64_t)Mp, s->dbp[L], s->out_p, s->loss_part, s->noise);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, st, s->loss_part,
                        tiles_m * (s->out_p / TILE),
@@ -931,6 +946,20 @@ npx_status npx_sur_train_step(npx_sur* s, const float* x, int64_t ldx, const flo
   if (r != NPX_OK) return r;
   s->step += 1;
   HIP_TRY(refresh(s, 1, (float)lr, (hipStream_t)stream));
+  return NPX_OK;
+}
+
+npx_status npx_sur_set_noise(npx_sur* s, const float* noise, int64_t ldn, int32_t col0,
+                             int32_t ncols) {
+  if (!s) return fail(NPX_EINVAL, "null surrogate handle");
+  if (!noise) {
+    s->noise = Noise{nullptr, 0, 0, 0};
+    return NPX_OK;
+  }
+  if (col0 < 0 || ncols < 1 || col0 + ncols > s->n_in || col0 + ncols > s->n_out || ldn < ncols)
+    return fail(NPX_EINVAL, "noise columns [%d, %d) must lie in both the inputs and the outputs",
+                col0, col0 + ncols);
+  s->noise = Noise{noise, ldn, col0, ncols};
   return NPX_OK;
 }
 

@@ -138,6 +138,8 @@ def lib():
         L.npx_sur_grad.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp, vp, vp]
         L.npx_sur_train_step.argtypes = [vp, vp, i64, vp, i64, vp, i64, d, vp, vp]
         L.npx_sur_norm_stats.argtypes = [vp, i64, i64, C.c_int32, vp, vp, vp]
+        L.npx_sur_set_noise.argtypes = [vp, vp, i64, C.c_int32, C.c_int32]
+        L.npx_sur_set_noise.restype = C.c_int
         L.npx_sur_widths.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.npx_world_rows.argtypes = [vp, vp, i64, vp]
         L.npx_sur_features.argtypes = [vp, vp, i64, i64, vp, i64, vp]
@@ -534,6 +536,15 @@ class Surrogate:
 
     def set_adam(self, beta1=0.9, beta2=0.999, eps=1e-8):
         check(lib().npx_sur_set_adam(self.h, beta1, beta2, eps))
+
+    def set_noise(self, noise=None, col0=0):
+        """Training noise [batch, ncols] added to inputs col0.. and taken off the
+        same target columns (None: off). Keep the tensor alive while set."""
+        self._noise = noise
+        if noise is None:
+            check(lib().npx_sur_set_noise(self.h, None, 0, 0, 0))
+        else:
+            check(lib().npx_sur_set_noise(self.h, _ptr(noise), noise.stride(0), col0, noise.shape[1]))
 
     def forward(self, x, out, rows=None, batch=None, stream=None):
         b = x.shape[0] if rows is None else rows.shape[0]

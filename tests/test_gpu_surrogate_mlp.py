@@ -173,8 +173,6 @@ def test_adam_step_fp32_matches_oracle():
         assert np.abs((got - p_new)[big]).max() <= 2e-3 * lr
         assert np.abs(got - p_new).max() <= 2.0 * lr + 1e-6
         p = got     # continue both from the GPU's parameters
-        opt_state = opt
-    del opt_state
     s.close()
 
 
@@ -244,3 +242,43 @@ def test_edge_cases_and_errors():
     s.close()
     with pytest.raises(N.NpxError):
         N.Surrogate(n_in=3, n_hidden=8, n_hidden_layers=0, n_out=1, max_batch=4)
+
+
+def test_training_noise_shifts_inputs_and_targets():
+    """With training noise set, the gradient is the oracle's on inputs + noise
+    and targets - noise in the same columns; inference ignores the noise."""
+    from paper_2411_05799_amd import native as N
+    torch = _torch()
+    rng = np.random.default_rng(31)
+    batch = 300
+    x, y, xm, xs, ym, ys = _data(rng, batch)
+    s = _make(N.SUR_FP32)
+    s.set_norm(xm, xs, ym, ys)
+    p = s.get_params().astype(np.float64)
+    nz = (rng.normal(size=(batch, 11)) * 0.3).astype(np.float32)
+    nz_d = _dev(nz)
+    s.set_noise(nz_d, col0=2)
+    loss = torch.zeros(1, device="cuda")
+    g = torch.zeros(p.size, device="cuda")
+    s.grad(_dev(x), _dev(y), loss=loss, grad=g)
+    out = torch.zeros((batch, 49), device="cuda")
+    s.forward(_dev(x), out)
+    torch.cuda.synchronize()
+    f32 = np.float32
+    xn_in = x.astype(np.float64).copy()
+    yn_in = y.astype(np.float64).copy()
+    xn_in[:, 2:13] += nz
+    yn_in[:, 2:13] -= nz
+    xn = M.standardise(xn_in, xm.astype(f32), xs.astype(f32))
+    yn = M.standardise(yn_in, ym.astype(f32), ys.astype(f32))
+    l_ref, g_ref = M.loss_and_grad(p, _shapes(), xn, yn)
+    assert abs(loss.item() - l_ref) <= 1e-6 * l_ref
+    assert np.linalg.norm(g.cpu().numpy() - g_ref) <= 1e-5 * np.linalg.norm(g_ref)
+    ref = M.predict(p, _shapes(), x.astype(np.float64), xm.astype(f32), xs.astype(f32),
+                    ym.astype(f32), ys.astype(f32))
+    got = out.cpu().numpy().astype(np.float64)
+    assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max()
+    with pytest.raises(N.NpxError):
+        s.set_noise(_dev(np.zeros((batch, 60), np.float32)), col0=2)   # past the outputs
+    s.set_noise(None)
+    s.close()
