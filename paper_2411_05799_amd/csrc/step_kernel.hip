@@ -110,7 +110,7 @@ using LinkT = float4[3];
 
 template <int G, int PPL, int LPL, int MODE>
 __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT, int* cand,
-                                          int* touch, int tb, int seg, int sl) {
+                                          int* touch, int* lpar, int tb, int seg, int sl) {
   constexpr int IPW = 64 / G;
   const int I = a.n_inst;
   const int task = tb * IPW + seg;
@@ -142,13 +142,13 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
   }
 
   // ---- this lane's link constants, read once per launch: hinge anchor and
-  // unit axis, limits, mass, CoG and inertia, tree depth and parent, and the
+  // unit axis, limits, mass, CoG and inertia, parent, and the
   // joint's controller (amplitude, frequency, phase in turns)
   float k_ao[LPL][3], k_ax[LPL][3], k_lo[LPL], k_hi[LPL], k_m[LPL], k_c[LPL][3], k_I[LPL][6];
   float k_box[LPL][6];  // box of the link's points: centre, half extents
   float k_A[LPL], k_f[LPL];
   double k_ph[LPL];
-  int k_dep[LPL], k_par[LPL];
+  int k_par[LPL];
 #pragma unroll
   for (int l = 0; l < LPL; ++l) {
     const float* lk = a.links + (size_t)lrow[l] * LINK_F;
@@ -170,8 +170,8 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
     k_lo[l] = lk[6];
     k_hi[l] = lk[7];
     k_m[l] = lk[LK_MASS];
-    k_dep[l] = lv[l] ? a.link_depth[lrow[l]] : -1;
     k_par[l] = a.link_parent[lrow[l]];
+    if (lv[l]) lpar[sl + l * G] = k_par[l];  // read by descendants after the next barrier
     const int li = sl + l * G;
     const float* cp = a.ctrl + ((size_t)inst * a.j_max + (lj[l] ? li - 1 : 0)) * 3;
     k_A[l] = cp[0];
@@ -220,10 +220,21 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
                            z * x * C1 - y * s, z * y * C1 + x * s, co + z * z * C1};
       // increment Rj(q) - Rj(q - dq) = -Rj(q) E(-dq), E(t) = sin t K + (1 - cos t) K^2,
       // K^2 = a a^T - 1, with 1 - cos t = 2 sin^2(t/2) to keep small angles exact
-      float se, ce, sh, ch;
-      sin_cos(-dql[l], &se, &ce);
-      sin_cos(-0.5f * dql[l], &sh, &ch);
-      const float ve = 2.f * sh * sh;
+      // the joint increment is a fraction of a degree per frame: below 0.1 rad
+      // sin t = t (1 - t^2/6 (1 - t^2/20)) and 1 - cos t = t^2/2 (1 - t^2/12
+      // (1 - t^2/30)) to float32 precision (the next terms are 1e-10 relative)
+      float se, ve;
+      const float tq = -dql[l];
+      if (!__any(!(fabsf(tq) < 0.1f))) {
+        const float t2 = tq * tq;
+        se = tq * (1.f - t2 * (1.f / 6.f) * (1.f - t2 * (1.f / 20.f)));
+        ve = 0.5f * t2 * (1.f - t2 * (1.f / 12.f) * (1.f - t2 * (1.f / 30.f)));
+      } else {
+        float ce, sh, ch;
+        sin_cos(tq, &se, &ce);
+        sin_cos(0.5f * tq, &sh, &ch);
+        ve = 2.f * sh * sh;
+      }
       const float E[9] = {ve * (x * x - 1.f), ve * x * y - se * z,  ve * x * z + se * y,
                           ve * y * x + se * z, ve * (y * y - 1.f),  ve * y * z - se * x,
                           ve * z * x - se * y, ve * z * y + se * x, ve * (z * z - 1.f)};
@@ -256,53 +267,84 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
       T[0][2] = make_float4(0.f, 0.f, 1.f, 0.f);
       dT[0][0] = dT[0][1] = dT[0][2] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    // link transforms and their increments down the tree, one depth level at a time:
-    //   R = Rp Rj, t = Rp tj + tp, dR = dRp Rj + (Rp - dRp) dRj, dt = dRp tj + (Rp - dRp) dtj + dtp
-    for (int lev = 1; lev <= a.max_depth; ++lev) {
-      __syncthreads();
+    // Each link's transform and increment from its own joint transform and its
+    // ancestors', composed up the chain by left-multiplying with the next
+    // ancestor (A, dA):  R <- Ra R,  t <- Ra t + ta,  dR <- dRa R + (Ra - dRa) dR,
+    // dt <- dRa t + dta + (Ra - dRa) dt.  A link at depth d needs d - 1 steps;
+    // only joint transforms are read, so one barrier separates the phases.
+    __syncthreads();
+    float cR[LPL][9], ct[LPL][3], cdR[LPL][9], cdt[LPL][3];
 #pragma unroll
-      for (int l = 0; l < LPL; ++l) {
-        if (k_dep[l] == lev) {
-          const int par = k_par[l];
-          const int li = sl + l * G;
-          const float4 j0 = T[li][0], j1 = T[li][1], j2 = T[li][2];
-          const float4 e0 = dT[li][0], e1 = dT[li][1], e2 = dT[li][2];
-          const float Rj[9] = {j0.x, j0.y, j0.z, j1.x, j1.y, j1.z, j2.x, j2.y, j2.z};
-          const float tj[3] = {j0.w, j1.w, j2.w};
-          const float dRj[9] = {e0.x, e0.y, e0.z, e1.x, e1.y, e1.z, e2.x, e2.y, e2.z};
-          const float dtj[3] = {e0.w, e1.w, e2.w};
-          const float4 p0 = T[par][0], p1 = T[par][1], p2 = T[par][2];
-          const float4 d0 = dT[par][0], d1 = dT[par][1], d2 = dT[par][2];
-          const float Rp[9] = {p0.x, p0.y, p0.z, p1.x, p1.y, p1.z, p2.x, p2.y, p2.z};
-          const float tp[3] = {p0.w, p1.w, p2.w};
-          const float dRp[9] = {d0.x, d0.y, d0.z, d1.x, d1.y, d1.z, d2.x, d2.y, d2.z};
-          const float dtp[3] = {d0.w, d1.w, d2.w};
-          float R[9], t[3], dR[9], dt[3];
+    for (int l = 0; l < LPL; ++l) {
+      const int li = sl + l * G;
+      const float4 j0 = T[li][0], j1 = T[li][1], j2 = T[li][2];
+      const float4 e0 = dT[li][0], e1 = dT[li][1], e2 = dT[li][2];
+      const float R0[9] = {j0.x, j0.y, j0.z, j1.x, j1.y, j1.z, j2.x, j2.y, j2.z};
+      const float dR0[9] = {e0.x, e0.y, e0.z, e1.x, e1.y, e1.z, e2.x, e2.y, e2.z};
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        cR[l][i] = R0[i];
+        cdR[l][i] = dR0[i];
+      }
+      ct[l][0] = j0.w;
+      ct[l][1] = j1.w;
+      ct[l][2] = j2.w;
+      cdt[l][0] = e0.w;
+      cdt[l][1] = e1.w;
+      cdt[l][2] = e2.w;
+      int anc = lj[l] ? k_par[l] : 0;
+      for (int it = 1; it < a.max_depth; ++it) {
+        if (anc >= 1) {
+          const float4 p0 = T[anc][0], p1 = T[anc][1], p2 = T[anc][2];
+          const float4 d0 = dT[anc][0], d1 = dT[anc][1], d2 = dT[anc][2];
+          const float Ra[9] = {p0.x, p0.y, p0.z, p1.x, p1.y, p1.z, p2.x, p2.y, p2.z};
+          const float ta[3] = {p0.w, p1.w, p2.w};
+          const float dRa[9] = {d0.x, d0.y, d0.z, d1.x, d1.y, d1.z, d2.x, d2.y, d2.z};
+          const float dta[3] = {d0.w, d1.w, d2.w};
+          float R[9], t[3], dR[9], dtt[3];
 #pragma unroll
           for (int i = 0; i < 3; ++i) {
-            const float Po[3] = {Rp[3 * i] - dRp[3 * i], Rp[3 * i + 1] - dRp[3 * i + 1],
-                                 Rp[3 * i + 2] - dRp[3 * i + 2]};
+            const float Po[3] = {Ra[3 * i] - dRa[3 * i], Ra[3 * i + 1] - dRa[3 * i + 1],
+                                 Ra[3 * i + 2] - dRa[3 * i + 2]};
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-              R[3 * i + k] = Rp[3 * i] * Rj[k] + Rp[3 * i + 1] * Rj[3 + k] +
-                             Rp[3 * i + 2] * Rj[6 + k];
-              dR[3 * i + k] = dRp[3 * i] * Rj[k] + dRp[3 * i + 1] * Rj[3 + k] +
-                              dRp[3 * i + 2] * Rj[6 + k] + Po[0] * dRj[k] +
-                              Po[1] * dRj[3 + k] + Po[2] * dRj[6 + k];
+              R[3 * i + k] = Ra[3 * i] * cR[l][k] + Ra[3 * i + 1] * cR[l][3 + k] +
+                             Ra[3 * i + 2] * cR[l][6 + k];
+              dR[3 * i + k] = dRa[3 * i] * cR[l][k] + dRa[3 * i + 1] * cR[l][3 + k] +
+                              dRa[3 * i + 2] * cR[l][6 + k] + Po[0] * cdR[l][k] +
+                              Po[1] * cdR[l][3 + k] + Po[2] * cdR[l][6 + k];
             }
-            t[i] = Rp[3 * i] * tj[0] + Rp[3 * i + 1] * tj[1] + Rp[3 * i + 2] * tj[2] +
-                   tp[i];
-            dt[i] = dRp[3 * i] * tj[0] + dRp[3 * i + 1] * tj[1] +
-                    dRp[3 * i + 2] * tj[2] + Po[0] * dtj[0] + Po[1] * dtj[1] +
-                    Po[2] * dtj[2] + dtp[i];
+            t[i] = Ra[3 * i] * ct[l][0] + Ra[3 * i + 1] * ct[l][1] + Ra[3 * i + 2] * ct[l][2] +
+                   ta[i];
+            dtt[i] = dRa[3 * i] * ct[l][0] + dRa[3 * i + 1] * ct[l][1] +
+                     dRa[3 * i + 2] * ct[l][2] + Po[0] * cdt[l][0] + Po[1] * cdt[l][1] +
+                     Po[2] * cdt[l][2] + dta[i];
           }
-          T[li][0] = make_float4(R[0], R[1], R[2], t[0]);
-          T[li][1] = make_float4(R[3], R[4], R[5], t[1]);
-          T[li][2] = make_float4(R[6], R[7], R[8], t[2]);
-          dT[li][0] = make_float4(dR[0], dR[1], dR[2], dt[0]);
-          dT[li][1] = make_float4(dR[3], dR[4], dR[5], dt[1]);
-          dT[li][2] = make_float4(dR[6], dR[7], dR[8], dt[2]);
+#pragma unroll
+          for (int i = 0; i < 9; ++i) {
+            cR[l][i] = R[i];
+            cdR[l][i] = dR[i];
+          }
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            ct[l][i] = t[i];
+            cdt[l][i] = dtt[i];
+          }
+          anc = lpar[anc];
         }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < LPL; ++l) {
+      const int li = sl + l * G;
+      if (lj[l]) {
+        T[li][0] = make_float4(cR[l][0], cR[l][1], cR[l][2], ct[l][0]);
+        T[li][1] = make_float4(cR[l][3], cR[l][4], cR[l][5], ct[l][1]);
+        T[li][2] = make_float4(cR[l][6], cR[l][7], cR[l][8], ct[l][2]);
+        dT[li][0] = make_float4(cdR[l][0], cdR[l][1], cdR[l][2], cdt[l][0]);
+        dT[li][1] = make_float4(cdR[l][3], cdR[l][4], cdR[l][5], cdt[l][1]);
+        dT[li][2] = make_float4(cdR[l][6], cdR[l][7], cdR[l][8], cdt[l][2]);
       }
     }
     __syncthreads();
@@ -498,7 +540,9 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
   #pragma unroll
       for (int p = 0; p < PPL; ++p) {
         const bool hit = (kap >> p) & 1u;
-        const unsigned long long m = seg_bits<G>(__ballot(hit), seg);
+        const unsigned long long wm = __ballot(hit);
+        if (wm == 0ull) continue;  // no candidate in this slot anywhere in the wave
+        const unsigned long long m = seg_bits<G>(wm, seg);
         if (hit) cand[n_cand + __popcll(m & ((1ull << sl) - 1ull))] = sl + p * G;
         n_cand += __popcll(m);
       }
@@ -768,6 +812,7 @@ void step_kernel(const StepArgs a) {
   __shared__ LinkT dT[IPW][LMAX];
   __shared__ int cand[IPW][G * PPL];  // contact points of a frame, compacted
   __shared__ int touch[IPW][LMAX];    // links that may reach the ground this frame
+  __shared__ int lpar[IPW][LMAX];     // parent of every link of the robot
   const int lane = threadIdx.x;
   const int seg = lane / G;
   const int sl = lane - seg * G;
@@ -782,7 +827,8 @@ void step_kernel(const StepArgs a) {
       tb = blockIdx.x;
     }
     if (tb >= a.n_blocks) break;
-    run_block<G, PPL, LPL, MODE>(a, T[seg], dT[seg], cand[seg], touch[seg], tb, seg, sl);
+    run_block<G, PPL, LPL, MODE>(a, T[seg], dT[seg], cand[seg], touch[seg], lpar[seg], tb, seg,
+                                 sl);
     __syncthreads();
   }
 }
