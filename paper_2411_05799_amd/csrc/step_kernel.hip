@@ -179,6 +179,19 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
     k_ph[l] = (double)cp[2] * kInvTwoPi;
   }
 
+  // ---- the link of each of this lane's points (6 bits per slot, five slots
+  // per register), read once per launch
+  constexpr int PACKW = (PPL + 4) / 5;
+  unsigned plk[PACKW];
+#pragma unroll
+  for (int w = 0; w < PACKW; ++w) plk[w] = 0u;
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) {
+    const int k = sl + p * G;
+    const unsigned lk = k < N ? (unsigned)a.pt_link[pt_off + k] : 0u;
+    plk[p / 5] |= (lk & 63u) << (6 * (p % 5));
+  }
+
   // ---- per-robot state (same value in every lane of the segment)
   float c[3], Q[4], v[3], w[3];
 #pragma unroll
@@ -697,7 +710,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
       const int k = sl + p * G;
       const bool ok = k < N;
       const int kk = pt_off + (ok ? k : 0);
-      const int lk = ok ? a.pt_link[kk] : 0;
+      const int lk = (int)((plk[p / 5] >> (6 * (p % 5))) & 63u);
       if (ok && touch[lk]) {
         const float4 rho = a.pts[kk];
         const float4 r0 = T[lk][0], r1 = T[lk][1], r2 = T[lk][2];
