@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "npx.h"
@@ -224,6 +225,84 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<T> g) {
         const int col = n0 + 16 * j + r16;
         g.colsum[(int64_t)mt * g.N + col] = csum[j] + red[(wave & 1) * 32 + 16 * j + r16];
       }
+  }
+}
+
+// Large-batch forward products (BF16 only): one block = 4 waves = a 128x128
+// output tile, each wave 64x64 as 2x2 blocks of v_mfma_f32_32x32x16_bf16,
+// which doubles the arithmetic per loaded byte of the 16x16 form. Lane l
+// supplies row (l mod 32) and the k-slice 8*(l/32) .. +8 of both operands;
+// the result lands as D[8*(e/4) + 4*(l/32) + (e mod 4)][l mod 32], e = 0..15.
+// M and N must be multiples of 128, K of 32; EPI_HID or EPI_OUT.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+constexpr int BIG = 128;
+
+template <int EPI>
+__global__ __launch_bounds__(256) void gemm_big_kernel(GemmArgs<__bf16> g) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tiles_n = g.N / BIG;
+  int tile = blockIdx.x;
+  const int nb = gridDim.x;
+  if ((nb & 7) == 0) tile = (tile & 7) * (nb >> 3) + (tile >> 3);
+  const int m0 = (tile / tiles_n) * BIG + (wave >> 1) * 64;
+  const int n0 = (tile % tiles_n) * BIG + (wave & 1) * 64;
+  const int r32 = lane & 31, grp = lane >> 5;
+  const __bf16* a0 = g.A + (int64_t)(m0 + r32) * g.lda + grp * 8;
+  const __bf16* a1 = a0 + 32 * g.lda;
+  const __bf16* b0 = g.B + (int64_t)(n0 + r32) * g.ldb + grp * 8;
+  const __bf16* b1 = b0 + 32 * g.ldb;
+  f32x16 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+  auto ld = [](const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); };
+  bf16x8 fa0 = ld(a0), fa1 = ld(a1), fb0 = ld(b0), fb1 = ld(b1);
+  for (int k = 16; k < g.K; k += 16) {
+    const bf16x8 na0 = ld(a0 + k), na1 = ld(a1 + k), nb0 = ld(b0 + k), nb1 = ld(b1 + k);
+    acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa0, fb0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa0, fb1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa1, fb0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa1, fb1, acc[1][1], 0, 0, 0);
+    fa0 = na0; fa1 = na1; fb0 = nb0; fb1 = nb1;
+  }
+  acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa0, fb0, acc[0][0], 0, 0, 0);
+  acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa0, fb1, acc[0][1], 0, 0, 0);
+  acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa1, fb0, acc[1][0], 0, 0, 0);
+  acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa1, fb1, acc[1][1], 0, 0, 0);
+
+  for (int i = 0; i < 2; ++i) {
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + 32 * j + r32;
+      for (int q = 0; q < 4; ++q) {
+        const int row = m0 + 32 * i + 8 * q + 4 * grp;  // rows row .. row + 3
+        if constexpr (EPI == EPI_OUT) {
+          if (col < g.n_valid) {
+            const float b = g.bias[col];
+            float sc = 1.f, sh = 0.f;
+            if (g.scale) {
+              sc = g.scale[col];
+              sh = g.shift[col];
+            }
+            for (int e = 0; e < 4; ++e)
+              if (row + e < g.m_valid)
+                g.C[(int64_t)(row + e) * g.ldc + col] = (acc[i][j][4 * q + e] + b) * sc + sh;
+          }
+        } else {
+          const float b = g.bias[col];
+          __bf16 out[4];
+          for (int e = 0; e < 4; ++e) {
+            const float z = acc[i][j][4 * q + e] + b;
+            if (g.C) g.C[(int64_t)(row + e) * g.ldc + col] = z;
+            out[e] = (__bf16)(z * sigmoid(z));
+          }
+          for (int e = 0; e < 4; ++e) g.H[(int64_t)(row + e) * g.ldh + col] = out[e];
+          if (g.HT) {
+            __bf16* ht = g.HT + (int64_t)col * g.ldht + row;
+            for (int e = 0; e < 4; ++e) ht[e] = out[e];
+          }
+        }
+      }
+    }
   }
 }
 
@@ -516,6 +595,14 @@ hipError_t launch_gemm(const GemmArgs<T>& g, int slices, hipStream_t st) {
   if (g.M % TILE || g.N % TILE || g.K % KSTEP || g.k_split % KSTEP ||
       (int64_t)g.k_split * slices < g.K)
     return hipErrorInvalidValue;
+  // large forward products: 128x128 tiles when they still give >= 4 blocks per CU
+  if constexpr (std::is_same<T, __bf16>::value && (EPI == EPI_HID || EPI == EPI_OUT)) {
+    if (slices == 1 && g.M % BIG == 0 && g.N % BIG == 0 && (g.M / BIG) * (g.N / BIG) >= 1024) {
+      hipLaunchKernelGGL((gemm_big_kernel<EPI>), dim3((g.M / BIG) * (g.N / BIG)), dim3(256), 0,
+                         st, g);
+      return hipGetLastError();
+    }
+  }
   dim3 grid((g.M / TILE) * (g.N / TILE), slices);
   hipLaunchKernelGGL((gemm_kernel<T, EPI>), grid, dim3(256), 0, st, g);
   return hipGetLastError();

@@ -282,3 +282,29 @@ def test_training_noise_shifts_inputs_and_targets():
         s.set_noise(_dev(np.zeros((batch, 60), np.float32)), col0=2)   # past the outputs
     s.set_noise(None)
     s.close()
+
+
+def test_forward_bf16_large_batch_matches_oracle_on_sampled_rows():
+    """65,536 rows take the 128x128 tiles of the large-batch forward: sampled
+    rows against the FP64 reference (BF16-representable inputs and weights)."""
+    from paper_2411_05799_amd import native as N
+    torch = _torch()
+    rng = np.random.default_rng(12)
+    B = 65536
+    x = bf16_round(rng.normal(0.3, 1.7, size=(B, SHAPE["n_in"]))).astype(np.float32)
+    s = N.Surrogate(max_batch=B, precision=N.SUR_BF16, training=False, seed=2, **SHAPE)
+    s.set_params(bf16_round(s.get_params()))
+    ym, ys = rng.normal(size=49), rng.uniform(0.5, 2.0, size=49)
+    s.set_norm(np.zeros(SHAPE["n_in"]), np.ones(SHAPE["n_in"]), ym, ys)
+    p = s.get_params().astype(np.float64)
+    out = torch.zeros((B, 49), device="cuda")
+    s.forward(_dev(x), out)
+    torch.cuda.synchronize()
+    rows = np.sort(rng.choice(B, 512, replace=False))
+    f32 = np.float32
+    ref = M.predict(p, _shapes(), x[rows].astype(np.float64), np.zeros(SHAPE["n_in"]),
+                    np.ones(SHAPE["n_in"]), ym.astype(f32), ys.astype(f32))
+    got = out.cpu().numpy()[rows].astype(np.float64)
+    assert np.linalg.norm(got - ref) <= 1e-2 * np.linalg.norm(ref - ym.astype(f32))
+    assert np.isfinite(out.cpu().numpy()).all()
+    s.close()
