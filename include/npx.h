@@ -332,6 +332,9 @@ npx_status npx_sur_norm_stats(const float* x, int64_t ldx, int64_t rows, int32_t
 npx_status npx_sur_widths(const npx_world* w, int32_t* state_width, int32_t* feature_width);
 /* s[i] = state row of instance i. */
 npx_status npx_world_rows(npx_world* w, float* s, int64_t lds, void* stream);
+/* State of instance i = s[i] (the inverse of npx_world_rows; the frame
+ * counters, flags and telemetry are left as they are). */
+npx_status npx_world_set_rows(npx_world* w, const float* s, int64_t lds, void* stream);
 /* x[i] = network input of instance i, from the state rows s (s != NULL, at
  * frame `frame` >= 0) or from the world's own state and step counters (s ==
  * NULL), with the world's controllers and height map. */

@@ -144,6 +144,15 @@ __global__ void rows_kernel(WorldView v, float* s, int64_t lds, int width) {
   s[(int64_t)i * lds + r] = v.a.st[(int64_t)r * I + i];
 }
 
+// world state of i = s[i] (the inverse of rows_kernel)
+__global__ void set_rows_kernel(WorldView v, const float* s, int64_t lds, int width) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int I = v.a.n_inst;
+  if (e >= (int64_t)I * width) return;
+  const int r = (int)(e / I), i = (int)(e % I);
+  v.a.st[(int64_t)r * I + i] = s[(int64_t)i * lds + r];
+}
+
 // y[i] = (world state of i) - s0[i], the body entries in the heading frame of
 // s0[i].  One wave per instance, lanes over the columns.
 __global__ __launch_bounds__(256) void delta_kernel(WorldView v, const float* s0, int64_t lds,
@@ -457,6 +466,21 @@ npx_status npx_world_rows(npx_world* w, float* s, int64_t lds, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   hipLaunchKernelGGL(rows_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v, s, lds,
                      width);
+  HIP_TRY(hipGetLastError());
+  npx::note_stream(w, st);
+  return NPX_OK;
+}
+
+npx_status npx_world_set_rows(npx_world* w, const float* s, int64_t lds, void* stream) {
+  npx_status r = check_world(w);
+  if (r != NPX_OK) return r;
+  const WorldView v = npx::world_view(w);
+  const int width = state_width(v.a.j_max);
+  if (!s || lds < width) return fail(NPX_EINVAL, "bad state buffer or stride");
+  const int64_t n = (int64_t)v.a.n_inst * width;
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(set_rows_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v, s,
+                     lds, width);
   HIP_TRY(hipGetLastError());
   npx::note_stream(w, st);
   return NPX_OK;

@@ -142,6 +142,8 @@ def lib():
         L.npx_sur_set_noise.restype = C.c_int
         L.npx_sur_widths.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.npx_world_rows.argtypes = [vp, vp, i64, vp]
+        L.npx_world_set_rows.argtypes = [vp, vp, i64, vp]
+        L.npx_world_set_rows.restype = C.c_int
         L.npx_sur_features.argtypes = [vp, vp, i64, i64, vp, i64, vp]
         L.npx_sur_delta.argtypes = [vp, vp, i64, vp, i64, vp]
         L.npx_sur_advance.argtypes = [vp, vp, i64, vp, i64, i64, vp]
@@ -350,6 +352,11 @@ class World:
         check(lib().npx_world_rows(self.h, _ptr(out), out.stride(0),
                                    C.c_void_p(_stream_handle(stream))))
         return out
+
+    def set_rows(self, s, stream=None):
+        """Every instance's state from the rows of a device tensor."""
+        check(lib().npx_world_set_rows(self.h, _ptr(s), s.stride(0),
+                                       C.c_void_p(_stream_handle(stream))))
 
     def sur_features(self, x, s=None, frame=-1, stream=None):
         """Network inputs into x [I, >= width]: from rows s at `frame`, or from

@@ -42,6 +42,24 @@ def test_widths_and_rows_match_read_state(walked):
     np.testing.assert_array_equal(r[:, 31:], gw.read_state(N.F_JOINT_PREV).T)
 
 
+def test_set_rows_inverts_rows(walked):
+    import torch
+    from paper_2411_05799_amd import native as N
+    w, gw, rows = walked
+    say("case: set_rows then rows on a fresh world, strided buffer")
+    gw2 = N.World(w)
+    buf = torch.full((N_INST, 64), 7.0, device="cuda")
+    buf[:, :49] = rows
+    gw2.set_rows(buf[:, :49])
+    back = torch.zeros_like(rows)
+    gw2.rows(back)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(back.cpu().numpy(), rows.cpu().numpy())
+    np.testing.assert_array_equal(gw2.read_state(N.F_BODY).T, rows[:, :13].cpu().numpy())
+    assert np.all(gw2.read_state(N.F_STEP) == 0)
+    gw2.close()
+
+
 def test_features_match_reference(walked):
     import torch
     w, gw, rows = walked

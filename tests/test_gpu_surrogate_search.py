@@ -53,3 +53,27 @@ def test_screen_gains_over_random_candidates(trained):
     assert beaten > 0.5
     assert out["top_recall"] > 0.15          # random choice gives 0.05
     assert out["rank_error"] < 0.3           # random ranking gives 1/3
+
+
+def test_output_weights_keep_the_delta_scale(trained):
+    """Loss weights on output columns are realised in the target scale: the
+    de-standardised outputs stay the state change, so a network trained with
+    the joint columns nearly ignored predicts the body columns as well as
+    the unweighted one and the joint columns still in their own units."""
+    from paper_2411_05799_amd import surrogate as S
+    tr, ev = trained
+    say("case: re-train 12 epochs with joint outputs at weight 1e-3")
+    X, Y, _ = S.generate(n_terrains=2, n_inst=2048, n_samples=120, seed=4242)
+    X, Y, n_train = S.split(X, Y, holdout=0.05)
+    ow = np.ones(49)
+    ow[13:] = 1e-3
+    tw = S.train(X, Y, n_train, epochs=12, batch=4096, out_weight=ow)
+    np.testing.assert_allclose(tw.y_std, tw.y_std_raw / np.sqrt(ow), rtol=1e-6)
+    np.testing.assert_allclose(tw.y_std_raw, tr.y_std_raw, rtol=1e-5)
+    evw = S.evaluate(tw, X, Y, n_train, X.shape[0])
+    body, body_w = np.array(ev["rmse"][:13]), np.array(evw["rmse"][:13])
+    say(f"body rmse ratio weighted/unweighted: {np.round(body_w / body, 3).tolist()}")
+    assert np.all(body_w < 1.25 * body)
+    joint_std = tr.y_std_raw[13:]
+    assert np.all(np.array(evw["rmse"][13:]) < 2.0 * joint_std + 1e-6)
+    tw.net.close()
