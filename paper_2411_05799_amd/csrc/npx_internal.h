@@ -36,6 +36,7 @@ struct StepArgs {
   const float* morph_mass;
   const float4* pts;      // [total points] x y z m (construction frame)
   const int* pt_link;     // [total points]
+  const int* pt_orig;     // [total points] index in the morphology's own point order
   const float* links;     // [total links][LINK_F]
   const int* link_parent; // [total links]
   const int* link_depth;  // [total links]

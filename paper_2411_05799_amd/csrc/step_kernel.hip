@@ -475,6 +475,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
   // round differently and make a trajectory depend on where launches begin.
   bool fk_pending = true, fk_now = false;
   unsigned kap = 0u;
+  unsigned kap_slots = 0u;  // slots with a contact point in some lane of the wave
   float F = 0.f, tx = 0.f, ty = 0.f, nc = 0.f;
   for (int s = 0;; ++s) {
     if (fk_pending) forward_kinematics(dql);
@@ -511,7 +512,14 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
       {
         const float th0 = dt * w1[0], th1 = dt * w1[1], th2 = dt * w1[2];
         const float ang2 = th0 * th0 + th1 * th1 + th2 * th2;
-        if (ang2 < 1e-24f) {
+        if (!__any(!(ang2 < 0.01f))) {
+          // half angle h below 0.05 rad: cos h and sin(h) / |theta| = sin(h) / (2h)
+          // from their series in h^2 to float32 precision (next terms < 1e-12)
+          const float h2 = 0.25f * ang2;
+          const float k = 0.5f - h2 * (1.f / 12.f) * (1.f - h2 * (1.f / 20.f));
+          dq[0] = 1.f - 0.5f * h2 * (1.f - h2 * (1.f / 12.f) * (1.f - h2 * (1.f / 30.f)));
+          dq[1] = k * th0; dq[2] = k * th1; dq[3] = k * th2;
+        } else if (ang2 < 1e-24f) {
           dq[0] = 1.f; dq[1] = 0.5f * th0; dq[2] = 0.5f * th1; dq[3] = 0.5f * th2;
         } else {
           const float ang = __builtin_amdgcn_sqrtf(ang2);
@@ -550,12 +558,10 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
       // slot, in lane order) and the segment's lanes then share the list: one
       // pass of G candidates instead of PPL mostly idle slots.
       int n_cand = 0;
-  #pragma unroll
-      for (int p = 0; p < PPL; ++p) {
+      for (unsigned rest = kap_slots; rest != 0u; rest &= rest - 1u) {
+        const int p = __builtin_ctz(rest);
         const bool hit = (kap >> p) & 1u;
-        const unsigned long long wm = __ballot(hit);
-        if (wm == 0ull) continue;  // no candidate in this slot anywhere in the wave
-        const unsigned long long m = seg_bits<G>(wm, seg);
+        const unsigned long long m = seg_bits<G>(__ballot(hit), seg);
         if (hit) cand[n_cand + __popcll(m & ((1ull << sl) - 1ull))] = sl + p * G;
         n_cand += __popcll(m);
       }
@@ -625,11 +631,22 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
       }
 
       // S8 correction and commit
-      const float alpha = asinf(fminf(fmaxf(a3, -1.f), 1.f));
+      float alpha, sh, ch;
+      if (!__any(!(fabsf(a3) < 0.1f))) {
+        // |a3| < 0.1: asin from its series to float32 precision (the next term
+        // is below 3e-10 relative), and the half-angle rotation |beta| < 0.06
+        // from the sine and cosine series
+        const float x2 = a3 * a3;
+        alpha = a3 * (1.f + x2 * ((1.f / 6.f) + x2 * ((3.f / 40.f) + x2 * (5.f / 112.f))));
+        const float be = -0.5f * lam * alpha, b2 = be * be;
+        sh = be * (1.f - b2 * (1.f / 6.f) * (1.f - b2 * (1.f / 20.f)));
+        ch = 1.f - 0.5f * b2 * (1.f - b2 * (1.f / 12.f) * (1.f - b2 * (1.f / 30.f)));
+      } else {
+        alpha = asinf(fminf(fmaxf(a3, -1.f), 1.f));
+        sin_cos(-0.5f * lam * alpha, &sh, &ch);
+      }
       float Q2[4];
       {
-        float sh, ch;
-        sin_cos(-0.5f * lam * alpha, &sh, &ch);
         Q2[0] = ch * Q1[0] - sh * Q1[3];
         Q2[1] = ch * Q1[1] - sh * Q1[2];
         Q2[2] = ch * Q1[2] + sh * Q1[1];
@@ -701,6 +718,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
     }
     __builtin_amdgcn_wave_barrier();
     kap = 0u;
+    kap_slots = 0u;
     F = 0.f;
     tx = 0.f;
     ty = 0.f;
@@ -711,6 +729,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
       const bool ok = k < N;
       const int kk = pt_off + (ok ? k : 0);
       const int lk = (int)((plk[p / 5] >> (6 * (p % 5))) & 63u);
+      bool hit = false;
       if (ok && touch[lk]) {
         const float4 rho = a.pts[kk];
         const float4 r0 = T[lk][0], r1 = T[lk][1], r2 = T[lk][2];
@@ -723,6 +742,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
         const float Px = c[0] + ux, Py = c[1] + uy, Pz = c[2] + uz;
         const float d = hf_at(a, Px, Py) - Pz;
         if (d > 0.f) {
+          hit = true;
           kap |= 1u << p;
           const float vz = v[2] + (w[0] * uy - w[1] * ux);
           const float f = fmaxf(a.kn * d * (1.f - a.zeta * vz), 0.f);
@@ -732,6 +752,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
           nc += 1.f;
         }
       }
+      if (__ballot(hit) != 0ull) kap_slots |= 1u << p;
       group_fence(p);
     }
     F = seg_sum<G>(F);
@@ -770,7 +791,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
       const int k = sl + p * G;
       float r[3];
       if (body_point(k, r) && valid) {
-        float* o = a.points_out + ((size_t)inst * a.n_max + k) * 3;
+        float* o = a.points_out + ((size_t)inst * a.n_max + a.pt_orig[pt_off + k]) * 3;
         o[0] = c[0] + (R[0] * r[0] + R[1] * r[1] + R[2] * r[2]);
         o[1] = c[1] + (R[3] * r[0] + R[4] * r[1] + R[5] * r[2]);
         o[2] = c[2] + (R[6] * r[0] + R[7] * r[1] + R[8] * r[2]);

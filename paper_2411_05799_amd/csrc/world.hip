@@ -70,6 +70,7 @@ struct npx_world {
   float* morph_mass = nullptr;
   float4* pts = nullptr;
   int* pt_link = nullptr;
+  int* pt_orig = nullptr;  // [total points] index of each point in its morphology's own order
   float* links = nullptr;
   int* link_parent = nullptr;
   int* link_depth = nullptr;
@@ -289,7 +290,8 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   std::vector<int4> info(d->n_morphs);
   std::vector<float> mass(d->n_morphs);
   std::vector<float4> pts;
-  std::vector<int> ptl, par, dep;
+  std::vector<int> ptl, pto, par, dep;
+  std::vector<std::vector<int>> slot_of(d->n_morphs);  // position of each point in pts
   std::vector<float> lk;
   for (int mi = 0; mi < d->n_morphs; ++mi) {
     const npx_morph_tables& m = d->morphs[mi];
@@ -299,11 +301,38 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
     w->n_max = std::max(w->n_max, m.n_points);
     w->l_max = std::max(w->l_max, m.n_links);
     std::vector<double> lm(m.n_links, 0.0), lc(3 * m.n_links, 0.0), lI(6 * m.n_links, 0.0);
+    std::vector<int> depth(m.n_links, 0), children(m.n_links, 0);
+    for (int l = 1; l < m.n_links; ++l) {
+      depth[l] = depth[m.parent[l]] + 1;
+      children[m.parent[l]] += 1;
+    }
+    // Point order in the tables: points of leaf links (the feet, usually the
+    // only links near the ground) first, then the deeper links before the
+    // shallower, each link's points in their own order. The step kernel puts
+    // point k on lane k mod G, register slot k / G, and skips a slot when no
+    // lane's point belongs to a link that may reach the ground, so this order
+    // packs the points that get tested into the fewest slots.
+    std::vector<int> order(m.n_points);
+    for (int k = 0; k < m.n_points; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      const int lx = m.pt_link[x], ly = m.pt_link[y];
+      const int kx = children[lx] == 0 ? 0 : 1, ky = children[ly] == 0 ? 0 : 1;
+      if (kx != ky) return kx < ky;
+      if (depth[lx] != depth[ly]) return depth[lx] > depth[ly];
+      return lx < ly;
+    });
+    slot_of[mi].assign(m.n_points, 0);
+    for (int k = 0; k < m.n_points; ++k) {
+      const int o = order[k];
+      const float* p = m.points + 4 * o;
+      slot_of[mi][o] = k;
+      pts.push_back(make_float4(p[0], p[1], p[2], p[3]));
+      ptl.push_back(m.pt_link[o]);
+      pto.push_back(o);
+    }
     double M = 0;
     for (int k = 0; k < m.n_points; ++k) {
       const float* p = m.points + 4 * k;
-      pts.push_back(make_float4(p[0], p[1], p[2], p[3]));
-      ptl.push_back(m.pt_link[k]);
       int l = m.pt_link[k];
       lm[l] += p[3];
       for (int i = 0; i < 3; ++i) lc[3 * l + i] += (double)p[3] * p[i];
@@ -325,9 +354,7 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
       lI[6 * l + 5] -= mk * r[1] * r[2];
     }
     mass[mi] = (float)M;
-    std::vector<int> depth(m.n_links, 0);
     for (int l = 0; l < m.n_links; ++l) {
-      depth[l] = l == 0 ? 0 : depth[m.parent[l]] + 1;
       w->max_depth = std::max(w->max_depth, depth[l]);
       par.push_back(m.parent[l]);
       dep.push_back(depth[l]);
@@ -364,7 +391,7 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
     const int p0 = info[mi].x;
     for (int l = 0; l < m.n_links; ++l) {
       for (int k = 0; k < m.n_points; ++k)
-        if (m.pt_link[k] == l) lpi.push_back(p0 + k);
+        if (m.pt_link[k] == l) lpi.push_back(p0 + slot_of[mi][k]);
       lpo.push_back((int)lpi.size());
     }
   }
@@ -402,6 +429,7 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   ALLOC(w->morph_mass, mass.size());
   ALLOC(w->pts, pts.size());
   ALLOC(w->pt_link, ptl.size());
+  ALLOC(w->pt_orig, pto.size());
   ALLOC(w->links, lk.size());
   ALLOC(w->link_parent, par.size());
   ALLOC(w->link_depth, dep.size());
@@ -425,6 +453,7 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   H2D(w->morph_mass, mass.data(), mass.size() * sizeof(float));
   H2D(w->pts, pts.data(), pts.size() * sizeof(float4));
   H2D(w->pt_link, ptl.data(), ptl.size() * sizeof(int));
+  H2D(w->pt_orig, pto.data(), pto.size() * sizeof(int));
   H2D(w->links, lk.data(), lk.size() * sizeof(float));
   H2D(w->link_parent, par.data(), par.size() * sizeof(int));
   H2D(w->link_depth, dep.data(), dep.size() * sizeof(int));
@@ -456,6 +485,7 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   a.morph_mass = w->morph_mass;
   a.pts = w->pts;
   a.pt_link = w->pt_link;
+  a.pt_orig = w->pt_orig;
   a.links = w->links;
   a.link_parent = w->link_parent;
   a.link_depth = w->link_depth;
@@ -526,7 +556,7 @@ void npx_destroy_world(npx_world* w) {
   w->drop_graphs();
   if (w->capture_stream) (void)hipStreamDestroy(w->capture_stream);
   void* bufs[] = {w->st, w->step, w->flags, w->tele, w->inst_morph_d, w->morph_info,
-                  w->morph_mass, w->pts, w->pt_link, w->links, w->link_parent,
+                  w->morph_mass, w->pts, w->pt_link, w->pt_orig, w->links, w->link_parent,
                   w->link_depth, w->ctrl, w->hf, w->order, w->queue, w->lp_off,
                   w->lp_idx, w->sub_mask};
   for (void* b : bufs)
