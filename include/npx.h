@@ -359,9 +359,13 @@ npx_status npx_sur_advance(npx_world* w, float* s, int64_t lds, const float* dy,
 npx_status npx_sur_torque(npx_world* w, const float* s, int64_t lds, float* acc, int accumulate,
                           void* stream);
 /* n_calls surrogate calls from rows s at frame frame0: per call the inputs
- * (into x_work [I][ldx]), the network (into y_work [I][ldy]), the update of s,
- * and (tau_acc != NULL) the torque proxy added to tau_acc[i].  The network's
- * widths must match the world's and its max_batch must cover the instances. */
+ * (written standardised straight into the network's own input rows), the
+ * network (into y_work [I][ldy]), the update of s, and (tau_acc != NULL) the
+ * torque proxy added to tau_acc[i].  The results equal those of
+ * npx_sur_features + npx_sur_forward + npx_sur_advance (+ npx_sur_torque) call
+ * by call.  x_work [I][ldx] (ldx >= the feature width) is checked but holds
+ * nothing defined afterwards.  The network's widths must match the world's
+ * and its max_batch must cover the instances. */
 npx_status npx_sur_rollout(npx_sur* net, npx_world* w, float* s, int64_t lds, int64_t frame0,
                            int32_t n_calls, float* x_work, int64_t ldx, float* y_work,
                            int64_t ldy, float* tau_acc, void* stream);

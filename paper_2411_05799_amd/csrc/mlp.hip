@@ -247,28 +247,57 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(GemmArgs<__bf16> g) {
   const int m0 = (tile / tiles_n) * BIG + (wave >> 1) * 64;
   const int n0 = (tile % tiles_n) * BIG + (wave & 1) * 64;
   const int r32 = lane & 31, grp = lane >> 5;
-  const __bf16* a0 = g.A + (int64_t)(m0 + r32) * g.lda + grp * 8;
+  // K is walked in chunks of 64. In a chunk, lane (r32, grp) holds k in
+  // [32 grp, 32 grp + 32) of its A and B rows as four 8-element slices and
+  // step j of the chunk multiplies slice j of both operands: every k meets
+  // its partner exactly once, each lane reads 64 contiguous bytes of a row
+  // per chunk, and the next chunk's loads are in flight during the current
+  // chunk's 16 products.
+  const __bf16* a0 = g.A + (int64_t)(m0 + r32) * g.lda + grp * 32;
   const __bf16* a1 = a0 + 32 * g.lda;
-  const __bf16* b0 = g.B + (int64_t)(n0 + r32) * g.ldb + grp * 8;
+  const __bf16* b0 = g.B + (int64_t)(n0 + r32) * g.ldb + grp * 32;
   const __bf16* b1 = b0 + 32 * g.ldb;
   f32x16 acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j)
       for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
   auto ld = [](const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); };
-  bf16x8 fa0 = ld(a0), fa1 = ld(a1), fb0 = ld(b0), fb1 = ld(b1);
-  for (int k = 16; k < g.K; k += 16) {
-    const bf16x8 na0 = ld(a0 + k), na1 = ld(a1 + k), nb0 = ld(b0 + k), nb1 = ld(b1 + k);
-    acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa0, fb0, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa0, fb1, acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa1, fb0, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa1, fb1, acc[1][1], 0, 0, 0);
-    fa0 = na0; fa1 = na1; fb0 = nb0; fb1 = nb1;
+  bf16x8 fa[2][4], fb[2][4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    fa[0][j] = ld(a0 + 8 * j);
+    fa[1][j] = ld(a1 + 8 * j);
+    fb[0][j] = ld(b0 + 8 * j);
+    fb[1][j] = ld(b1 + 8 * j);
   }
-  acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa0, fb0, acc[0][0], 0, 0, 0);
-  acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa0, fb1, acc[0][1], 0, 0, 0);
-  acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa1, fb0, acc[1][0], 0, 0, 0);
-  acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa1, fb1, acc[1][1], 0, 0, 0);
+  auto chunk = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0][j], fb[0][j], acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0][j], fb[1][j], acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[1][j], fb[0][j], acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[1][j], fb[1][j], acc[1][1], 0, 0, 0);
+    }
+  };
+  for (int k = 64; k < g.K; k += 64) {
+    bf16x8 na[2][4], nb[2][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      na[0][j] = ld(a0 + k + 8 * j);
+      na[1][j] = ld(a1 + k + 8 * j);
+      nb[0][j] = ld(b0 + k + 8 * j);
+      nb[1][j] = ld(b1 + k + 8 * j);
+    }
+    chunk();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      fa[0][j] = na[0][j];
+      fa[1][j] = na[1][j];
+      fb[0][j] = nb[0][j];
+      fb[1][j] = nb[1][j];
+    }
+  }
+  chunk();
 
   for (int i = 0; i < 2; ++i) {
     for (int j = 0; j < 2; ++j) {
@@ -597,7 +626,8 @@ hipError_t launch_gemm(const GemmArgs<T>& g, int slices, hipStream_t st) {
     return hipErrorInvalidValue;
   // large forward products: 128x128 tiles when they still give >= 4 blocks per CU
   if constexpr (std::is_same<T, __bf16>::value && (EPI == EPI_HID || EPI == EPI_OUT)) {
-    if (slices == 1 && g.M % BIG == 0 && g.N % BIG == 0 && (g.M / BIG) * (g.N / BIG) >= 1024) {
+    if (slices == 1 && g.M % BIG == 0 && g.N % BIG == 0 && g.K % 64 == 0 &&
+        (g.M / BIG) * (g.N / BIG) >= 1024) {
       hipLaunchKernelGGL((gemm_big_kernel<EPI>), dim3((g.M / BIG) * (g.N / BIG)), dim3(256), 0,
                          st, g);
       return hipGetLastError();
@@ -638,18 +668,30 @@ inline const float* bias(const npx_sur* s, int l) {
 // pass (pre-activations, transposed copies, normalised output in Yhat); else
 // the de-normalised prediction goes to final_out.
 template <class T>
+npx_status forward_packed_t(npx_sur* s, int batch, float* final_out, int64_t ld_out,
+                            hipStream_t st);
+
+template <class T>
 npx_status forward_t(npx_sur* s, const float* x, int64_t ldx, const int* rows, int batch,
                      float* final_out, int64_t ld_out, hipStream_t st) {
   const int Mp = round_up(batch, TILE);
   const bool train = final_out == nullptr;
-  {
-    dim3 grid(Mp / TILE, s->in_p0 / TILE);
-    hipLaunchKernelGGL((pack_input_kernel<T>), grid, dim3(256), 0, st, x, ldx, rows, batch,
-                       s->n_in, s->x_mean, s->x_inv, static_cast<T*>(s->X0), (int64_t)s->in_p0,
-                       train ? static_cast<T*>(s->X0T) : nullptr, (int64_t)Mp,
-                       train ? s->noise : Noise{nullptr, 0, 0, 0});
-    HIP_TRY(hipGetLastError());
-  }
+  dim3 grid(Mp / TILE, s->in_p0 / TILE);
+  hipLaunchKernelGGL((pack_input_kernel<T>), grid, dim3(256), 0, st, x, ldx, rows, batch,
+                     s->n_in, s->x_mean, s->x_inv, static_cast<T*>(s->X0), (int64_t)s->in_p0,
+                     train ? static_cast<T*>(s->X0T) : nullptr, (int64_t)Mp,
+                     train ? s->noise : Noise{nullptr, 0, 0, 0});
+  HIP_TRY(hipGetLastError());
+  return forward_packed_t<T>(s, batch, final_out, ld_out, st);
+}
+
+// The layers from the packed, standardised input rows in X0 (and X0T when
+// training) onwards.
+template <class T>
+npx_status forward_packed_t(npx_sur* s, int batch, float* final_out, int64_t ld_out,
+                            hipStream_t st) {
+  const int Mp = round_up(batch, TILE);
+  const bool train = final_out == nullptr;
   const void* prev = s->X0;
   int64_t ld_prev = s->in_p0;
   for (int l = 0; l < s->n_hl; ++l) {
@@ -779,6 +821,28 @@ npx_status check_io(const npx_sur* s, const float* x, int64_t ldx, int64_t batch
 }  // namespace
 
 namespace npx {
+npx_status sur_input(npx_sur* s, int batch, SurInput* in) {
+  if (!s) return fail(NPX_EINVAL, "null surrogate handle");
+  if (batch < 0 || batch > s->max_batch)
+    return fail(NPX_EINVAL, "batch %d outside [0, %d]", batch, s->max_batch);
+  in->x = s->X0;
+  in->ld = s->in_p0;
+  in->width = s->in_p0;
+  in->rows = round_up(batch, TILE);
+  in->mean = s->x_mean;
+  in->inv_std = s->x_inv;
+  in->bf16 = s->precision != NPX_SUR_FP32;
+  return NPX_OK;
+}
+
+npx_status sur_forward_input(npx_sur* s, int batch, float* y, int64_t ldy, hipStream_t st) {
+  if (!s) return fail(NPX_EINVAL, "null surrogate handle");
+  if (batch == 0) return NPX_OK;
+  if (!y || ldy < s->n_out) return fail(NPX_EINVAL, "bad output buffer or stride");
+  return s->precision == NPX_SUR_FP32 ? forward_packed_t<float>(s, batch, y, ldy, st)
+                                      : forward_packed_t<__bf16>(s, batch, y, ldy, st);
+}
+
 void sur_dims(const npx_sur* s, int* n_in, int* n_out, int* max_batch) {
   *n_in = s->n_in;
   *n_out = s->n_out;

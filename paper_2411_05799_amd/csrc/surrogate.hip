@@ -179,31 +179,45 @@ __global__ __launch_bounds__(256) void delta_kernel(WorldView v, const float* s0
 }
 
 // ---- network inputs: one wave per instance, lanes over the features ---------
+// Values shared by the instance's features (heading, body entries in the
+// heading frame, ground height under the CoG) are computed once per wave;
+// each lane then writes its columns. STD: write the standardised value
+// (x - mean) * inv_std as OUT (the network's own input rows), zero in the
+// padding columns [nf, width) and in whole rows of instances past n_inst
+// below `rows`; otherwise the raw feature as float.
+template <class OUT, bool STD>
 __global__ __launch_bounds__(256) void features_kernel(WorldView v, const float* s, int64_t lds,
-                                                       int64_t frame, float* x, int64_t ldx) {
+                                                       int64_t frame, OUT* x, int64_t ldx,
+                                                       int width, int rows, const float* mean,
+                                                       const float* inv_std) {
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= v.a.n_inst) return;
   const int J = v.a.j_max;
+  const int nf = feature_width(J);
+  if (i >= v.a.n_inst) {
+    if (STD && i < rows)
+      for (int f = lane; f < width; f += 64) x[(int64_t)i * ldx + f] = static_cast<OUT>(0.f);
+    return;
+  }
   const int4 mi = v.a.morph_info[v.a.inst_morph[i]];
   const int Ji = mi.w - 1;
   const int64_t n = frame >= 0 ? frame : (int64_t)v.a.step[i];
-  const float cx = srow(v, s, lds, i, 0), cy = srow(v, s, lds, i, 1);
+  float in[13], body[13];
+#pragma unroll
+  for (int k = 0; k < 13; ++k) in[k] = srow(v, s, lds, i, k);
+  const Heading hd = heading_of(in[3], in[4], in[5], in[6]);
+  body_frame<false>(hd, in, body);
+  const float cx = in[0], cy = in[1];
   const float h0 = hf(v, cx, cy);
-  const int nf = feature_width(J);
-  float* xr = x + (int64_t)i * ldx;
-  for (int f = lane; f < nf; f += 64) {
+  body[0] = 0.f;
+  body[1] = 0.f;
+  body[2] = in[2] - h0;
+  OUT* xr = x + (int64_t)i * ldx;
+  for (int f = lane; f < width; f += 64) {
     float val = 0.f;
     if (f < 13) {
-      if (f == 2) {
-        val = srow(v, s, lds, i, 2) - h0;
-      } else if (f >= 3) {
-        float in[13], out[13];
-        for (int k = 0; k < 13; ++k) in[k] = srow(v, s, lds, i, k);
-        body_frame<false>(heading_of(in[3], in[4], in[5], in[6]), in, out);
 #pragma unroll
-        for (int k = 3; k < 13; ++k) val = f == k ? out[k] : val;
-      }
+      for (int k = 0; k < 13; ++k) val = f == k ? body[k] : val;
     } else if (f < 13 + J) {
       const int j = f - 13;
       if (j < Ji) val = srow(v, s, lds, i, 13 + j);
@@ -214,18 +228,16 @@ __global__ __launch_bounds__(256) void features_kernel(WorldView v, const float*
       const int idx = f - 13 - 2 * J;
       const int k = idx / J, j = idx % J;
       if (j < Ji) val = command(v, i, mi.z, j, n + k);
-    } else {
+    } else if (f < nf) {
       const int idx = f - 13 - 12 * J;
       const int a = idx / PATCH, b = idx % PATCH;
-      const Heading hd = heading_of(srow(v, s, lds, i, 3), srow(v, s, lds, i, 4),
-                                    srow(v, s, lds, i, 5), srow(v, s, lds, i, 6));
-      const float ch = hd.ch, sh = hd.sh;
       const float u = ((float)a - 0.5f * (PATCH - 1)) * PATCH_STEP;
       const float w = ((float)b - 0.5f * (PATCH - 1)) * PATCH_STEP;
-      const float px = cx + (ch * u - sh * w), py = cy + (sh * u + ch * w);
+      const float px = cx + (hd.ch * u - hd.sh * w), py = cy + (hd.sh * u + hd.ch * w);
       val = hf(v, px, py) - h0;
     }
-    xr[f] = val;
+    if (STD) val = f < nf ? (val - mean[f]) * inv_std[f] : 0.f;
+    xr[f] = static_cast<OUT>(val);
   }
 }
 
@@ -294,6 +306,7 @@ __global__ __launch_bounds__(64) void torque_kernel(WorldView v, const float* s,
   __shared__ float T[64][12];  // link transform in the construction frame: R (row-major), t
   __shared__ float S[64][6];   // per-link load sums: force, moment about the CoG
   __shared__ int low_n[64];
+  __shared__ int near[64];     // links whose box of points may reach the load band
   __shared__ unsigned long long low_x[64], low_y[64];
   const int i = blockIdx.x;
   const int l = threadIdx.x;
@@ -326,26 +339,37 @@ __global__ __launch_bounds__(64) void torque_kernel(WorldView v, const float* s,
     Rj[6] = C * x * z - sq * y; Rj[7] = C * y * z + sq * x; Rj[8] = cq + C * z * z;
     for (int r = 0; r < 3; ++r) tj[r] = o[r] - (Rj[3 * r] * o[0] + Rj[3 * r + 1] * o[1] + Rj[3 * r + 2] * o[2]);
   }
-  const int depth = own ? v.a.link_depth[lk0 + l] : -1;
+  // Each link's transform: its joint transform left-multiplied by its
+  // ancestors' joint transforms, nearest first (the root's is the identity).
+  // Only joint transforms are read, so one barrier separates the two phases.
   const int parent = own && l > 0 ? v.a.link_parent[lk0 + l] : 0;
-  for (int d = 0; d <= v.a.max_depth; ++d) {
-    if (depth == d) {
-      if (d == 0) {
-        for (int k = 0; k < 9; ++k) T[l][k] = Rj[k];
-        for (int k = 0; k < 3; ++k) T[l][9 + k] = 0.f;
-      } else {
-        float Rp[9], tp[3];
-        for (int k = 0; k < 9; ++k) Rp[k] = T[parent][k];
-        for (int k = 0; k < 3; ++k) tp[k] = T[parent][9 + k];
-        for (int r = 0; r < 3; ++r) {
-          for (int c = 0; c < 3; ++c)
-            T[l][3 * r + c] = Rp[3 * r] * Rj[c] + Rp[3 * r + 1] * Rj[3 + c] + Rp[3 * r + 2] * Rj[6 + c];
-          T[l][9 + r] = Rp[3 * r] * tj[0] + Rp[3 * r + 1] * tj[1] + Rp[3 * r + 2] * tj[2] + tp[r];
-        }
-      }
-    }
-    __syncthreads();
+  if (own) {
+    for (int k = 0; k < 9; ++k) T[l][k] = Rj[k];
+    for (int k = 0; k < 3; ++k) T[l][9 + k] = tj[k];
   }
+  __syncthreads();
+  float Rc[9], tc[3];
+  for (int k = 0; k < 9; ++k) Rc[k] = Rj[k];
+  for (int k = 0; k < 3; ++k) tc[k] = tj[k];
+  for (int anc = parent, it = 0; anc >= 1 && it < v.a.max_depth;
+       anc = v.a.link_parent[lk0 + anc], ++it) {
+    float Ra[9], ta[3], Rn[9], tn[3];
+    for (int k = 0; k < 9; ++k) Ra[k] = T[anc][k];
+    for (int k = 0; k < 3; ++k) ta[k] = T[anc][9 + k];
+    for (int r = 0; r < 3; ++r) {
+      for (int c = 0; c < 3; ++c)
+        Rn[3 * r + c] = Ra[3 * r] * Rc[c] + Ra[3 * r + 1] * Rc[3 + c] + Ra[3 * r + 2] * Rc[6 + c];
+      tn[r] = Ra[3 * r] * tc[0] + Ra[3 * r + 1] * tc[1] + Ra[3 * r + 2] * tc[2] + ta[r];
+    }
+    for (int k = 0; k < 9; ++k) Rc[k] = Rn[k];
+    for (int k = 0; k < 3; ++k) tc[k] = tn[k];
+  }
+  __syncthreads();
+  if (own) {
+    for (int k = 0; k < 9; ++k) T[l][k] = Rc[k];
+    for (int k = 0; k < 3; ++k) T[l][9 + k] = tc[k];
+  }
+  __syncthreads();
 
   // body CoG in the construction frame from the link masses and link CoGs
   const float ml = own ? lk[npx::LK_MASS] : 0.f;
@@ -373,11 +397,30 @@ __global__ __launch_bounds__(64) void torque_kernel(WorldView v, const float* s,
     for (int r = 0; r < 3; ++r) out[r] = R[3 * r] * y[0] + R[3 * r + 1] * y[1] + R[3 * r + 2] * y[2];
   };
 
+  // A link whose box of points lies wholly above the highest entry of the
+  // height map plus the band has no point in it; its points are not tested
+  // (the box's lowest world height: its centre's minus sum_j |w_j| e_j, w = the
+  // world z row of the link's axes). The tables list the leaf links' points
+  // first, so whole passes of the loop below are skipped.
+  if (own) {
+    const float* bx = lk + npx::LK_BOX;
+    float yb[3];
+    arm(bx[0], bx[1], bx[2], l, yb);
+    float ez = 0.f;
+    for (int j = 0; j < 3; ++j) {
+      const float wz = R[6] * T[l][j] + R[7] * T[l][3 + j] + R[8] * T[l][6 + j];
+      ez += fabsf(wz) * bx[3 + j];
+    }
+    near[l] = c[2] + yb[2] - ez <= v.a.hf_max + LOW_BAND + 1e-3f ? 1 : 0;
+  }
+  __syncthreads();
+
   // points in the load band: count and summed horizontal arms per link
 #pragma unroll 2
   for (int k = l; k < N; k += 64) {
-    const float4 p = v.a.pts[pt0 + k];
     const int kl = v.a.pt_link[pt0 + k];  // link index local to the morphology
+    if (!near[kl]) continue;
+    const float4 p = v.a.pts[pt0 + k];
     float a[3];
     arm(p.x, p.y, p.z, kl, a);
     if (c[2] + a[2] - hf(v, c[0] + a[0], c[1] + a[1]) < LOW_BAND) {
@@ -418,9 +461,10 @@ __global__ __launch_bounds__(64) void torque_kernel(WorldView v, const float* s,
     // sums over the subtree, in link order
     const unsigned long long sub = v.sub_mask[lk0 + l];
     float St[6] = {0, 0, 0, 0, 0, 0};
-    for (int k = l; k < L; ++k)
-      if ((sub >> k) & 1ull)
-        for (int r = 0; r < 6; ++r) St[r] += S[k][r];
+    for (unsigned long long m = sub; m != 0ull; m &= m - 1ull) {
+      const int k = __builtin_ctzll(m);
+      for (int r = 0; r < 6; ++r) St[r] += S[k][r];
+    }
     // the hinge anchor moves with the link (the joint rotation fixes it)
     float ao[3], ab[3], aw[3];
     arm(lk[0], lk[1], lk[2], l, ao);
@@ -495,8 +539,9 @@ npx_status npx_sur_features(npx_world* w, const float* s, int64_t lds, int64_t f
   if (s && lds < state_width(v.a.j_max)) return fail(NPX_EINVAL, "state stride too small");
   if (s && frame < 0) return fail(NPX_EINVAL, "state rows need a frame >= 0");
   hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL(features_kernel, dim3((unsigned)((v.a.n_inst + 3) / 4)), dim3(256), 0, st, v,
-                     s, lds, s ? frame : (int64_t)-1, x, ldx);
+  hipLaunchKernelGGL((features_kernel<float, false>), dim3((unsigned)((v.a.n_inst + 3) / 4)),
+                     dim3(256), 0, st, v, s, lds, s ? frame : (int64_t)-1, x, ldx,
+                     feature_width(v.a.j_max), 0, nullptr, nullptr);
   HIP_TRY(hipGetLastError());
   npx::note_stream(w, st);
   return NPX_OK;
@@ -566,11 +611,27 @@ npx_status npx_sur_rollout(npx_sur* net, npx_world* w, float* s, int64_t lds, in
     return fail(NPX_EINVAL, "network batch limit %d < %d instances", max_batch, v.a.n_inst);
   if (n_calls < 0 || frame0 < 0) return fail(NPX_EINVAL, "negative call count or frame");
   if (!y_work || ldy < n_out) return fail(NPX_EINVAL, "bad output workspace");
+  if (!s || lds < n_out) return fail(NPX_EINVAL, "bad state buffer or stride");
+  if (!x_work || ldx < n_in) return fail(NPX_EINVAL, "bad feature workspace");
+  // The features go straight into the network's own standardised input rows
+  // (what npx_sur_forward would make of x_work), so x_work is left unused.
+  if (n_calls == 0 || v.a.n_inst == 0) return NPX_OK;
+  npx::SurInput in{};
+  if ((r = npx::sur_input(net, v.a.n_inst, &in)) != NPX_OK) return r;
+  hipStream_t st = (hipStream_t)stream;
+  const unsigned blocks = (unsigned)((in.rows + 3) / 4);
   for (int c = 0; c < n_calls; ++c) {
     const int64_t frame = frame0 + (int64_t)c * HORIZON;
-    if ((r = npx_sur_features(w, s, lds, frame, x_work, ldx, stream)) != NPX_OK) return r;
-    if ((r = npx_sur_forward(net, x_work, ldx, nullptr, v.a.n_inst, y_work, ldy, stream)) != NPX_OK)
-      return r;
+    if (in.bf16)
+      hipLaunchKernelGGL((features_kernel<__bf16, true>), dim3(blocks), dim3(256), 0, st, v, s,
+                         lds, frame, static_cast<__bf16*>(in.x), in.ld, in.width, in.rows,
+                         in.mean, in.inv_std);
+    else
+      hipLaunchKernelGGL((features_kernel<float, true>), dim3(blocks), dim3(256), 0, st, v, s,
+                         lds, frame, static_cast<float*>(in.x), in.ld, in.width, in.rows,
+                         in.mean, in.inv_std);
+    HIP_TRY(hipGetLastError());
+    if ((r = npx::sur_forward_input(net, v.a.n_inst, y_work, ldy, st)) != NPX_OK) return r;
     if ((r = npx_sur_advance(w, s, lds, y_work, ldy, frame, stream)) != NPX_OK) return r;
     if (tau_acc && (r = npx_sur_torque(w, s, lds, tau_acc, 1, stream)) != NPX_OK) return r;
   }
