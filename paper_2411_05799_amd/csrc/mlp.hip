@@ -247,57 +247,65 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(GemmArgs<__bf16> g) {
   const int m0 = (tile / tiles_n) * BIG + (wave >> 1) * 64;
   const int n0 = (tile % tiles_n) * BIG + (wave & 1) * 64;
   const int r32 = lane & 31, grp = lane >> 5;
-  // K is walked in chunks of 64. In a chunk, lane (r32, grp) holds k in
-  // [32 grp, 32 grp + 32) of its A and B rows as four 8-element slices and
-  // step j of the chunk multiplies slice j of both operands: every k meets
-  // its partner exactly once, each lane reads 64 contiguous bytes of a row
-  // per chunk, and the next chunk's loads are in flight during the current
-  // chunk's 16 products.
-  const __bf16* a0 = g.A + (int64_t)(m0 + r32) * g.lda + grp * 32;
-  const __bf16* a1 = a0 + 32 * g.lda;
-  const __bf16* b0 = g.B + (int64_t)(n0 + r32) * g.ldb + grp * 32;
-  const __bf16* b1 = b0 + 32 * g.ldb;
+  // K is walked in chunks of 64. The block stages each chunk of its 128 A rows
+  // and 128 B rows in LDS (coalesced 16-byte loads, eight lanes per row; the
+  // next chunk's loads are in flight while the current one is multiplied,
+  // two LDS buffers, one barrier per chunk), so a row is fetched once per
+  // block rather than once per wave. In a chunk, lane (r32, grp) takes k in
+  // [32 grp, 32 grp + 32) of its rows as four 8-element slices and product j
+  // multiplies slice j of both operands: every k meets its partner once.
+  // Rows are padded to 72 elements so that eight lanes reading eight rows
+  // touch 32 distinct banks.
+  constexpr int KC = 64, LDR = KC + 8;
+  __shared__ __bf16 As[2][BIG][LDR];
+  __shared__ __bf16 Bs[2][BIG][LDR];
+  const int mt = (tile / tiles_n) * BIG, nt = (tile % tiles_n) * BIG;
+  const int t = threadIdx.x;
+  auto ld = [](const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); };
+  bf16x8 ga[4], gb[4];
+  auto fetch = [&](int k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int piece = t + 256 * i, row = piece >> 3, c8 = (piece & 7) * 8;
+      ga[i] = ld(g.A + (int64_t)(mt + row) * g.lda + k0 + c8);
+      gb[i] = ld(g.B + (int64_t)(nt + row) * g.ldb + k0 + c8);
+    }
+  };
+  auto stage = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int piece = t + 256 * i, row = piece >> 3, c8 = (piece & 7) * 8;
+      *reinterpret_cast<bf16x8*>(&As[buf][row][c8]) = ga[i];
+      *reinterpret_cast<bf16x8*>(&Bs[buf][row][c8]) = gb[i];
+    }
+  };
   f32x16 acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j)
       for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
-  auto ld = [](const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); };
-  bf16x8 fa[2][4], fb[2][4];
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  fetch(0);
+  stage(0);
+  __syncthreads();
+  const int n_chunks = g.K / KC;
+  for (int c = 0; c < n_chunks; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < n_chunks) fetch((c + 1) * KC);
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    fa[0][j] = ld(a0 + 8 * j);
-    fa[1][j] = ld(a1 + 8 * j);
-    fb[0][j] = ld(b0 + 8 * j);
-    fb[1][j] = ld(b1 + 8 * j);
+    for (int j = 0; j < 4; ++j) {
+      const int kk = 32 * grp + 8 * j;
+      const bf16x8 fa0 = *reinterpret_cast<const bf16x8*>(&As[buf][wm + r32][kk]);
+      const bf16x8 fa1 = *reinterpret_cast<const bf16x8*>(&As[buf][wm + 32 + r32][kk]);
+      const bf16x8 fb0 = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn + r32][kk]);
+      const bf16x8 fb1 = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn + 32 + r32][kk]);
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa0, fb0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa0, fb1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa1, fb0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa1, fb1, acc[1][1], 0, 0, 0);
+    }
+    if (c + 1 < n_chunks) stage(buf ^ 1);
+    __syncthreads();
   }
-  auto chunk = [&]() __attribute__((always_inline)) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0][j], fb[0][j], acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0][j], fb[1][j], acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[1][j], fb[0][j], acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[1][j], fb[1][j], acc[1][1], 0, 0, 0);
-    }
-  };
-  for (int k = 64; k < g.K; k += 64) {
-    bf16x8 na[2][4], nb[2][4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      na[0][j] = ld(a0 + k + 8 * j);
-      na[1][j] = ld(a1 + k + 8 * j);
-      nb[0][j] = ld(b0 + k + 8 * j);
-      nb[1][j] = ld(b1 + k + 8 * j);
-    }
-    chunk();
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      fa[0][j] = na[0][j];
-      fa[1][j] = na[1][j];
-      fb[0][j] = nb[0][j];
-      fb[1][j] = nb[1][j];
-    }
-  }
-  chunk();
 
   for (int i = 0; i < 2; ++i) {
     for (int j = 0; j < 2; ++j) {

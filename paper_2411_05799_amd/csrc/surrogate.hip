@@ -213,7 +213,16 @@ __global__ __launch_bounds__(256) void features_kernel(WorldView v, const float*
   body[1] = 0.f;
   body[2] = in[2] - h0;
   OUT* xr = x + (int64_t)i * ldx;
-  for (int f = lane; f < width; f += 64) {
+  auto put = [&](int f, float val) __attribute__((always_inline)) {
+    if (STD) val = f < nf ? (val - mean[f]) * inv_std[f] : 0.f;
+    xr[f] = static_cast<OUT>(val);
+  };
+  // The three kinds of columns go in separate passes so that the lanes of a
+  // pass do the same work: body, joint angles and rates; the commanded
+  // targets of frames n .. n+9 (joint j of frame n + k at 13 + 2J + kJ + j);
+  // the height patch and the padding.
+  const int c_cmd = 13 + 2 * J, c_patch = 13 + 12 * J;
+  for (int f = lane; f < c_cmd; f += 64) {
     float val = 0.f;
     if (f < 13) {
 #pragma unroll
@@ -221,23 +230,38 @@ __global__ __launch_bounds__(256) void features_kernel(WorldView v, const float*
     } else if (f < 13 + J) {
       const int j = f - 13;
       if (j < Ji) val = srow(v, s, lds, i, 13 + j);
-    } else if (f < 13 + 2 * J) {
+    } else {
       const int j = f - 13 - J;
       if (j < Ji) val = (srow(v, s, lds, i, 13 + j) - srow(v, s, lds, i, 13 + J + j)) * v.a.inv_dt;
-    } else if (f < 13 + 12 * J) {
-      const int idx = f - 13 - 2 * J;
-      const int k = idx / J, j = idx % J;
-      if (j < Ji) val = command(v, i, mi.z, j, n + k);
-    } else if (f < nf) {
-      const int idx = f - 13 - 12 * J;
+    }
+    put(f, val);
+  }
+  {
+    // (k, j) of column c_cmd + lane, then stepped by 64 columns per pass
+    // without a division in the loop
+    int k = lane / J, j = lane - (lane / J) * J;
+    const int dk = 64 / J, dj = 64 - (64 / J) * J;
+    for (int f = c_cmd + lane; f < c_patch; f += 64) {
+      put(f, j < Ji ? command(v, i, mi.z, j, n + k) : 0.f);
+      k += dk;
+      j += dj;
+      if (j >= J) {
+        j -= J;
+        k += 1;
+      }
+    }
+  }
+  for (int f = c_patch + lane; f < width; f += 64) {
+    float val = 0.f;
+    if (f < nf) {
+      const int idx = f - c_patch;
       const int a = idx / PATCH, b = idx % PATCH;
       const float u = ((float)a - 0.5f * (PATCH - 1)) * PATCH_STEP;
       const float w = ((float)b - 0.5f * (PATCH - 1)) * PATCH_STEP;
       const float px = cx + (hd.ch * u - hd.sh * w), py = cy + (hd.sh * u + hd.ch * w);
       val = hf(v, px, py) - h0;
     }
-    if (STD) val = f < nf ? (val - mean[f]) * inv_std[f] : 0.f;
-    xr[f] = static_cast<OUT>(val);
+    put(f, val);
   }
 }
 
@@ -283,9 +307,25 @@ __global__ __launch_bounds__(256) void advance_kernel(WorldView v, float* s, int
 }
 
 // ---- torque proxy: one wave per instance -------------------------------------
+// Sum over the wave, the same bits in every lane: DPP adds with the quad
+// partners, the mirrored half-row and row, then the other row and the other
+// half-wave through permlane swaps.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
 __device__ __forceinline__ float wave_sum(float x) {
-  for (int m = 1; m < 64; m <<= 1) x += __shfl_xor(x, m);
-  return x;
+  x += dpp_f<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += dpp_f<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += dpp_f<0x141>(x);  // row_half_mirror
+  x += dpp_f<0x140>(x);  // row_mirror
+  auto r16 = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, x),
+                                              __builtin_bit_cast(unsigned, x), false, false);
+  x = __builtin_bit_cast(float, (unsigned)r16[0]) + __builtin_bit_cast(float, (unsigned)r16[1]);
+  auto r32 = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, x),
+                                              __builtin_bit_cast(unsigned, x), false, false);
+  return __builtin_bit_cast(float, (unsigned)r32[0]) + __builtin_bit_cast(float, (unsigned)r32[1]);
 }
 
 // Quasi-static joint torque: every point carries its weight m_k g, and the
