@@ -23,6 +23,7 @@
 
 #include "npx.h"
 #include "npx_internal.h"
+#include "npx_sur_internal.h"
 
 using npx::fail;
 

@@ -28,6 +28,7 @@
 #include "npx.h"
 #include "npx_device.h"
 #include "npx_internal.h"
+#include "npx_sur_internal.h"
 
 using npx::fail;
 
