@@ -91,6 +91,11 @@ __device__ __forceinline__ T to_t(float x) {
 }
 
 __device__ __forceinline__ float sigmoid(float z) { return 1.0f / (1.0f + __expf(-z)); }
+// With the hardware reciprocal (about 1 ulp) instead of a correctly rounded
+// divide: for activations that are rounded to BF16 next.
+__device__ __forceinline__ float sigmoid_fast(float z) {
+  return __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+}
 
 enum Epi { EPI_HID = 0, EPI_OUT = 1, EPI_DX = 2, EPI_DW = 3 };
 
@@ -344,6 +349,151 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(GemmArgs<__bf16> g) {
   }
 }
 
+// ---- the whole forward pass of an inference network in one kernel ----------
+// A block takes 128 input rows through every layer with the activations kept
+// in LDS (BF16, rows padded by 8 elements against bank conflicts), so only
+// the input rows and the outputs cross HBM. Eight waves, two per SIMD, so
+// that one wave's matrix products overlap the other's activation epilogue.
+// Hidden layer: wave w computes rows [64 (w / 4), + 64) x columns
+// [(w % 4) NB 32, + NB 32) as 2 x NB blocks of v_mfma_f32_32x32x16_bf16, A
+// from LDS, B (the weights, k-contiguous rows) straight from global memory
+// in 64-wide K chunks with the next chunk's loads in flight (lane group g
+// takes k in [32 g, 32 g + 32) of the chunk as four slices, product j the
+// j-th slice of both operands); then every wave waits, writes SiLU(z) over
+// the layer's input and waits again. Output layer (64 padded columns): wave w
+// takes the 32 x 32 block (rows 32 (w / 2), columns 32 (w % 2)).
+constexpr int MAX_LAYERS = 8;  // hidden layers + output layer
+constexpr int FB_M = 128, FB_KMAX = 512, FB_LDA = FB_KMAX + 8;
+
+struct FusedArgs {
+  const __bf16* X;  // [M][ldx] standardised input rows (zero padded)
+  int64_t ldx;
+  int M, K0, H, n_hl;          // rows (multiple of 128), input width, hidden width (128 NB)
+  const __bf16* W[MAX_LAYERS];  // layer l: [out_p][in_p] BF16, k contiguous
+  int ldw[MAX_LAYERS];
+  const float* b[MAX_LAYERS];
+  float* y;  // [m_valid][ldy] de-standardised outputs
+  int64_t ldy;
+  int n_out, m_valid;
+  const float* y_std;
+  const float* y_mean;
+};
+
+template <int NB>
+__global__ __launch_bounds__(512) void mlp_fused_kernel(FusedArgs f) {
+  __shared__ __bf16 act[FB_M][FB_LDA];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = threadIdx.x;
+  const int r32 = lane & 31, grp = lane >> 5;
+  int blk = blockIdx.x;
+  const int nb = gridDim.x;
+  if ((nb & 7) == 0) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
+  const int m0 = blk * FB_M;
+  auto ld8 = [](const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); };
+
+  // input rows into LDS: 16-byte pieces, K0 / 8 per row
+  {
+    const int per_row = f.K0 / 8;
+    for (int piece = t; piece < FB_M * per_row; piece += 512) {
+      const int row = piece / per_row, c8 = (piece - row * per_row) * 8;
+      *reinterpret_cast<bf16x8*>(&act[row][c8]) = ld8(f.X + (int64_t)(m0 + row) * f.ldx + c8);
+    }
+  }
+  __syncthreads();
+
+  const int r_base = (wave >> 2) * 64;
+  for (int l = 0; l < f.n_hl; ++l) {
+    const int K = l == 0 ? f.K0 : f.H;
+    const int n_base = (wave & 3) * NB * 32;
+    const __bf16* wrow[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) wrow[c] = f.W[l] + (int64_t)(n_base + 32 * c + r32) * f.ldw[l] + grp * 32;
+    f32x16 acc[2][NB];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[i][c][e] = 0.f;
+    bf16x8 fb[NB][4];
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) fb[c][j] = ld8(wrow[c] + 8 * j);
+    for (int k0 = 0; k0 < K; k0 += 64) {
+      bf16x8 nbf[NB][4];
+      const bool more = k0 + 64 < K;
+      if (more) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) nbf[c][j] = ld8(wrow[c] + k0 + 64 + 8 * j);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int kk = k0 + 32 * grp + 8 * j;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const bf16x8 fa = *reinterpret_cast<const bf16x8*>(&act[r_base + 32 * i + r32][kk]);
+#pragma unroll
+          for (int c = 0; c < NB; ++c)
+            acc[i][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa, fb[c][j], acc[i][c], 0, 0, 0);
+        }
+      }
+      if (more) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) fb[c][j] = nbf[c][j];
+      }
+    }
+    __syncthreads();  // every wave has read the layer's input
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      const int col = n_base + 32 * c + r32;
+      const float bc = f.b[l][col];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float z = acc[i][c][4 * q + e] + bc;
+            act[r_base + 32 * i + 8 * q + 4 * grp + e][col] = (__bf16)(z * sigmoid_fast(z));
+          }
+    }
+    __syncthreads();  // the layer's output is complete
+  }
+
+  // output layer: 64 padded columns, 32 x 32 per wave
+  {
+    const int L = f.n_hl;
+    const int ro = 32 * (wave >> 1), co = 32 * (wave & 1);
+    const __bf16* w0 = f.W[L] + (int64_t)(co + r32) * f.ldw[L] + grp * 32;
+    f32x16 acc;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[e] = 0.f;
+    for (int k0 = 0; k0 < f.H; k0 += 64) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int kk = k0 + 32 * grp + 8 * j;
+        const bf16x8 fa = *reinterpret_cast<const bf16x8*>(&act[ro + r32][kk]);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa, ld8(w0 + k0 + 8 * j), acc, 0, 0, 0);
+      }
+    }
+    const int col = co + r32;
+    if (col < f.n_out) {
+      const float bc = f.b[L][col], sc = f.y_std[col], sh = f.y_mean[col];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = m0 + ro + 8 * q + 4 * grp + e;
+          if (row < f.m_valid) f.y[(int64_t)row * f.ldy + col] = (acc[4 * q + e] + bc) * sc + sh;
+        }
+    }
+  }
+}
+
 // ---- layer-0 input: gather rows, standardise, pad, write X and X^T ---------
 // Block: 64 rows x 64 columns through an LDS tile.
 // Training noise (optional): noise[r][j] is added to input column nc0 + j of
@@ -441,7 +591,6 @@ __global__ void loss_final_kernel(const double* partial, int n, double inv_count
 
 // ---- parameter-vector kernels ----------------------------------------------
 // The padded parameter vector holds, per layer, W [out_p][in_p] then b [out_p].
-constexpr int MAX_LAYERS = 8;
 struct LayerTable {
   int n_layers;
   int64_t off[MAX_LAYERS + 1];  // start of each layer's block in the padded vector
@@ -701,6 +850,41 @@ npx_status forward_packed_t(npx_sur* s, int batch, float* final_out, int64_t ld_
                             hipStream_t st) {
   const int Mp = round_up(batch, TILE);
   const bool train = final_out == nullptr;
+  if constexpr (std::is_same<T, __bf16>::value) {
+    // inference over whole 128-row blocks of a network whose widths fit the
+    // fused kernel: one launch for all layers
+    const int nb = s->hp / 128;
+    if (!train && Mp % FB_M == 0 && s->hp % 128 == 0 && nb >= 1 && nb <= 4 &&
+        s->in_p0 <= FB_KMAX && s->out_p == 64 && s->n_hl >= 1 && s->n_layers <= MAX_LAYERS) {
+      FusedArgs f{};
+      f.X = static_cast<const __bf16*>(s->X0);
+      f.ldx = s->in_p0;
+      f.M = Mp;
+      f.K0 = s->in_p0;
+      f.H = s->hp;
+      f.n_hl = s->n_hl;
+      for (int l = 0; l < s->n_layers; ++l) {
+        f.W[l] = wc<__bf16>(s, l);
+        f.ldw[l] = s->tab.in_p[l];
+        f.b[l] = bias(s, l);
+      }
+      f.y = final_out;
+      f.ldy = ld_out;
+      f.n_out = s->n_out;
+      f.m_valid = batch;
+      f.y_std = s->y_std;
+      f.y_mean = s->y_mean;
+      const dim3 grid(Mp / FB_M), block(512);
+      switch (nb) {
+        case 1: hipLaunchKernelGGL(mlp_fused_kernel<1>, grid, block, 0, st, f); break;
+        case 2: hipLaunchKernelGGL(mlp_fused_kernel<2>, grid, block, 0, st, f); break;
+        case 3: hipLaunchKernelGGL(mlp_fused_kernel<3>, grid, block, 0, st, f); break;
+        default: hipLaunchKernelGGL(mlp_fused_kernel<4>, grid, block, 0, st, f); break;
+      }
+      HIP_TRY(hipGetLastError());
+      return NPX_OK;
+    }
+  }
   const void* prev = s->X0;
   int64_t ld_prev = s->in_p0;
   for (int l = 0; l < s->n_hl; ++l) {

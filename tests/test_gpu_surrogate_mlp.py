@@ -15,6 +15,10 @@ def _torch():
     return torch
 
 
+def say(msg):
+    print(msg, flush=True)
+
+
 def bf16_round(a):
     """Round to the nearest BF16 value (ties to even), returned as float64."""
     f = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
@@ -284,26 +288,35 @@ def test_training_noise_shifts_inputs_and_targets():
     s.close()
 
 
-def test_forward_bf16_large_batch_matches_oracle_on_sampled_rows():
-    """65,536 rows take the 128x128 tiles of the large-batch forward: sampled
-    rows against the FP64 reference (BF16-representable inputs and weights)."""
+@pytest.mark.parametrize("shape", [
+    dict(n_in=293, n_hidden=256, n_hidden_layers=3, n_out=49),    # one fused launch
+    dict(n_in=293, n_hidden=384, n_hidden_layers=4, n_out=49),    # fused, three blocks per wave
+    dict(n_in=293, n_hidden=256, n_hidden_layers=3, n_out=100),   # layer by layer, 128x128 tiles
+], ids=["fused256", "fused384", "tiled"])
+def test_forward_bf16_large_batch_matches_oracle_on_sampled_rows(shape):
+    """65,536 rows: the whole-network kernel (widths it takes) or the 128x128
+    tiles of the layer-by-layer forward (an output wider than 64): sampled rows
+    against the FP64 reference (BF16-representable inputs and weights)."""
     from paper_2411_05799_amd import native as N
     torch = _torch()
     rng = np.random.default_rng(12)
     B = 65536
-    x = bf16_round(rng.normal(0.3, 1.7, size=(B, SHAPE["n_in"]))).astype(np.float32)
-    s = N.Surrogate(max_batch=B, precision=N.SUR_BF16, training=False, seed=2, **SHAPE)
+    n_in, n_out = shape["n_in"], shape["n_out"]
+    say(f"case: large batch forward {shape}")
+    x = bf16_round(rng.normal(0.3, 1.7, size=(B, n_in))).astype(np.float32)
+    s = N.Surrogate(max_batch=B, precision=N.SUR_BF16, training=False, seed=2, **shape)
     s.set_params(bf16_round(s.get_params()))
-    ym, ys = rng.normal(size=49), rng.uniform(0.5, 2.0, size=49)
-    s.set_norm(np.zeros(SHAPE["n_in"]), np.ones(SHAPE["n_in"]), ym, ys)
+    ym, ys = rng.normal(size=n_out), rng.uniform(0.5, 2.0, size=n_out)
+    s.set_norm(np.zeros(n_in), np.ones(n_in), ym, ys)
     p = s.get_params().astype(np.float64)
-    out = torch.zeros((B, 49), device="cuda")
+    out = torch.zeros((B, n_out), device="cuda")
     s.forward(_dev(x), out)
     torch.cuda.synchronize()
     rows = np.sort(rng.choice(B, 512, replace=False))
     f32 = np.float32
-    ref = M.predict(p, _shapes(), x[rows].astype(np.float64), np.zeros(SHAPE["n_in"]),
-                    np.ones(SHAPE["n_in"]), ym.astype(f32), ys.astype(f32))
+    shapes = M.layer_shapes(n_in, shape["n_hidden"], shape["n_hidden_layers"], n_out)
+    ref = M.predict(p, shapes, x[rows].astype(np.float64), np.zeros(n_in), np.ones(n_in),
+                    ym.astype(f32), ys.astype(f32))
     got = out.cpu().numpy()[rows].astype(np.float64)
     assert np.linalg.norm(got - ref) <= 1e-2 * np.linalg.norm(ref - ym.astype(f32))
     assert np.isfinite(out.cpu().numpy()).all()
