@@ -282,7 +282,7 @@ npx_status npx_sur_set_norm(npx_sur* s, const float* x_mean, const float* x_std,
 npx_status npx_sur_set_adam(npx_sur* s, double beta1, double beta2, double eps);
 /* y[b] = network(x[rows[b]]) in raw units, b < batch <= max_batch.  Each
  * call is deterministic; a BF16 network whose hidden width is a multiple of
- * 128 (up to 512) runs whole 128-row blocks in one kernel and other batches
+ * 128 (up to 384) runs whole 128-row blocks in one kernel and other batches
  * layer by layer, so a row's result can differ in the last bits between
  * batches of the two kinds. */
 npx_status npx_sur_forward(npx_sur* s, const float* x, int64_t ldx, const int32_t* rows,

@@ -363,7 +363,7 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(GemmArgs<__bf16> g) {
 // the layer's input and waits again. Output layer (64 padded columns): wave w
 // takes the 32 x 32 block (rows 32 (w / 2), columns 32 (w % 2)).
 constexpr int MAX_LAYERS = 8;  // hidden layers + output layer
-constexpr int FB_M = 128, FB_KMAX = 512, FB_LDA = FB_KMAX + 8;
+constexpr int FB_M = 128, FB_KMAX = 384, FB_LDA = FB_KMAX + 8, FB_WLD = 64 + 8;
 
 struct FusedArgs {
   const __bf16* X;  // [M][ldx] standardised input rows (zero padded)
@@ -382,6 +382,7 @@ struct FusedArgs {
 template <int NB>
 __global__ __launch_bounds__(512) void mlp_fused_kernel(FusedArgs f) {
   __shared__ __bf16 act[FB_M][FB_LDA];
+  __shared__ __bf16 wst[FB_KMAX][FB_WLD];  // one 64-wide K chunk of a layer's weights
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = threadIdx.x;
   const int r32 = lane & 31, grp = lane >> 5;
   int blk = blockIdx.x;
@@ -401,12 +402,23 @@ __global__ __launch_bounds__(512) void mlp_fused_kernel(FusedArgs f) {
   __syncthreads();
 
   const int r_base = (wave >> 2) * 64;
+  constexpr int PIECES = 2 * NB;  // 16-byte pieces of a weight chunk per thread
   for (int l = 0; l < f.n_hl; ++l) {
     const int K = l == 0 ? f.K0 : f.H;
     const int n_base = (wave & 3) * NB * 32;
-    const __bf16* wrow[NB];
+    // the layer's weights go through LDS in 64-wide K chunks (rows padded to
+    // 72 elements), each 16-byte piece fetched once per block; the next
+    // chunk's pieces are in registers while the current one is multiplied
+    const __bf16* wl = f.W[l];
+    const int ldw = f.ldw[l];
+    bf16x8 stage[PIECES];
+    auto fetch = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
-    for (int c = 0; c < NB; ++c) wrow[c] = f.W[l] + (int64_t)(n_base + 32 * c + r32) * f.ldw[l] + grp * 32;
+      for (int i = 0; i < PIECES; ++i) {
+        const int piece = t + 512 * i, row = piece >> 3, c8 = (piece & 7) * 8;
+        stage[i] = ld8(wl + (int64_t)row * ldw + k0 + c8);
+      }
+    };
     f32x16 acc[2][NB];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -414,36 +426,30 @@ __global__ __launch_bounds__(512) void mlp_fused_kernel(FusedArgs f) {
       for (int c = 0; c < NB; ++c)
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[i][c][e] = 0.f;
-    bf16x8 fb[NB][4];
-#pragma unroll
-    for (int c = 0; c < NB; ++c)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) fb[c][j] = ld8(wrow[c] + 8 * j);
+    fetch(0);
     for (int k0 = 0; k0 < K; k0 += 64) {
-      bf16x8 nbf[NB][4];
-      const bool more = k0 + 64 < K;
-      if (more) {
+      __syncthreads();  // the previous chunk's weights are no longer read
 #pragma unroll
-        for (int c = 0; c < NB; ++c)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) nbf[c][j] = ld8(wrow[c] + k0 + 64 + 8 * j);
+      for (int i = 0; i < PIECES; ++i) {
+        const int piece = t + 512 * i, row = piece >> 3, c8 = (piece & 7) * 8;
+        *reinterpret_cast<bf16x8*>(&wst[row][c8]) = stage[i];
       }
+      __syncthreads();
+      if (k0 + 64 < K) fetch(k0 + 64);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int kk = k0 + 32 * grp + 8 * j;
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          const bf16x8 fa = *reinterpret_cast<const bf16x8*>(&act[r_base + 32 * i + r32][kk]);
-#pragma unroll
-          for (int c = 0; c < NB; ++c)
-            acc[i][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa, fb[c][j], acc[i][c], 0, 0, 0);
-        }
-      }
-      if (more) {
+        const int kk = 32 * grp + 8 * j;
+        bf16x8 fb[NB];
 #pragma unroll
         for (int c = 0; c < NB; ++c)
+          fb[c] = *reinterpret_cast<const bf16x8*>(&wst[n_base + 32 * c + r32][kk]);
 #pragma unroll
-          for (int j = 0; j < 4; ++j) fb[c][j] = nbf[c][j];
+        for (int i = 0; i < 2; ++i) {
+          const bf16x8 fa = *reinterpret_cast<const bf16x8*>(&act[r_base + 32 * i + r32][k0 + kk]);
+#pragma unroll
+          for (int c = 0; c < NB; ++c)
+            acc[i][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa, fb[c], acc[i][c], 0, 0, 0);
+        }
       }
     }
     __syncthreads();  // every wave has read the layer's input
@@ -854,7 +860,7 @@ npx_status forward_packed_t(npx_sur* s, int batch, float* final_out, int64_t ld_
     // inference over whole 128-row blocks of a network whose widths fit the
     // fused kernel: one launch for all layers
     const int nb = s->hp / 128;
-    if (!train && Mp % FB_M == 0 && s->hp % 128 == 0 && nb >= 1 && nb <= 4 &&
+    if (!train && Mp % FB_M == 0 && s->hp % 128 == 0 && nb >= 1 && nb <= 3 &&
         s->in_p0 <= FB_KMAX && s->out_p == 64 && s->n_hl >= 1 && s->n_layers <= MAX_LAYERS) {
       FusedArgs f{};
       f.X = static_cast<const __bf16*>(s->X0);
@@ -878,8 +884,7 @@ npx_status forward_packed_t(npx_sur* s, int batch, float* final_out, int64_t ld_
       switch (nb) {
         case 1: hipLaunchKernelGGL(mlp_fused_kernel<1>, grid, block, 0, st, f); break;
         case 2: hipLaunchKernelGGL(mlp_fused_kernel<2>, grid, block, 0, st, f); break;
-        case 3: hipLaunchKernelGGL(mlp_fused_kernel<3>, grid, block, 0, st, f); break;
-        default: hipLaunchKernelGGL(mlp_fused_kernel<4>, grid, block, 0, st, f); break;
+        default: hipLaunchKernelGGL(mlp_fused_kernel<3>, grid, block, 0, st, f); break;
       }
       HIP_TRY(hipGetLastError());
       return NPX_OK;
