@@ -308,15 +308,17 @@ __global__ __launch_bounds__(256) void advance_kernel(WorldView v, float* s, int
 }
 
 // ---- torque proxy: one wave per instance -------------------------------------
-// Sum over the wave, the same bits in every lane: DPP adds with the quad
-// partners, the mirrored half-row and row, then the other row and the other
-// half-wave through permlane swaps.
+// Sum over a segment of G lanes (32 or 64), the same bits in every lane of
+// it: DPP adds with the quad partners, the mirrored half-row and row, then
+// the other row and (G = 64) the other half-wave through permlane swaps.
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float x) {
   return __builtin_bit_cast(
       float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
 }
-__device__ __forceinline__ float wave_sum(float x) {
+template <int G>
+__device__ __forceinline__ float seg_sum(float x) {
+  static_assert(G == 32 || G == 64, "segment of 32 or 64 lanes");
   x += dpp_f<0xB1>(x);   // quad_perm [1,0,3,2]
   x += dpp_f<0x4E>(x);   // quad_perm [2,3,0,1]
   x += dpp_f<0x141>(x);  // row_half_mirror
@@ -324,9 +326,12 @@ __device__ __forceinline__ float wave_sum(float x) {
   auto r16 = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, x),
                                               __builtin_bit_cast(unsigned, x), false, false);
   x = __builtin_bit_cast(float, (unsigned)r16[0]) + __builtin_bit_cast(float, (unsigned)r16[1]);
-  auto r32 = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, x),
-                                              __builtin_bit_cast(unsigned, x), false, false);
-  return __builtin_bit_cast(float, (unsigned)r32[0]) + __builtin_bit_cast(float, (unsigned)r32[1]);
+  if constexpr (G == 64) {
+    auto r32 = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, x),
+                                                __builtin_bit_cast(unsigned, x), false, false);
+    x = __builtin_bit_cast(float, (unsigned)r32[0]) + __builtin_bit_cast(float, (unsigned)r32[1]);
+  }
+  return x;
 }
 
 // Quasi-static joint torque: every point carries its weight m_k g, and the
@@ -342,18 +347,31 @@ __device__ __forceinline__ float wave_sum(float x) {
 // independent of timing.
 constexpr double FIX = 1073741824.0;
 
+// One robot per segment of G lanes (32 when every robot has at most 32 links:
+// two robots per wave), lane l of the segment owning link l. A segment past
+// the last instance takes part in the barriers with no links and no points.
+template <int G>
 __global__ __launch_bounds__(64) void torque_kernel(WorldView v, const float* s, int64_t lds,
                                                     float* acc, int accumulate) {
-  __shared__ float T[64][12];  // link transform in the construction frame: R (row-major), t
-  __shared__ float S[64][6];   // per-link load sums: force, moment about the CoG
-  __shared__ int low_n[64];
-  __shared__ int near[64];     // links whose box of points may reach the load band
-  __shared__ unsigned long long low_x[64], low_y[64];
-  const int i = blockIdx.x;
-  const int l = threadIdx.x;
+  constexpr int IPW = 64 / G;
+  __shared__ float Tsh[IPW][G][12];  // link transforms in the construction frame: R, t
+  __shared__ float Ssh[IPW][G][6];   // per-link load sums: force, moment about the CoG
+  __shared__ int low_nsh[IPW][G];
+  __shared__ int nearsh[IPW][G];     // links whose box of points may reach the load band
+  __shared__ unsigned long long low_xsh[IPW][G], low_ysh[IPW][G];
+  const int seg = threadIdx.x / G;
+  const int l = threadIdx.x - seg * G;
+  float (*T)[12] = Tsh[seg];
+  float (*S)[6] = Ssh[seg];
+  int* low_n = low_nsh[seg];
+  int* near = nearsh[seg];
+  unsigned long long* low_x = low_xsh[seg];
+  unsigned long long* low_y = low_ysh[seg];
   const int I = v.a.n_inst;
+  const bool live = blockIdx.x * IPW + seg < I;
+  const int i = live ? blockIdx.x * IPW + seg : 0;
   const int4 mi = v.a.morph_info[v.a.inst_morph[i]];
-  const int N = mi.y, L = mi.w, pt0 = mi.x, lk0 = mi.z;
+  const int N = live ? mi.y : 0, L = live ? mi.w : 0, pt0 = mi.x, lk0 = mi.z;
   const bool own = l < L;
   const float* lk = v.a.links + (int64_t)(lk0 + (own ? l : 0)) * LINK_F;
   low_n[l] = 0;
@@ -422,7 +440,7 @@ __global__ __launch_bounds__(64) void torque_kernel(WorldView v, const float* s,
   }
   const float M = v.a.morph_mass[v.a.inst_morph[i]];
   float gb[3];
-  for (int r = 0; r < 3; ++r) gb[r] = wave_sum(ml * yc[r]) / M;
+  for (int r = 0; r < 3; ++r) gb[r] = seg_sum<G>(ml * yc[r]) / M;
   float c[3], R[9];
   for (int r = 0; r < 3; ++r) c[r] = s ? s[(int64_t)i * lds + r] : v.a.st[(int64_t)r * I + i];
   {
@@ -458,7 +476,7 @@ __global__ __launch_bounds__(64) void torque_kernel(WorldView v, const float* s,
 
   // points in the load band: count and summed horizontal arms per link
 #pragma unroll 2
-  for (int k = l; k < N; k += 64) {
+  for (int k = l; k < N; k += G) {
     const int kl = v.a.pt_link[pt0 + k];  // link index local to the morphology
     if (!near[kl]) continue;
     const float4 p = v.a.pts[pt0 + k];
@@ -471,7 +489,7 @@ __global__ __launch_bounds__(64) void torque_kernel(WorldView v, const float* s,
     }
   }
   __syncthreads();
-  const float nlow = wave_sum(own ? (float)low_n[l] : 0.f);
+  const float nlow = seg_sum<G>(own ? (float)low_n[l] : 0.f);
   const float f_up = nlow > 0.f ? -M * v.a.gz / nlow : 0.f;
 
   // this link's load sums: weight m_l g at its CoG, plus f_up on each band point
@@ -516,8 +534,8 @@ __global__ __launch_bounds__(64) void torque_kernel(WorldView v, const float* s,
     const float m2 = St[5] - (ao[0] * St[1] - ao[1] * St[0]);
     tau = fabsf(aw[0] * m0 + aw[1] * m1 + aw[2] * m2);
   }
-  tau = wave_sum(tau);
-  if (l == 0) {
+  tau = seg_sum<G>(tau);
+  if (l == 0 && live) {
     const float mean = L > 1 ? tau / (float)(L - 1) : 0.f;
     acc[i] = accumulate ? acc[i] + mean : mean;
   }
@@ -629,8 +647,12 @@ npx_status npx_sur_torque(npx_world* w, const float* s, int64_t lds, float* acc,
   if (s && lds < state_width(v.a.j_max)) return fail(NPX_EINVAL, "state stride too small");
   if (v.l_max > 64) return fail(NPX_EUNSUPPORTED, "more than 64 links");
   hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL(torque_kernel, dim3((unsigned)v.a.n_inst), dim3(64), 0, st, v, s, lds, acc,
-                     accumulate ? 1 : 0);
+  if (v.l_max <= 32)
+    hipLaunchKernelGGL(torque_kernel<32>, dim3((unsigned)((v.a.n_inst + 1) / 2)), dim3(64), 0, st,
+                       v, s, lds, acc, accumulate);
+  else
+    hipLaunchKernelGGL(torque_kernel<64>, dim3((unsigned)v.a.n_inst), dim3(64), 0, st, v, s, lds,
+                       acc, accumulate);
   HIP_TRY(hipGetLastError());
   npx::note_stream(w, st);
   return NPX_OK;

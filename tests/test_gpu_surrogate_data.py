@@ -204,3 +204,38 @@ def test_advance_needs_joints_every_frame():
     with pytest.raises(N.NpxError):
         gw.sur_advance(s, s, 0)
     gw.close()
+
+
+def test_torque_uneven_robots_with_more_than_32_links():
+    """Random legged robots, some with 33 links: the proxy runs one robot per
+    64-lane wave (at most 32 links: two per wave); against the reference."""
+    import torch
+    from paper_2411_05799_amd import native as N
+    from paper_2411_05799_amd import workloads as W
+    w = W.config3(n_inst=96, n_steps=200)
+    l_max = max(m.n_links for m in w.morphs)
+    assert l_max > 32, l_max
+    say(f"case: torque proxy, 96 uneven robots, up to {l_max} links")
+    gw = N.World(w)
+    gw.step_n(200)
+    sw, _ = gw.sur_widths()
+    rows = torch.zeros((96, sw), device="cuda")
+    gw.rows(rows)
+    acc = torch.zeros(96, device="cuda")
+    gw.sur_torque(acc, s=rows)
+    torch.cuda.synchronize()
+    flags = gw.read_state(N.F_FLAGS)
+    gw.close()
+    a = acc.cpu().numpy().astype(np.float64)
+    so = SO.SurrogateOracle(w)
+    r = rows.cpu().numpy().astype(np.float64)
+    compared = 0
+    for i in range(96):
+        if flags[i] != 0:
+            continue
+        tau, ambiguous = so.torque(i, r[i])
+        if ambiguous:
+            continue
+        assert abs(a[i] - tau) <= 1e-4 * max(1.0, tau), (i, a[i], tau)
+        compared += 1
+    assert compared >= 0.6 * 96, compared
