@@ -239,3 +239,45 @@ def test_torque_uneven_robots_with_more_than_32_links():
         assert abs(a[i] - tau) <= 1e-4 * max(1.0, tau), (i, a[i], tau)
         compared += 1
     assert compared >= 0.6 * 96, compared
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp32"])
+def test_native_rollout_fused_network_and_fp32(precision):
+    """256 robots (whole 128-row blocks): the BF16 network runs as one fused
+    kernel inside the rollout and inside npx_sur_forward alike, the FP32 one
+    layer by layer with float inputs; the native rollout equals the composed
+    calls bit for bit in both."""
+    import torch
+    from paper_2411_05799_amd import native as N
+    from paper_2411_05799_amd import workloads as W
+    say(f"case: native rollout vs composed calls, 256 robots, {precision}")
+    I = 256
+    w = W.config2(n_inst=I, n_steps=100)
+    gw = N.World(w)
+    gw.step_n(100)
+    sw, fw = gw.sur_widths()
+    rows = torch.zeros((I, sw), device="cuda")
+    gw.rows(rows)
+    prec = N.SUR_BF16 if precision == "bf16" else N.SUR_FP32
+    net = N.Surrogate(fw, 384, 2, sw, max_batch=I, precision=prec, training=False, seed=7)
+    rng = np.random.default_rng(1)
+    net.set_norm(rng.normal(0, 0.1, fw), rng.uniform(0.5, 2, fw), np.zeros(sw),
+                 np.full(sw, 1e-3))
+    s1, s2 = rows.clone(), rows.clone()
+    x = torch.zeros((I, fw), device="cuda")
+    y = torch.zeros((I, sw), device="cuda")
+    t1 = torch.zeros(I, device="cuda")
+    t2 = torch.zeros(I, device="cuda")
+    gw.sur_rollout(net, s1, 100, 4, x, y, t1)
+    for c in range(4):
+        f = 100 + 10 * c
+        gw.sur_features(x, s=s2, frame=f)
+        net.forward(x, y)
+        gw.sur_advance(s2, y, f)
+        gw.sur_torque(t2, s=s2, accumulate=True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(s1.cpu().numpy(), s2.cpu().numpy())
+    np.testing.assert_array_equal(t1.cpu().numpy(), t2.cpu().numpy())
+    assert not torch.equal(s1, rows) and torch.isfinite(s1).all()
+    net.close()
+    gw.close()
