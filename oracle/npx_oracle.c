@@ -241,25 +241,38 @@ double orc_height(const orc_params* p, double x, double y) {
  * Reading: with one pair, or pairs with no spread (sum |src - mean|^2 <= n eps^2),
  * the rotation is not determined and only the displacement is fitted. */
 int orc_lsq(int n, const double* src, const double* dst, double eps, double* a) {
+  return orc_lsq_w(n, src, dst, NULL, eps, a);
+}
+
+/* Weighted reading of the closing remark of Sec. III-C: pair i's two
+ * residuals enter the sum of squares times its weight w_i, so every sum of
+ * eqs. (4)-(6) gains the factor w_i; the spread test and the
+ * displacement-only fallback use the weighted spread and the total weight W
+ * in place of n. */
+int orc_lsq_w(int n, const double* src, const double* dst, const double* wt, double eps,
+              double* a) {
   a[0] = a[1] = a[2] = 0.0;
   if (n <= 0) return 0;
   double A[9] = {0}, b[3] = {0};
-  double sx = 0, sy = 0, s2 = 0;
+  double W = 0, sx = 0, sy = 0, s2 = 0;
   for (int i = 0; i < n; ++i) {
+    double wi = wt ? wt[i] : 1.0;
     double x = src[2 * i], y = src[2 * i + 1];
     double dx = dst[2 * i] - x, dy = dst[2 * i + 1] - y;
     double r1[3] = {1.0, 0.0, -y}; /* d/da of the x-residual */
     double r2[3] = {0.0, 1.0, x};  /* d/da of the y-residual */
     for (int u = 0; u < 3; ++u) {
-      for (int v = 0; v < 3; ++v) A[3 * u + v] += r1[u] * r1[v] + r2[u] * r2[v];
-      b[u] += r1[u] * dx + r2[u] * dy;
+      for (int v = 0; v < 3; ++v) A[3 * u + v] += wi * (r1[u] * r1[v] + r2[u] * r2[v]);
+      b[u] += wi * (r1[u] * dx + r2[u] * dy);
     }
-    sx += x; sy += y; s2 += x * x + y * y;
+    W += wi;
+    sx += wi * x; sy += wi * y; s2 += wi * (x * x + y * y);
   }
-  double spread = s2 - (sx * sx + sy * sy) / n;
-  if (n >= 2 && spread > n * eps * eps && solve3(A, b, a)) return 3;
-  a[0] = b[0] / n;
-  a[1] = b[1] / n;
+  if (!(W > 0.0)) return 0;
+  double spread = s2 - (sx * sx + sy * sy) / W;
+  if (n >= 2 && spread > W * eps * eps && solve3(A, b, a)) return 3;
+  a[0] = b[0] / W;
+  a[1] = b[1] / W;
   a[2] = 0.0;
   return 2;
 }
@@ -269,7 +282,7 @@ int orc_lsq(int n, const double* src, const double* dst, double eps, double* a) 
 /* ------------------------------------------------------------------------- */
 
 typedef struct {
-  double *y, *r, *P, *Ps, *src, *dst;
+  double *y, *r, *P, *Ps, *src, *dst, *f, *wt;
   int* kap;
 } work_t;
 
@@ -281,11 +294,14 @@ static int work_alloc(work_t* w, int N) {
   w->src = (double*)malloc(sizeof(double) * 2 * N);
   w->dst = (double*)malloc(sizeof(double) * 2 * N);
   w->kap = (int*)malloc(sizeof(int) * N);
+  w->f = (double*)malloc(sizeof(double) * N);
+  w->wt = (double*)malloc(sizeof(double) * N);
   return w->y && w->r && w->P && w->Ps && w->src && w->dst && w->kap;
 }
 
 static void work_free(work_t* w) {
   free(w->y); free(w->r); free(w->P); free(w->Ps); free(w->src); free(w->dst); free(w->kap);
+  free(w->f); free(w->wt);
 }
 
 static int morph_ok(const orc_morph* m) {
@@ -362,6 +378,7 @@ static int step_ws(const orc_morph* m, const orc_params* p, const float* ctrl, d
   /* S2: per-point normal force along +z, summed to force and torque about c */
   double F = 0.0, tau[3] = {0, 0, 0};
   for (int k = 0; k < N; ++k) {
+    w->f[k] = 0.0;
     if (!w->kap[k]) continue;
     double arm[3] = {w->P[3 * k] - c[0], w->P[3 * k + 1] - c[1], w->P[3 * k + 2] - c[2]};
     double wxa[3];
@@ -370,6 +387,7 @@ static int step_ws(const orc_morph* m, const orc_params* p, const float* ctrl, d
     double d = orc_height(p, w->P[3 * k], w->P[3 * k + 1]) - w->P[3 * k + 2];
     double f = p->k_n * d * (1.0 - p->zeta * uz);
     if (f < 0.0) f = 0.0;
+    w->f[k] = f;
     double fz[3] = {0.0, 0.0, f}, tk[3];
     cross3(arm, fz, tk);
     F += f;
@@ -425,24 +443,29 @@ static int step_ws(const orc_morph* m, const orc_params* p, const float* ctrl, d
       w->src[2 * nS + 1] = w->P[3 * k + 1] - c1[1];
       w->dst[2 * nS] = w->Ps[3 * k] - c1[0];
       w->dst[2 * nS + 1] = w->Ps[3 * k + 1] - c1[1];
+      w->wt[nS] = w->f[k];  /* the force pressing the point at P^n */
       ++nS;
     }
   }
 
   /* S6: least-squares displacement and rotation of the contact points */
   double a[3];
-  orc_lsq(nS, w->src, w->dst, p->eps, a);
+  const double* wt = p->weighted ? w->wt : NULL;
+  int fit = orc_lsq_w(nS, w->src, w->dst, wt, p->eps, a);
 
-  /* S7: cap by the maximum static friction mu F_N */
+  /* S7: cap by the maximum static friction mu F_N (the mean slip is weighted
+   * like the fit) */
   double lam = 0.0, Ff = 0.0;
-  if (nS > 0) {
-    double sbx = 0.0, sby = 0.0;
+  if (fit > 0) {
+    double sbx = 0.0, sby = 0.0, W = 0.0;
     for (int i = 0; i < nS; ++i) {
-      sbx += w->dst[2 * i] - w->src[2 * i];
-      sby += w->dst[2 * i + 1] - w->src[2 * i + 1];
+      double wi = wt ? wt[i] : 1.0;
+      sbx += wi * (w->dst[2 * i] - w->src[2 * i]);
+      sby += wi * (w->dst[2 * i + 1] - w->src[2 * i + 1]);
+      W += wi;
     }
-    sbx /= nS;
-    sby /= nS;
+    sbx /= W;
+    sby /= W;
     Ff = M * sqrt(sbx * sbx + sby * sby) / (dt * dt);
     if (isinf(p->mu) || Ff <= p->mu * F) lam = 1.0;
     else lam = p->mu * F / Ff;
@@ -472,7 +495,7 @@ static int step_ws(const orc_morph* m, const orc_params* p, const float* ctrl, d
   /* S9: telemetry and health */
   st[ORC_TELE + 0] += torso_height(m, p, st, g_b);
   st[ORC_TELE + 1] += n_contact;
-  st[ORC_TELE + 2] += (nS > 0 && lam < 1.0) ? 1.0 : 0.0;
+  st[ORC_TELE + 2] += (fit > 0 && lam < 1.0) ? 1.0 : 0.0;
   int bad = 0;
   for (int i = 0; i < 13; ++i)
     if (!isfinite(st[i])) bad |= ORC_FLAG_NONFINITE;

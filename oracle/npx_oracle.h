@@ -42,6 +42,8 @@ typedef struct {
   double k_n;     /* normal stiffness per point */
   double zeta;    /* Hunt-Crossley damping */
   double eps;     /* LSQ spread threshold */
+  int weighted;   /* 1: each point's terms in the friction fit weighted by its
+                     normal force (Sec. III-C, closing remark) */
   int hf_nx, hf_ny;
   double hf_s, hf_x0, hf_y0;
   const float* hf; /* [hf_ny][hf_nx] */
@@ -91,6 +93,11 @@ double orc_height(const orc_params* p, double x, double y);
  * src [n][2] at t, dst [n][2] at t+1. Writes a1, a2, a3. Returns the number of
  * unknowns solved (0 none, 2 translation only, 3 full). */
 int orc_lsq(int n, const double* src, const double* dst, double eps, double* a);
+/* The same fit with pair i's residuals weighted by wt[i] >= 0 (wt == NULL:
+ * all 1). Returns 3 (rotation fitted), 2 (displacement only) or 0 (no pair,
+ * or all weights zero: no motion). */
+int orc_lsq_w(int n, const double* src, const double* dst, const double* wt, double eps,
+              double* a);
 
 /* State from a start pose [7] = torso origin xyz + quaternion, at rest. */
 int orc_init_state(const orc_morph* m, const orc_params* p, const float* ctrl,

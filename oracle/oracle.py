@@ -41,7 +41,7 @@ class _Morph(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("dt", C.c_double), ("K", C.c_int), ("g", C.c_double * 3), ("mu", C.c_double),
                 ("k_n", C.c_double), ("zeta", C.c_double), ("eps", C.c_double),
-                ("hf_nx", C.c_int), ("hf_ny", C.c_int), ("hf_s", C.c_double),
+                ("weighted", C.c_int), ("hf_nx", C.c_int), ("hf_ny", C.c_int), ("hf_s", C.c_double),
                 ("hf_x0", C.c_double), ("hf_y0", C.c_double), ("hf", C.POINTER(C.c_float))]
 
 
@@ -62,6 +62,7 @@ def lib():
         L.orc_height.argtypes = [C.POINTER(_Params), C.c_double, C.c_double]
         L.orc_height.restype = C.c_double
         L.orc_lsq.argtypes = [C.c_int, dp, dp, C.c_double, dp]
+        L.orc_lsq_w.argtypes = [C.c_int, dp, dp, dp, C.c_double, dp]
         L.orc_init_state.argtypes = [C.POINTER(_Morph), C.POINTER(_Params), fp, fp, dp]
         L.orc_points.argtypes = [C.POINTER(_Morph), dp, dp]
         L.orc_step.argtypes = [C.POINTER(_Morph), C.POINTER(_Params), fp, dp, dp]
@@ -112,7 +113,8 @@ class OracleParams:
         self.H = np.ascontiguousarray(hf.H, dtype=np.float32)
         g = (C.c_double * 3)(*[float(x) for x in params.g])
         self.c = _Params(float(params.dt), int(params.K), g, float(params.mu), float(params.k_n),
-                         float(params.zeta), float(params.eps), int(hf.nx), int(hf.ny),
+                         float(params.zeta), float(params.eps),
+                         int(getattr(params, "friction_weighting", False)), int(hf.nx), int(hf.ny),
                          float(hf.s), float(hf.x0), float(hf.y0), _fptr(self.H))
 
     def cell(self, x, y):
@@ -124,11 +126,19 @@ class OracleParams:
         return lib().orc_height(C.byref(self.c), float(x), float(y))
 
 
-def lsq(src, dst, eps=1e-4):
+def lsq(src, dst, eps=1e-4, weights=None):
+    """Friction fit (eqs. 4-6) of the pairs src -> dst; weights: the
+    per-pair weights of the force-weighted variant (None: unweighted)."""
     src = np.ascontiguousarray(src, dtype=np.float64).reshape(-1, 2)
     dst = np.ascontiguousarray(dst, dtype=np.float64).reshape(-1, 2)
     a = np.zeros(3)
-    k = lib().orc_lsq(int(src.shape[0]), _dptr(src), _dptr(dst), float(eps), _dptr(a))
+    if weights is None:
+        k = lib().orc_lsq(int(src.shape[0]), _dptr(src), _dptr(dst), float(eps), _dptr(a))
+    else:
+        w = np.ascontiguousarray(weights, dtype=np.float64).reshape(-1)
+        assert w.shape[0] == src.shape[0]
+        k = lib().orc_lsq_w(int(src.shape[0]), _dptr(src), _dptr(dst), _dptr(w), float(eps),
+                            _dptr(a))
     return a, k
 
 

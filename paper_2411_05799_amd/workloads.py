@@ -80,6 +80,7 @@ class Params:
     k_n: float = 5000.0         # normal penalty stiffness per point, N/m
     zeta: float = 5.0           # Hunt-Crossley damping, s/m
     eps: float = 1.0e-4         # LSQ spread threshold, m
+    friction_weighting: bool = False  # friction fit weighted by each point's normal force
 
 
 @dataclass

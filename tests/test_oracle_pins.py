@@ -513,3 +513,100 @@ def test_friction_set_needs_contact_at_both_times():
     assert now == 2 and d[O.D_NC] == 2
     assert d[O.D_NS] == 2
     assert (Ps[:, 2] < 0).sum() == 4      # all four bottom corners touch after the step
+
+
+# ----------------------------------------------------------------------------
+# force-weighted friction fit (closing remark of Sec. III-C)
+# ----------------------------------------------------------------------------
+
+def weighted_lstsq_ref(src, dst, w):
+    """Each pair's two residual rows scaled by sqrt(w): the weighted least squares."""
+    n = len(src)
+    A = np.zeros((2 * n, 3))
+    b = np.zeros(2 * n)
+    A[0::2, 0] = 1.0
+    A[0::2, 2] = -src[:, 1]
+    A[1::2, 1] = 1.0
+    A[1::2, 2] = src[:, 0]
+    b[0::2] = dst[:, 0] - src[:, 0]
+    b[1::2] = dst[:, 1] - src[:, 1]
+    s = np.sqrt(np.repeat(w, 2))
+    return np.linalg.lstsq(A * s[:, None], b * s, rcond=None)[0]
+
+
+@pytest.mark.parametrize("n", [2, 3, 7, 40])
+def test_weighted_lsq_equals_weighted_lstsq(n):
+    rng = np.random.default_rng(100 + n)
+    src = rng.normal(scale=0.2, size=(n, 2))
+    dst = src + rng.normal(scale=0.01, size=(n, 2))
+    w = rng.uniform(0.1, 5.0, size=n)
+    a, k = O.lsq(src, dst, weights=w)
+    assert k == 3
+    np.testing.assert_allclose(a, weighted_lstsq_ref(src, dst, w), rtol=0, atol=1e-12)
+
+
+def test_weighted_lsq_special_cases():
+    rng = np.random.default_rng(7)
+    src = rng.normal(scale=0.3, size=(8, 2))
+    dst = src + rng.normal(scale=0.01, size=src.shape)
+    # equal weights: the unweighted fit, whatever their size
+    a0, _ = O.lsq(src, dst)
+    a1, _ = O.lsq(src, dst, weights=np.full(8, 3.7))
+    np.testing.assert_allclose(a1, a0, atol=1e-13)
+    # a zero weight drops its pair
+    w = rng.uniform(0.5, 2.0, size=8)
+    w[3] = 0.0
+    keep = np.arange(8) != 3
+    a2, _ = O.lsq(src, dst, weights=w)
+    a3, _ = O.lsq(src[keep], dst[keep], weights=w[keep])
+    np.testing.assert_allclose(a2, a3, atol=1e-13)
+    # data that the linear model fits exactly is fitted exactly for any weights
+    t = np.array([0.01, -0.02])
+    s3 = 0.05
+    exact = src + np.stack([-s3 * src[:, 1], s3 * src[:, 0]], 1) + t
+    a4, k = O.lsq(src, exact, weights=rng.uniform(0.1, 9.0, size=8))
+    assert k == 3
+    np.testing.assert_allclose(a4, [t[0], t[1], s3], atol=1e-13)
+    # one weighted pair among zeros: no spread, its own slip
+    w1 = np.zeros(8)
+    w1[5] = 2.0
+    a5, k = O.lsq(src, dst, weights=w1)
+    assert k == 2 and a5[2] == 0.0
+    np.testing.assert_allclose(a5[:2], dst[5] - src[5], atol=1e-15)
+    # all weights zero: no motion
+    a6, k = O.lsq(src, dst, weights=np.zeros(8))
+    assert k == 0 and not a6.any()
+
+
+def test_force_weighting_in_the_step():
+    """Slips that come from one rigid trial motion (a box spinning and
+    sliding, even tilted so that its corners press unequally) are fitted
+    exactly by either sum, so the weighted step equals the unweighted one;
+    joint motion makes the slips non-rigid and the weighting changes the
+    fit (a hexapod walking on flat ground)."""
+    for tilt in (0.0, 0.02):
+        out = []
+        for weighted in (False, True):
+            p = W.Params(mu=1.0, friction_weighting=weighted)
+            d_eq = G0 / (4 * p.k_n)
+            q = [math.cos(tilt / 2), math.sin(tilt / 2), 0.0, 0.0]
+            ow = scene(box_morph(), [0.0, 0.0, 0.0] + q, params=p)
+            st = ow.init_state(0)
+            st[O.C_:O.C_ + 3] = [0.0, 0.0, HALF_Z - d_eq]
+            st[O.W_ + 2] = 2.0
+            st[O.V_] = 0.05
+            d = ow.step(0, st, diag=True)
+            out.append((d[O.D_A:O.D_A + 3].copy(), d[O.D_NS]))
+        (a_u, n_u), (a_w, n_w) = out
+        assert n_u == n_w >= 2
+        np.testing.assert_allclose(a_w, a_u, rtol=0, atol=1e-14)
+    ends = []
+    for weighted in (False, True):
+        w = W.config1(n_steps=400)
+        w.params.friction_weighting = weighted
+        ow = O.OracleWorld(w)
+        st = ow.init_state(0)
+        ow.run(0, st, 400)
+        assert st[O.FLAGS] == 0 and np.isfinite(st[:13]).all()
+        ends.append(st[:13].copy())
+    assert np.abs(ends[1][:2] - ends[0][:2]).max() > 1e-6
