@@ -146,6 +146,11 @@ typedef struct {
   const float* ctrl;               /* host [n_instances][J_max][3] sinusoid controller
                                       (see npx_set_controller), J_max = max(1, max
                                       n_links - 1); NULL = all zero */
+  int32_t friction_weighting;      /* 0: the friction fit of eqs. (4)-(6) as printed;
+                                      1: every point's terms weighted by the normal
+                                      force pressing it at the frame's start (the
+                                      refinement closing Sec. III-C); other values
+                                      are rejected */
 } npx_world_desc;
 
 typedef struct npx_world npx_world;

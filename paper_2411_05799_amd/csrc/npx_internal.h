@@ -48,6 +48,7 @@ struct StepArgs {
   float mu;
   int mu_inf;
   float kn, zeta, eps;
+  int fric_w;             // friction fit weighted by each point's normal force
   const float* hf;
   int hf_nx, hf_ny;
   float hf_s, hf_x0, hf_y0;

@@ -567,7 +567,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
       }
       __builtin_amdgcn_wave_barrier();
       const float dcx = c1[0] - c[0], dcy = c1[1] - c[1];
-      float mn = 0.f, Sx = 0.f, Sy = 0.f, S2 = 0.f, Dx = 0.f, Dy = 0.f, Cd = 0.f;
+      float mn = 0.f, Sx = 0.f, Sy = 0.f, S2 = 0.f, Dx = 0.f, Dy = 0.f, Cd = 0.f, Wt = 0.f;
       for (int e = sl; e < n_cand; e += G) {
         const int kk = pt_off + cand[e];
         const float4 rho = a.pts[kk];
@@ -599,15 +599,32 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
           const float dy = (Eb[3] * Ux + Eb[4] * Uy + Eb[5] * Uz) +
                            (R1[3] * drx + R1[4] * dry + R1[5] * drz) + dcy;
           mn += 1.f;
-          Sx += sx;
-          Sy += sy;
-          S2 += sx * sx + sy * sy;
-          Dx += dx;
-          Dy += dy;
-          Cd += sx * dy - sy * dx;
+          if (a.fric_w) {
+            // weighted by the force pressing the point at P^n, the normal
+            // force of detection recomputed from the point before this
+            // frame's joint update (the position P^n = c + U)
+            const float dn = hf_at(a, c[0] + Ux, c[1] + Uy) - (c[2] + Uz);
+            const float vz = v[2] + (w[0] * Uy - w[1] * Ux);
+            const float wk = dn > 0.f ? fmaxf(a.kn * dn * (1.f - a.zeta * vz), 0.f) : 0.f;
+            Wt += wk;
+            Sx += wk * sx;
+            Sy += wk * sy;
+            S2 += wk * (sx * sx + sy * sy);
+            Dx += wk * dx;
+            Dy += wk * dy;
+            Cd += wk * (sx * dy - sy * dx);
+          } else {
+            Sx += sx;
+            Sy += sy;
+            S2 += sx * sx + sy * sy;
+            Dx += dx;
+            Dy += dy;
+            Cd += sx * dy - sy * dx;
+          }
         }
       }
       mn = seg_sum<G>(mn);
+      const float Wn = a.fric_w ? seg_sum<G>(Wt) : mn;  // total weight (count if unweighted)
       Sx = seg_sum<G>(Sx);
       Sy = seg_sum<G>(Sy);
       S2 = seg_sum<G>(S2);
@@ -617,12 +634,13 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
 
       // S6 closed form of eqs. (4)-(6) and S7 static-friction cap. In these
       // moments a3 = [sum xi x delta - (Sx Dy - Sy Dx)/n] / (sum |xi|^2 - |S|^2/n),
-      // a = (D + a3 J^T S)/n, the mean slip is D/n.
+      // a = (D + a3 J^T S)/n, the mean slip is D/n. With the force weighting
+      // every sum carries the point's weight and n becomes the total weight.
       float a1 = 0.f, a2 = 0.f, a3 = 0.f, lam = 0.f;
-      if (mn > 0.f) {
-        const float inv_n = rcp(mn);
+      if (mn > 0.f && Wn > 0.f) {
+        const float inv_n = rcp(Wn);
         const float D = S2 - (Sx * Sx + Sy * Sy) * inv_n;
-        if (mn >= 2.f && D > mn * a.eps * a.eps) a3 = (Cd - (Sx * Dy - Sy * Dx) * inv_n) * rcp(D);
+        if (mn >= 2.f && D > Wn * a.eps * a.eps) a3 = (Cd - (Sx * Dy - Sy * Dx) * inv_n) * rcp(D);
         a1 = (Dx + Sy * a3) * inv_n;
         a2 = (Dy - Sx * a3) * inv_n;
         const float sbx = Dx * inv_n, sby = Dy * inv_n;
@@ -683,7 +701,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
         for (int i = 0; i < 4; ++i) Q[i] = Q2[i];
         tele[0] += (double)th;
         tele[1] += (double)nc;
-        tele[2] += (mn > 0.f && lam < 1.f) ? 1.0 : 0.0;
+        tele[2] += (mn > 0.f && Wn > 0.f && lam < 1.f) ? 1.0 : 0.0;
         fl = bad;
         n += 1;
       }

@@ -264,6 +264,8 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
     return fail(NPX_EINVAL, "bad height map");
   if (!(d->mu >= 0) || !(d->k_n >= 0) || !(d->zeta >= 0) || !(d->eps_lsq >= 0))
     return fail(NPX_EINVAL, "mu, k_n, zeta, eps must be >= 0");
+  if (d->friction_weighting != 0 && d->friction_weighting != 1)
+    return fail(NPX_EINVAL, "friction_weighting must be 0 or 1");
   for (int i = 0; i < d->n_morphs; ++i) {
     npx_status s = check_tables(d->morphs[i], i);
     if (s != NPX_OK) return s;
@@ -502,6 +504,7 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   a.kn = (float)d->k_n;
   a.zeta = (float)d->zeta;
   a.eps = (float)d->eps_lsq;
+  a.fric_w = d->friction_weighting;
   a.hf = w->hf;
   a.hf_nx = d->hf_nx;
   a.hf_ny = d->hf_ny;

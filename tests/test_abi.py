@@ -56,6 +56,10 @@ def test_bad_tables_rejected_before_device_use():
                     inst_morph=np.array([5], np.int32), ctrl=w.ctrl, pose=w.pose)
     with pytest.raises(N.NpxError, match="instance_morph"):
         N.World(w4)
+    w5 = W.Workload(params=W.Params(friction_weighting=2), hf=w.hf, morphs=w.morphs,
+                    inst_morph=w.inst_morph, ctrl=w.ctrl, pose=w.pose)
+    with pytest.raises(N.NpxError, match="friction_weighting"):
+        N.World(w5)
 
 
 def test_missing_library_fails_loudly(monkeypatch):

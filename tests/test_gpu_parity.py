@@ -353,3 +353,23 @@ def test_robot_built_with_construction_api():
     with N.World(w) as gw:
         res = run_windows(ow, gw, [0], starts=[0, 400], every=40)
     assert_windows(res, "construction-API quadruped", ow)
+
+
+def test_force_weighted_friction_windows():
+    """The friction fit weighted by each point's normal force (the refinement
+    closing Sec. III-C): 32 hexapods on the terrain, 3 windows of 200 frames
+    each against the oracle's weighted fit, and the weighting changes the
+    trajectories."""
+    say("case: force-weighted friction, 32 hexapods x 3 windows")
+    w = W.hexapod_batch(32, seed=31, hf=W.octave_terrain(5), n_steps=600)
+    w.params.friction_weighting = True
+    ow = O.OracleWorld(w)
+    with N.World(w) as gw:
+        res = run_windows(ow, gw, list(range(32)), starts=[0, 200, 400], every=40)
+    assert_windows(res, "weighted", ow)
+    w0 = W.hexapod_batch(32, seed=31, hf=W.octave_terrain(5), n_steps=600)
+    with N.World(w) as gw_w, N.World(w0) as gw_u:
+        gw_w.step_n(600)
+        gw_u.step_n(600)
+        d = np.abs(gw_w.read_state(N.F_COG)[:2] - gw_u.read_state(N.F_COG)[:2]).max()
+    assert d > 1e-4, d
