@@ -224,7 +224,33 @@ void orc_cell(const orc_params* p, double x, double y, int* i, int* j) {
   *j = cell_index(y, p->hf_y0, p->hf_s, p->hf_ny);
 }
 
+/* One axis of the bilinear reading: the lower centre index and the fraction
+ * towards the next, the coordinate held inside the outer centres. */
+static void centre_axis(double x, double x0, double s, int n, int* i0, double* f) {
+  double u = (x - x0) * s - 0.5;
+  if (!(u > 0.0)) u = 0.0;
+  if (u > (double)(n - 1)) u = (double)(n - 1);
+  int i = (int)floor(u);
+  if (i > n - 2) i = n - 2;
+  if (i < 0) i = 0;
+  *i0 = i;
+  *f = n >= 2 ? u - (double)i : 0.0;
+}
+
 double orc_height(const orc_params* p, double x, double y) {
+  if (p->hf_bilinear) {
+    /* reading of the "smoother ground" option: entry (i, j) is the height at
+     * the centre of cell (i, j); bilinear between the four centres around */
+    int i0, j0;
+    double fu, fw;
+    centre_axis(x, p->hf_x0, p->hf_s, p->hf_nx, &i0, &fu);
+    centre_axis(y, p->hf_y0, p->hf_s, p->hf_ny, &j0, &fw);
+    const int i1 = p->hf_nx >= 2 ? i0 + 1 : i0, j1 = p->hf_ny >= 2 ? j0 + 1 : j0;
+    const double h00 = p->hf[(long)j0 * p->hf_nx + i0], h10 = p->hf[(long)j0 * p->hf_nx + i1];
+    const double h01 = p->hf[(long)j1 * p->hf_nx + i0], h11 = p->hf[(long)j1 * p->hf_nx + i1];
+    return (1.0 - fu) * (1.0 - fw) * h00 + fu * (1.0 - fw) * h10 + (1.0 - fu) * fw * h01 +
+           fu * fw * h11;
+  }
   int i, j;
   orc_cell(p, x, y, &i, &j);
   return (double)p->hf[(long)j * p->hf_nx + i];

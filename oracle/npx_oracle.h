@@ -44,6 +44,8 @@ typedef struct {
   double eps;     /* LSQ spread threshold */
   int weighted;   /* 1: each point's terms in the friction fit weighted by its
                      normal force (Sec. III-C, closing remark) */
+  int hf_bilinear; /* 1: the table's entries are heights at cell centres,
+                      interpolated bilinearly (0: the paper's look-up table) */
   int hf_nx, hf_ny;
   double hf_s, hf_x0, hf_y0;
   const float* hf; /* [hf_ny][hf_nx] */

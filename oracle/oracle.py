@@ -41,7 +41,7 @@ class _Morph(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("dt", C.c_double), ("K", C.c_int), ("g", C.c_double * 3), ("mu", C.c_double),
                 ("k_n", C.c_double), ("zeta", C.c_double), ("eps", C.c_double),
-                ("weighted", C.c_int), ("hf_nx", C.c_int), ("hf_ny", C.c_int), ("hf_s", C.c_double),
+                ("weighted", C.c_int), ("hf_bilinear", C.c_int), ("hf_nx", C.c_int), ("hf_ny", C.c_int), ("hf_s", C.c_double),
                 ("hf_x0", C.c_double), ("hf_y0", C.c_double), ("hf", C.POINTER(C.c_float))]
 
 
@@ -114,7 +114,8 @@ class OracleParams:
         g = (C.c_double * 3)(*[float(x) for x in params.g])
         self.c = _Params(float(params.dt), int(params.K), g, float(params.mu), float(params.k_n),
                          float(params.zeta), float(params.eps),
-                         int(getattr(params, "friction_weighting", False)), int(hf.nx), int(hf.ny),
+                         int(getattr(params, "friction_weighting", False)),
+                         int(getattr(params, "hf_bilinear", False)), int(hf.nx), int(hf.ny),
                          float(hf.s), float(hf.x0), float(hf.y0), _fptr(self.H))
 
     def cell(self, x, y):

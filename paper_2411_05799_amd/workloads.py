@@ -81,6 +81,7 @@ class Params:
     zeta: float = 5.0           # Hunt-Crossley damping, s/m
     eps: float = 1.0e-4         # LSQ spread threshold, m
     friction_weighting: bool = False  # friction fit weighted by each point's normal force
+    hf_bilinear: bool = False   # height map read bilinearly between cell centres
 
 
 @dataclass

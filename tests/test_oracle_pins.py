@@ -610,3 +610,78 @@ def test_force_weighting_in_the_step():
         assert st[O.FLAGS] == 0 and np.isfinite(st[:13]).all()
         ends.append(st[:13].copy())
     assert np.abs(ends[1][:2] - ends[0][:2]).max() > 1e-6
+
+
+# ----------------------------------------------------------------------------
+# bilinear height-map option (a smoother ground than the look-up table)
+# ----------------------------------------------------------------------------
+
+def _table(H, s=50.0, x0=-1.0, y0=-2.0):
+    ny, nx = H.shape
+    return W.Heightfield(nx=nx, ny=ny, s=s, x0=x0, y0=y0, H=H.astype(np.float32))
+
+
+def test_bilinear_reproduces_planes_and_centres():
+    """Entries sampled from a plane at the cell centres give that plane exactly
+    everywhere between the outer centres; at a centre the entry itself; the
+    table look-up of the same map differs inside a cell."""
+    nx, ny, s, x0, y0 = 7, 5, 50.0, -1.0, -2.0
+    xc = x0 + (np.arange(nx) + 0.5) / s
+    yc = y0 + (np.arange(ny) + 0.5) / s
+    H = (0.25 * xc[None, :] - 0.5 * yc[:, None] + 0.125).astype(np.float32)
+    hf = _table(H, s, x0, y0)
+    bil = O.OracleParams(W.Params(hf_bilinear=True), hf)
+    tab = O.OracleParams(W.Params(), hf)
+    rng = np.random.default_rng(3)
+    for x, y in zip(rng.uniform(xc[0], xc[-1], 50), rng.uniform(yc[0], yc[-1], 50)):
+        # the plane through the stored (float32) entries
+        i = min(int((x - x0) * s - 0.5), nx - 2)
+        j = min(int((y - y0) * s - 0.5), ny - 2)
+        fu, fw = (x - x0) * s - 0.5 - i, (y - y0) * s - 0.5 - j
+        h = ((1 - fu) * (1 - fw) * H[j, i] + fu * (1 - fw) * H[j, i + 1] +
+             (1 - fu) * fw * H[j + 1, i] + fu * fw * H[j + 1, i + 1])
+        assert abs(bil.height(x, y) - h) < 1e-15
+        assert abs(bil.height(x, y) - (0.25 * x - 0.5 * y + 0.125)) < 1e-7
+    for i in range(nx):
+        for j in range(ny):
+            assert abs(bil.height(xc[i], yc[j]) - float(H[j, i])) < 1e-12
+    assert abs(bil.height(xc[2] + 0.3 / s, yc[1]) - tab.height(xc[2] + 0.3 / s, yc[1])) > 1e-4
+
+
+def test_bilinear_is_continuous_and_held_outside():
+    rng = np.random.default_rng(4)
+    H = rng.uniform(-0.03, 0.03, size=(6, 9)).astype(np.float32)
+    hf = _table(H)
+    bil = O.OracleParams(W.Params(hf_bilinear=True), hf)
+    # across a cell edge (a table discontinuity) and across a centre line
+    for x in (-1.0 + 3.0 / 50, -1.0 + 4.5 / 50):
+        lo, hi = bil.height(x - 1e-12, -2.0 + 2.2 / 50), bil.height(x + 1e-12, -2.0 + 2.2 / 50)
+        assert abs(lo - hi) < 1e-9
+    # beyond the outer centres the height is held
+    assert abs(bil.height(-5.0, -2.0 + 0.5 / 50) - float(H[0, 0])) < 1e-12
+    assert bil.height(5.0, 5.0) == float(H[-1, -1])
+    # a one-cell map (flat ground) reads its entry everywhere
+    flat = O.OracleParams(W.Params(hf_bilinear=True), W.flat_ground())
+    assert flat.height(0.3, -7.0) == 0.0
+
+
+def test_bilinear_box_rests_on_a_slope_it_would_step_on():
+    """A box on a table sampled from a gentle slope: with the bilinear reading
+    the ground under the corners is the plane, so the box settles without
+    falling off cell steps; rest heights follow the plane."""
+    nx = ny = 40
+    s, x0, y0 = 50.0, -0.4, -0.4
+    xc = x0 + (np.arange(nx) + 0.5) / s
+    H = np.repeat((0.02 * xc)[None, :], ny, 0).astype(np.float32)
+    hf = _table(H, s, x0, y0)
+    p = W.Params(hf_bilinear=True, mu=math.inf)
+    ow = scene(box_morph(), [0.0, 0.0, 0.05, 1, 0, 0, 0], params=p, hf=hf)
+    st = ow.init_state(0)
+    ow.run(0, st, 3000)
+    assert st[O.FLAGS] == 0
+    P = ow.points(0, st)
+    low = P[P[:, 2] < st[O.C_ + 2]]
+    # the bottom corners rest just below the plane z = 0.02 x
+    gaps = low[:, 2] - 0.02 * low[:, 0]
+    assert np.all(gaps < 0) and np.all(gaps > -2e-3), gaps
+    assert np.linalg.norm(st[O.V_:O.V_ + 3]) < 1e-3
