@@ -151,6 +151,11 @@ typedef struct {
                                       force pressing it at the frame's start (the
                                       refinement closing Sec. III-C); other values
                                       are rejected */
+  int32_t hf_bilinear;             /* 0: the height map as the paper's look-up table;
+                                      1: its entries are heights at the cell centres,
+                                      read bilinearly between the four around (held
+                                      beyond the outer centres); other values are
+                                      rejected */
 } npx_world_desc;
 
 typedef struct npx_world npx_world;

@@ -46,4 +46,19 @@ __device__ __forceinline__ float hf_lookup(const float* hf, int nx, int ny, floa
   return hf[j * nx + i];
 }
 
+// Bilinear reading of the same table (the smoother-ground option): entry (i, j)
+// is the height at the centre of cell (i, j); between the four surrounding
+// centres the height is interpolated, beyond the outer centres it is held.
+__device__ __forceinline__ float hf_bilinear(const float* hf, int nx, int ny, float x0, float y0,
+                                             float s, float x, float y) {
+  float u = fminf(fmaxf((x - x0) * s - 0.5f, 0.f), (float)(nx - 1));
+  float w = fminf(fmaxf((y - y0) * s - 0.5f, 0.f), (float)(ny - 1));
+  const int i0 = min((int)u, max(nx - 2, 0)), j0 = min((int)w, max(ny - 2, 0));
+  const int i1 = min(i0 + 1, nx - 1), j1 = min(j0 + 1, ny - 1);
+  const float fu = u - (float)i0, fw = w - (float)j0;
+  const float h0 = hf[j0 * nx + i0] + fu * (hf[j0 * nx + i1] - hf[j0 * nx + i0]);
+  const float h1 = hf[j1 * nx + i0] + fu * (hf[j1 * nx + i1] - hf[j1 * nx + i0]);
+  return h0 + fw * (h1 - h0);
+}
+
 }  // namespace npx

@@ -53,6 +53,7 @@ struct StepArgs {
   int hf_nx, hf_ny;
   float hf_s, hf_x0, hf_y0;
   float hf_max;           // highest entry of the height map
+  int hf_bilinear;        // 1: read the table bilinearly between cell centres
   float* st;              // [state_rows(j_max)][n_inst]
   int* step;              // [n_inst]
   int* flags;             // [n_inst]

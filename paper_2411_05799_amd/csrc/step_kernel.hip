@@ -86,8 +86,11 @@ __device__ __forceinline__ void group_fence(int p) {
   if ((p + 1) % kGroup == 0) __builtin_amdgcn_sched_barrier(0);
 }
 
-// Height-map look-up (Sec. III-A) of the world's table.
+// Height-map look-up (Sec. III-A) of the world's table, or (BIL, a kernel
+// built for worlds that ask for it) its bilinear reading.
+template <bool BIL>
 __device__ __forceinline__ float hf_at(const StepArgs& a, float x, float y) {
+  if constexpr (BIL) return hf_bilinear(a.hf, a.hf_nx, a.hf_ny, a.hf_x0, a.hf_y0, a.hf_s, x, y);
   return hf_lookup(a.hf, a.hf_nx, a.hf_ny, a.hf_x0, a.hf_y0, a.hf_s, x, y);
 }
 
@@ -108,7 +111,7 @@ enum Mode { kStep = 0, kPlace = 1, kPoints = 2 };
 // LDS rows of one link: [R row 0 | t0], [R row 1 | t1], [R row 2 | t2].
 using LinkT = float4[3];
 
-template <int G, int PPL, int LPL, int MODE>
+template <int G, int PPL, int LPL, int MODE, bool BIL>
 __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT, int* cand,
                                           int* touch, int* lpar, int tb, int seg, int sl) {
   constexpr int IPW = 64 / G;
@@ -581,7 +584,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
         const float uy = R1[3] * rx + R1[4] * ry + R1[5] * rz;
         const float uz = R1[6] * rx + R1[7] * ry + R1[8] * rz;
         const float Px = c1[0] + ux, Py = c1[1] + uy, Pz = c1[2] + uz;
-        if (hf_at(a, Px, Py) - Pz > 0.f) {
+        if (hf_at<BIL>(a, Px, Py) - Pz > 0.f) {
           float drx = 0.f, dry = 0.f, drz = 0.f;
           if (fk_now) {
             const float4 d0 = dT[lk][0], d1 = dT[lk][1], d2 = dT[lk][2];
@@ -603,7 +606,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
             // weighted by the force pressing the point at P^n, the normal
             // force of detection recomputed from the point before this
             // frame's joint update (the position P^n = c + U)
-            const float dn = hf_at(a, c[0] + Ux, c[1] + Uy) - (c[2] + Uz);
+            const float dn = hf_at<BIL>(a, c[0] + Ux, c[1] + Uy) - (c[2] + Uz);
             const float vz = v[2] + (w[0] * Uy - w[1] * Ux);
             const float wk = dn > 0.f ? fmaxf(a.kn * dn * (1.f - a.zeta * vz), 0.f) : 0.f;
             Wt += wk;
@@ -680,7 +683,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
       const float ox = c2[0] - (R2[0] * gb[0] + R2[1] * gb[1] + R2[2] * gb[2]);
       const float oy = c2[1] - (R2[3] * gb[0] + R2[4] * gb[1] + R2[5] * gb[2]);
       const float oz = c2[2] - (R2[6] * gb[0] + R2[7] * gb[1] + R2[8] * gb[2]);
-      const float th = oz - hf_at(a, ox, oy);
+      const float th = oz - hf_at<BIL>(a, ox, oy);
       bool fin = true;
   #pragma unroll
       for (int i = 0; i < 3; ++i) fin = fin && isfinite(c2[i]) && isfinite(v2[i]) && isfinite(w2[i]);
@@ -758,7 +761,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
         const float uy = R[3] * rx + R[4] * ry + R[5] * rz;
         const float uz = R[6] * rx + R[7] * ry + R[8] * rz;
         const float Px = c[0] + ux, Py = c[1] + uy, Pz = c[2] + uz;
-        const float d = hf_at(a, Px, Py) - Pz;
+        const float d = hf_at<BIL>(a, Px, Py) - Pz;
         if (d > 0.f) {
           hit = true;
           kap |= 1u << p;
@@ -855,7 +858,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
 template <int G, int PPL, int LPL>
 constexpr int kMinWavesPerEU = ((G == 64 && PPL <= 6) || (G == 32 && PPL <= 12 && LPL == 1)) ? 2 : 1;
 
-template <int G, int PPL, int LPL, int MODE>
+template <int G, int PPL, int LPL, int MODE, bool BIL = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWavesPerEU<G, PPL, LPL>, 8)))
 void step_kernel(const StepArgs a) {
   constexpr int IPW = 64 / G;
@@ -879,7 +882,7 @@ void step_kernel(const StepArgs a) {
       tb = blockIdx.x;
     }
     if (tb >= a.n_blocks) break;
-    run_block<G, PPL, LPL, MODE>(a, T[seg], dT[seg], cand[seg], touch[seg], lpar[seg], tb, seg,
+    run_block<G, PPL, LPL, MODE, BIL>(a, T[seg], dT[seg], cand[seg], touch[seg], lpar[seg], tb, seg,
                                  sl);
     __syncthreads();
   }
@@ -918,6 +921,9 @@ hipError_t launch_step(const StepArgs& a, const Shape& s, int grid, hipStream_t 
                          stream, a);                                                   \
     else if (a.points_out)                                                             \
       hipLaunchKernelGGL((step_kernel<g, ppl, lpl, kPoints>), dim3(grid), dim3(64), 0,  \
+                         stream, a);                                                   \
+    else if (a.hf_bilinear)                                                            \
+      hipLaunchKernelGGL((step_kernel<g, ppl, lpl, kStep, true>), dim3(grid), dim3(64), 0, \
                          stream, a);                                                   \
     else                                                                               \
       hipLaunchKernelGGL((step_kernel<g, ppl, lpl, kStep>), dim3(grid), dim3(64), 0,    \

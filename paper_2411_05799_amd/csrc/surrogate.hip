@@ -72,6 +72,8 @@ __device__ __forceinline__ float command(const WorldView& v, int i, int lk_off, 
 }
 
 __device__ __forceinline__ float hf(const WorldView& v, float x, float y) {
+  if (v.a.hf_bilinear)
+    return npx::hf_bilinear(v.a.hf, v.a.hf_nx, v.a.hf_ny, v.a.hf_x0, v.a.hf_y0, v.a.hf_s, x, y);
   return npx::hf_lookup(v.a.hf, v.a.hf_nx, v.a.hf_ny, v.a.hf_x0, v.a.hf_y0, v.a.hf_s, x, y);
 }
 

@@ -266,6 +266,8 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
     return fail(NPX_EINVAL, "mu, k_n, zeta, eps must be >= 0");
   if (d->friction_weighting != 0 && d->friction_weighting != 1)
     return fail(NPX_EINVAL, "friction_weighting must be 0 or 1");
+  if (d->hf_bilinear != 0 && d->hf_bilinear != 1)
+    return fail(NPX_EINVAL, "hf_bilinear must be 0 or 1");
   for (int i = 0; i < d->n_morphs; ++i) {
     npx_status s = check_tables(d->morphs[i], i);
     if (s != NPX_OK) return s;
@@ -505,6 +507,7 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   a.zeta = (float)d->zeta;
   a.eps = (float)d->eps_lsq;
   a.fric_w = d->friction_weighting;
+  a.hf_bilinear = d->hf_bilinear;
   a.hf = w->hf;
   a.hf_nx = d->hf_nx;
   a.hf_ny = d->hf_ny;

@@ -41,7 +41,8 @@ class _WorldDesc(C.Structure):
                 ("hf_heights", C.POINTER(C.c_float)), ("n_instances", C.c_int64),
                 ("n_morphs", C.c_int32), ("morphs", C.POINTER(_MorphTables)),
                 ("instance_morph", C.POINTER(C.c_int32)), ("init_pose", C.POINTER(C.c_float)),
-                ("ctrl", C.POINTER(C.c_float)), ("friction_weighting", C.c_int32)]
+                ("ctrl", C.POINTER(C.c_float)), ("friction_weighting", C.c_int32),
+                ("hf_bilinear", C.c_int32)]
 
 
 class Launch(C.Structure):
@@ -219,7 +220,8 @@ class World:
                           len(w.morphs), morphs, im.ctypes.data_as(C.POINTER(C.c_int32)),
                           pose.ctypes.data_as(C.POINTER(C.c_float)),
                           ctrl.ctypes.data_as(C.POINTER(C.c_float)),
-                          int(getattr(p, "friction_weighting", 0)))
+                          int(getattr(p, "friction_weighting", 0)),
+                          int(getattr(p, "hf_bilinear", 0)))
         h = C.c_void_p()
         check(lib().npx_create_world(C.byref(desc), C.byref(h)))
         self.h = h

@@ -60,6 +60,10 @@ def test_bad_tables_rejected_before_device_use():
                     inst_morph=w.inst_morph, ctrl=w.ctrl, pose=w.pose)
     with pytest.raises(N.NpxError, match="friction_weighting"):
         N.World(w5)
+    w6 = W.Workload(params=W.Params(hf_bilinear=3), hf=w.hf, morphs=w.morphs,
+                    inst_morph=w.inst_morph, ctrl=w.ctrl, pose=w.pose)
+    with pytest.raises(N.NpxError, match="hf_bilinear"):
+        N.World(w6)
 
 
 def test_missing_library_fails_loudly(monkeypatch):

@@ -373,3 +373,22 @@ def test_force_weighted_friction_windows():
         gw_u.step_n(600)
         d = np.abs(gw_w.read_state(N.F_COG)[:2] - gw_u.read_state(N.F_COG)[:2]).max()
     assert d > 1e-4, d
+
+
+def test_bilinear_ground_windows():
+    """The height map read bilinearly between cell centres (the smoother-ground
+    option): 32 hexapods on the terrain, 3 windows of 200 frames against the
+    oracle's bilinear reading, and the reading changes the trajectories."""
+    say("case: bilinear ground, 32 hexapods x 3 windows")
+    w = W.hexapod_batch(32, seed=41, hf=W.octave_terrain(6), n_steps=600)
+    w.params.hf_bilinear = True
+    ow = O.OracleWorld(w)
+    with N.World(w) as gw:
+        res = run_windows(ow, gw, list(range(32)), starts=[0, 200, 400], every=40)
+    assert_windows(res, "bilinear", ow)
+    w0 = W.hexapod_batch(32, seed=41, hf=W.octave_terrain(6), n_steps=600)
+    with N.World(w) as gw_b, N.World(w0) as gw_t:
+        gw_b.step_n(600)
+        gw_t.step_n(600)
+        d = np.abs(gw_b.read_state(N.F_COG)[:2] - gw_t.read_state(N.F_COG)[:2]).max()
+    assert d > 1e-4, d
