@@ -151,7 +151,67 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<T> g) {
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  if (kb < ke) {
+  bool staged = false;
+  if constexpr (std::is_same<T, __bf16>::value) {
+    // BF16 with a K range of whole 64-wide chunks: the block stages each
+    // chunk of its 64 A rows and 64 B rows in LDS (coalesced 16-byte loads,
+    // eight lanes per row, two buffers, the next chunk's loads in flight
+    // during the current chunk's products, one barrier per chunk), so a row
+    // is fetched once per block rather than once per wave. In a chunk, lane
+    // group grp takes k in [16 grp, 16 grp + 16) of its rows as two 8-element
+    // slices and product j multiplies slice j of both operands; rows are
+    // padded to 72 elements (eight lanes reading eight rows touch 32 banks).
+    if (kb < ke && (ke - kb) % 64 == 0) {
+      staged = true;
+      constexpr int KC = 64, LDR = KC + 8;
+      __shared__ __bf16 As[2][TILE][LDR];
+      __shared__ __bf16 Bs[2][TILE][LDR];
+      const int t = threadIdx.x;
+      const int mb = mt * TILE, nbase = (tile % tiles_n) * TILE;
+      bf16x8 ga[2], gb[2];
+      auto fetch = [&](int k0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int piece = t + 256 * i, row = piece >> 3, c8 = (piece & 7) * 8;
+          ga[i] = M::load(g.A + (int64_t)(mb + row) * g.lda + k0 + c8);
+          gb[i] = M::load(g.B + (int64_t)(nbase + row) * g.ldb + k0 + c8);
+        }
+      };
+      auto stage = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int piece = t + 256 * i, row = piece >> 3, c8 = (piece & 7) * 8;
+          *reinterpret_cast<bf16x8*>(&As[buf][row][c8]) = ga[i];
+          *reinterpret_cast<bf16x8*>(&Bs[buf][row][c8]) = gb[i];
+        }
+      };
+      const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+      fetch(kb);
+      stage(0);
+      __syncthreads();
+      const int n_chunks = (ke - kb) / KC;
+      for (int c = 0; c < n_chunks; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < n_chunks) fetch(kb + (c + 1) * KC);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int kk = 16 * grp + 8 * j;
+          const bf16x8 fa0 = *reinterpret_cast<const bf16x8*>(&As[buf][wm + r16][kk]);
+          const bf16x8 fa1 = *reinterpret_cast<const bf16x8*>(&As[buf][wm + 16 + r16][kk]);
+          const bf16x8 fb0 = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn + r16][kk]);
+          const bf16x8 fb1 = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn + 16 + r16][kk]);
+          M::mma(fa0, fb0, acc[0][0]);
+          M::mma(fa0, fb1, acc[0][1]);
+          M::mma(fa1, fb0, acc[1][0]);
+          M::mma(fa1, fb1, acc[1][1]);
+        }
+        if (c + 1 < n_chunks) stage(buf ^ 1);
+        __syncthreads();
+      }
+    }
+  }
+
+  if (kb < ke && !staged) {
     auto fa0 = M::load(a0 + kb), fa1 = M::load(a1 + kb);
     auto fb0 = M::load(b0 + kb), fb1 = M::load(b1 + kb);
     for (int k = kb + KSTEP; k < ke; k += KSTEP) {
