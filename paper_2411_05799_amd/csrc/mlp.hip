@@ -684,10 +684,14 @@ __global__ void grad_reduce_kernel(LayerTable t, float* g) {
   const int64_t q = p - t.off[l];
   const int64_t nw = (int64_t)t.out_p[l] * t.in_p[l];
   float s = 0.f;
+  // (unrolled so that the loads of a run of slices are in flight together;
+  // the additions keep their order)
   if (q < nw) {
+#pragma unroll 8
     for (int k = 0; k < t.dw_slices[l]; ++k) s += t.dwp[l][(int64_t)k * nw + q];
   } else {
     const int o = (int)(q - nw);
+#pragma unroll 8
     for (int k = 0; k < t.db_tiles; ++k) s += t.dbp[l][(int64_t)k * t.out_p[l] + o];
   }
   g[p] = s;
@@ -1017,7 +1021,7 @@ npx_status backward_t(npx_sur* s, const float* x, int64_t ldx, const float* y, i
     GemmArgs<T> gw = gemm_args<T>(curT, Mp, hprevT, Mp, out_p, in_p, Mp);
     const int tiles = (out_p / TILE) * (in_p / TILE);
     const int sl = k_slices(tiles, Mp);
-    gw.k_split = round_up((Mp + sl - 1) / sl, KSTEP);
+    gw.k_split = round_up((Mp + sl - 1) / sl, 64);  // whole 64-wide chunks (LDS-staged)
     const int used = (Mp + gw.k_split - 1) / gw.k_split;
     gw.C = s->dwp[l];
     gw.ldc = in_p;
