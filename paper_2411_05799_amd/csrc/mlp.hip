@@ -852,10 +852,10 @@ hipError_t launch_gemm(const GemmArgs<T>& g, int slices, hipStream_t st) {
   if (g.M % TILE || g.N % TILE || g.K % KSTEP || g.k_split % KSTEP ||
       (int64_t)g.k_split * slices < g.K)
     return hipErrorInvalidValue;
-  // large forward products: 128x128 tiles when they give at least half a block per CU
+  // large forward products: 128x128 tiles when they give at least 4 blocks per CU
   if constexpr (std::is_same<T, __bf16>::value && (EPI == EPI_HID || EPI == EPI_OUT)) {
     if (slices == 1 && g.M % BIG == 0 && g.N % BIG == 0 && g.K % 64 == 0 &&
-        (g.M / BIG) * (g.N / BIG) >= 128) {
+        (g.M / BIG) * (g.N / BIG) >= 1024) {
       hipLaunchKernelGGL((gemm_big_kernel<EPI>), dim3((g.M / BIG) * (g.N / BIG)), dim3(256), 0,
                          st, g);
       return hipGetLastError();
