@@ -579,17 +579,32 @@ __global__ __launch_bounds__(256) void pack_input_kernel(
   __shared__ float tile[64][65];
   const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
   const int tc = threadIdx.x & 63, tr = threadIdx.x >> 6;
-  for (int rr = tr; rr < 64; rr += 4) {
-    const int r = r0 + rr, c = c0 + tc;
-    float v = 0.f;
-    if (r < batch && c < n_in) {
-      const int64_t src = rows ? (int64_t)rows[r] : (int64_t)r;
-      float xr = x[src * ldx + c];
-      if (nz.v && c >= nz.c0 && c < nz.c0 + nz.n) xr += nz.v[(int64_t)r * nz.ld + (c - nz.c0)];
-      v = (xr - mean[c]) * inv_std[c];
-    }
+  const int c = c0 + tc;
+  const bool cok = c < n_in;
+  const bool noisy = nz.v && c >= nz.c0 && c < nz.c0 + nz.n;
+  // a thread's 16 rows: every gather index, then every load, are issued
+  // before the first use, so the dependent loads overlap
+  constexpr int RPT = 16;
+  int64_t src[RPT];
+  float xr[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = r0 + tr + 4 * i;
+    src[i] = r < batch ? (rows ? (int64_t)rows[r] : (int64_t)r) : -1;
+  }
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = r0 + tr + 4 * i;
+    xr[i] = (src[i] >= 0 && cok) ? x[src[i] * ldx + c] : 0.f;
+    if (noisy && src[i] >= 0) xr[i] += nz.v[(int64_t)r * nz.ld + (c - nz.c0)];
+  }
+  const float mu = cok ? mean[c] : 0.f, is = cok ? inv_std[c] : 0.f;
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int rr = tr + 4 * i;
+    const float v = (src[i] >= 0 && cok) ? (xr[i] - mu) * is : 0.f;
     tile[rr][tc] = v;
-    X[(int64_t)r * ldX + c] = to_t<T>(v);
+    X[(int64_t)(r0 + rr) * ldX + c] = to_t<T>(v);
   }
   if (!XT) return;
   __syncthreads();
@@ -611,21 +626,38 @@ __global__ __launch_bounds__(256) void loss_kernel(
   const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
   const int tc = threadIdx.x & 63, tr = threadIdx.x >> 6;
   const int c = c0 + tc;
+  const bool cok = c < n_out;
+  const bool noisy = nz.v && c >= nz.c0 && c < nz.c0 + nz.n;
+  // as in the input packing: all gathers and loads issued before first use
+  constexpr int RPT = 16;
+  int64_t src[RPT];
+  float yr[RPT], yh[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = r0 + tr + 4 * i;
+    src[i] = r < batch ? (rows ? (int64_t)rows[r] : (int64_t)r) : -1;
+  }
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = r0 + tr + 4 * i;
+    const bool ok = src[i] >= 0 && cok;
+    yr[i] = ok ? y[src[i] * ldy + c] : 0.f;
+    yh[i] = ok ? yhat[(int64_t)r * ldyh + c] : 0.f;
+    if (noisy && src[i] >= 0) yr[i] -= nz.v[(int64_t)r * nz.ld + (c - nz.c0)];
+  }
+  const float mu = cok ? y_mean[c] : 0.f, is = cok ? y_inv_std[c] : 0.f;
   double l2 = 0.0;
-  for (int rr = tr; rr < 64; rr += 4) {
-    const int r = r0 + rr;
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int rr = tr + 4 * i;
     float d = 0.f;
-    if (r < batch && c < n_out) {
-      const int64_t src = rows ? (int64_t)rows[r] : (int64_t)r;
-      float yr = y[src * ldy + c];
-      if (nz.v && c >= nz.c0 && c < nz.c0 + nz.n) yr -= nz.v[(int64_t)r * nz.ld + (c - nz.c0)];
-      const float yn = (yr - y_mean[c]) * y_inv_std[c];
-      const float e = yhat[(int64_t)r * ldyh + c] - yn;
+    if (src[i] >= 0 && cok) {
+      const float e = yh[i] - (yr[i] - mu) * is;
       l2 += (double)e * e;
       d = grad_scale * e;
     }
     tile[rr][tc] = d;
-    dY[(int64_t)r * lddy + c] = to_t<T>(d);
+    dY[(int64_t)(r0 + rr) * lddy + c] = to_t<T>(d);
   }
   lsum[threadIdx.x] = l2;
   __syncthreads();
