@@ -224,6 +224,53 @@ void orc_cell(const orc_params* p, double x, double y, int* i, int* j) {
   *j = cell_index(y, p->hf_y0, p->hf_s, p->hf_ny);
 }
 
+static int cmp_double(const void* a, const void* b) {
+  const double x = *(const double*)a, y = *(const double*)b;
+  return (x > y) - (x < y);
+}
+
+/* The segment is split at every parameter t where it crosses a grid line
+ * x = x0 + k/s or y = y0 + k/s; inside each piece it stays in one cell (the
+ * cell of the piece's midpoint), whose ground is flat, and its height is
+ * linear in t. The first piece that starts at or below its cell's height, or
+ * ends there, holds the first ground point. */
+double orc_ray_range(const orc_params* p, const double A[3], const double B[3]) {
+  const double d[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+  const double len = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  const double s = p->hf_s;
+  const double org[2] = {p->hf_x0, p->hf_y0};
+  int cap = 2;
+  for (int a = 0; a < 2; ++a) cap += (int)(fabs(d[a]) * s) + 2;
+  double* t = (double*)malloc(sizeof(double) * cap);
+  int n = 0;
+  t[n++] = 0.0;
+  t[n++] = 1.0;
+  for (int a = 0; a < 2; ++a) {
+    if (d[a] == 0.0) continue;
+    const double u0 = (A[a] - org[a]) * s, u1 = (B[a] - org[a]) * s;
+    const double lo = fmin(u0, u1), hi = fmax(u0, u1);
+    for (double k = floor(lo) + 1.0; k < hi; k += 1.0) {
+      const double tk = (org[a] + k / s - A[a]) / d[a];
+      if (tk > 0.0 && tk < 1.0 && n < cap) t[n++] = tk;
+    }
+  }
+  qsort(t, n, sizeof(double), cmp_double);
+  double out = len;
+  for (int q = 0; q + 1 < n; ++q) {
+    const double ta = t[q], tb = t[q + 1];
+    if (!(tb > ta)) continue;
+    const double tm = 0.5 * (ta + tb);
+    int i, j;
+    orc_cell(p, A[0] + tm * d[0], A[1] + tm * d[1], &i, &j);
+    const double h = p->hf[(size_t)j * p->hf_nx + i];
+    const double za = A[2] + ta * d[2], zb = A[2] + tb * d[2];
+    if (za <= h) { out = ta * len; break; }
+    if (zb <= h) { out = (h - A[2]) / d[2] * len; break; }
+  }
+  free(t);
+  return out;
+}
+
 /* One axis of the bilinear reading: the lower centre index and the fraction
  * towards the next, the coordinate held inside the outer centres. */
 static void centre_axis(double x, double x0, double s, int n, int* i0, double* f) {

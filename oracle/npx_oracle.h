@@ -91,6 +91,13 @@ void orc_fk(const orc_morph* m, const double* q, double* y, double* g_b, double*
 void orc_cell(const orc_params* p, double x, double y, int* i, int* j);
 double orc_height(const orc_params* p, double x, double y);
 
+/* Range sensor (a ray of the construction API, Sec. IV, read against the
+ * look-up-table ground of Sec. III-A): the distance from A to the first point
+ * of the segment A -> B whose height is at or below the stored height of the
+ * cell it lies in, or |B - A| when there is none (0 when A is at or below).
+ * Nearest-cell ground only (p->hf_bilinear is ignored). */
+double orc_ray_range(const orc_params* p, const double A[3], const double B[3]);
+
 /* Friction least squares on n point pairs (ground-plane coordinates):
  * src [n][2] at t, dst [n][2] at t+1. Writes a1, a2, a3. Returns the number of
  * unknowns solved (0 none, 2 translation only, 3 full). */

@@ -8,6 +8,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 import subprocess
+from types import SimpleNamespace
 
 import numpy as np
 
@@ -61,6 +62,8 @@ def lib():
                                C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.orc_height.argtypes = [C.POINTER(_Params), C.c_double, C.c_double]
         L.orc_height.restype = C.c_double
+        L.orc_ray_range.argtypes = [C.POINTER(_Params), dp, dp]
+        L.orc_ray_range.restype = C.c_double
         L.orc_lsq.argtypes = [C.c_int, dp, dp, C.c_double, dp]
         L.orc_lsq_w.argtypes = [C.c_int, dp, dp, dp, C.c_double, dp]
         L.orc_init_state.argtypes = [C.POINTER(_Morph), C.POINTER(_Params), fp, fp, dp]
@@ -125,6 +128,13 @@ class OracleParams:
 
     def height(self, x, y):
         return lib().orc_height(C.byref(self.c), float(x), float(y))
+
+    def ray_range(self, A, B):
+        """Distance from A to the first ground point of the segment A -> B
+        (look-up-table ground), or |B - A|."""
+        a = (C.c_double * 3)(*[float(v) for v in A])
+        b = (C.c_double * 3)(*[float(v) for v in B])
+        return lib().orc_ray_range(C.byref(self.c), a, b)
 
 
 def lsq(src, dst, eps=1e-4, weights=None):
@@ -194,6 +204,24 @@ class OracleWorld:
         sptr = (dp * n)(*[_dptr(s) for s in states])
         return lib().orc_run_batch(n, self._cmorphs, _iptr(im), C.byref(self.params.c), cptr, sptr,
                                    int(n_steps), int(threads))
+
+    def ray_ends(self, i, st, rays, ray_link):
+        """World start and end [n, 3] of rays riding on instance i's links at
+        state st: each end is a massless point of its link, moved like the mass
+        points (the robot's CoG and inertia are unchanged)."""
+        m = self.morph_of(i)
+        r = np.asarray(rays, dtype=np.float32).reshape(-1, 6)
+        k = np.asarray(ray_link, dtype=np.int32).reshape(-1)
+        n = r.shape[0]
+        z = np.zeros((n, 1), np.float32)
+        aug = SimpleNamespace(points=np.concatenate([m.points, np.hstack([r[:, :3], z]),
+                                                     np.hstack([r[:, 3:], z])]),
+                              pt_link=np.concatenate([m.pt_link, k, k]),
+                              parent=m.parent, joint=m.joint)
+        am = OracleMorph(aug)
+        P = np.zeros((am.n_points, 3))
+        lib().orc_points(C.byref(am.c), _dptr(np.ascontiguousarray(st)), _dptr(P))
+        return P[m.n_points:m.n_points + n], P[m.n_points + n:]
 
     def points(self, i, st):
         m = self.morph_of(i)

@@ -234,6 +234,38 @@ def random_legged(rng: np.random.Generator) -> Morph:
 # terrain
 # ----------------------------------------------------------------------------
 
+def sensor_rays(m: Morph) -> tuple:
+    """Six range-sensor rays of a legged robot, in its construction frame: from
+    the torso's centre (mean of the root link's points) straight down 0.5 m and
+    0.5 m down-and-out towards +x, -x, +y, -y at 45 degrees; and from the
+    centre of the first leaf link's points straight down 0.3 m.
+    Returns (rays [6, 6] float32 start+end, ray_link [6] int32)."""
+    pts = m.points[:, :3].astype(np.float64)
+    c0 = pts[m.pt_link == 0].mean(axis=0)
+    children = np.bincount(m.parent[1:], minlength=m.n_links) if m.n_links > 1 else np.zeros(1)
+    leaf = int(np.flatnonzero(children == 0)[0]) if m.n_links > 1 else 0
+    cf = pts[m.pt_link == leaf].mean(axis=0)
+    h = 0.5 / np.sqrt(2.0)
+    dirs = [(0, 0, -0.5), (h, 0, -h), (-h, 0, -h), (0, h, -h), (0, -h, -h)]
+    rays = [np.r_[c0, c0 + np.asarray(d)] for d in dirs] + [np.r_[cf, cf + [0, 0, -0.3]]]
+    links = [0] * 5 + [leaf]
+    return np.asarray(rays, np.float32), np.asarray(links, np.int32)
+
+
+def random_rays(m: Morph, n: int, rng: np.random.Generator) -> tuple:
+    """n rays on random links of m: starts at random points of the link (jittered
+    by up to 2 cm), random directions, lengths U[0.05, 1.0] m."""
+    link = rng.integers(0, m.n_links, n).astype(np.int32)
+    rays = np.zeros((n, 6), np.float32)
+    for k in range(n):
+        own = np.flatnonzero(m.pt_link == link[k])
+        p = m.points[rng.choice(own), :3].astype(np.float64) + rng.uniform(-0.02, 0.02, 3)
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        rays[k] = np.r_[p, p + d * rng.uniform(0.05, 1.0)]
+    return rays, link
+
+
 def flat_ground(s: float = 50.0) -> Heightfield:
     """Flat plane z = 0: a single cell, every look-up clamps onto it."""
     return Heightfield(nx=1, ny=1, s=s, x0=float(np.float32(-5.12)), y0=float(np.float32(-5.12)),
