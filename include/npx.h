@@ -95,7 +95,8 @@ int npx_create_cylinder(npx_morph* m, double x1, double y1, double z1, double x2
                         double z2, double rr, double mass, int ring_pts);
 /* the 12 vertices of a regular icosahedron of radius rr (mode 0). */
 int npx_create_sphere(npx_morph* m, double x, double y, double z, double rr, double mass);
-/* no mass points; never collides. */
+/* no mass points; never collides. Glued (npx_connect_bodies) to a body of a
+ * link, it becomes that link's range sensor (npx_world_ray_ranges). */
 int npx_create_ray(npx_morph* m, double x1, double y1, double z1, double x2, double y2, double z2);
 /* connectBodies: glue two bodies into one rigid link. */
 npx_status npx_connect_bodies(npx_morph* m, int id1, int id2);
@@ -117,6 +118,13 @@ int npx_get_max_body_id(const npx_morph* m);
  * parent joints or a body not reachable from the root. */
 npx_status npx_finalize_construction(npx_morph* m);
 npx_status npx_morph_get_tables(const npx_morph* m, npx_morph_tables* out);
+/* The finalised morph's range-sensor rays (Sec. IV, createRay): those glued
+ * to a link, in creation order. rays [n][6]: start then end point in the
+ * construction frame (the frame of the tables' points, after the bodies'
+ * moves and rotations); ray_link [n]: the link each rides on. Views owned by
+ * the morph, valid until npx_morph_free; NPX_ESTATE before finalisation. */
+npx_status npx_morph_get_rays(const npx_morph* m, int32_t* n_rays, const float** rays,
+                              const int32_t** ray_link);
 /* index of a joint id in the tables' joint order (the controller's order). */
 int npx_morph_joint_index(const npx_morph* m, int joint_id);
 
@@ -212,6 +220,31 @@ npx_status npx_write_state(npx_world* w, int field, const void* src, size_t byte
  * step's own transform path: float [n_instances][N_max][3] (rows past an
  * instance's point count are zero). Synchronous. */
 npx_status npx_read_points(npx_world* w, float* dst, size_t bytes, int dst_on_device);
+
+/* ---------------------------------------------------------------------- */
+/* Range sensors: the rays of the construction API (Sec. IV, createRay)    */
+/* ---------------------------------------------------------------------- */
+/* Sets the rays of every instance of morphology `morph` (replacing earlier
+ * ones). rays: host [n_rays][6], start then end point in that morphology's
+ * construction frame (the frame of its table points, as npx_morph_get_rays
+ * lists them); ray_link: host [n_rays], the link each rides on, in
+ * [0, n_links). 0 <= n_rays <= 64 (0 removes them). A ray may cross at most
+ * 65,536 cells of the height map (s sqrt(2) length + 4 <= 65,536), else
+ * NPX_EINVAL. Copies the tables; synchronous (waits for the device). */
+npx_status npx_world_set_rays(npx_world* w, int32_t morph, int32_t n_rays, const float* rays,
+                              const int32_t* ray_link);
+/* Range of every ray at the current state, asynchronously on hip_stream:
+ * dst device float [n_instances][ld], ld >= the largest ray count of any
+ * morphology (and >= 1). A ray rides on its link like a massless point: an
+ * end p is at c + R(Q)(T_link p - g_b), the transform of the mass points
+ * (Sec. III-A, III-B). dst[i][k] = the distance from ray k's start to the
+ * first point of the segment that is at or below the ground, the ground
+ * being the step's look-up table (Sec. III-A: the height of the cell a
+ * point's floor indices name, clamped to the map); 0 when the start is at or
+ * below it; the ray's length when no point is. NaN for a non-finite state.
+ * Entries past an instance's own ray count are not written. NPX_EINVAL for a
+ * world that reads its map bilinearly or for ld too small. */
+npx_status npx_world_ray_ranges(npx_world* w, float* dst, int64_t ld, void* hip_stream);
 
 /* ---------------------------------------------------------------------- */
 /* Launch shape (chosen by the autotuner or set by hand)                   */

@@ -17,7 +17,9 @@
 //  * simplifyMode applies to cylinders and spheres created afterwards
 //    (Sec. IV-C): 1 box (the 8 corners of the bounding box), 2 two points,
 //    >= 3 one point at the reference point;
-//  * a ray has no mass points and never collides;
+//  * a ray has no mass points and never collides; glued to a body of a link,
+//    it is that link's range sensor (its start and end follow the body's
+//    moves and rotations); a ray glued to no link is not listed;
 //  * the root link is the link holding body 0.
 #include <algorithm>
 #include <cmath>
@@ -86,6 +88,7 @@ struct Body {
   std::vector<V3> local;  // points in the body frame
   double mass = 0;
   bool ray = false;
+  V3 ray_end;             // a ray's end point in the body frame (its start is ref)
 };
 
 struct Joint {
@@ -106,6 +109,8 @@ struct npx_morph {
   // finalised tables
   std::vector<float> points, joint_rows;
   std::vector<int32_t> pt_link, parent, joint_of_link, link_of_joint;
+  std::vector<float> rays;       // [n][6] start, end (construction frame)
+  std::vector<int32_t> ray_link; // [n]
 };
 
 namespace {
@@ -240,11 +245,11 @@ int npx_create_sphere(npx_morph* m, double x, double y, double z, double rr, dou
 
 int npx_create_ray(npx_morph* m, double x1, double y1, double z1, double x2, double y2, double z2) {
   if (!m) return bad(NPX_EINVAL, "null morph");
-  (void)x2, (void)y2, (void)z2;
   Body b;
   b.ref = {x1, y1, z1};
   b.orient = M3::eye();
   b.ray = true;
+  b.ray_end = {x2 - x1, y2 - y1, z2 - z1};
   return add_body(m, b);
 }
 
@@ -362,6 +367,17 @@ npx_status npx_finalize_construction(npx_morph* m) {
     }
   }
   if (m->points.empty()) return bad(NPX_EINVAL, "no mass points");
+  m->rays.clear();
+  m->ray_link.clear();
+  for (int b = 0; b < B; ++b) {
+    const Body& bd = m->bodies[b];
+    const int l = link_of_group[group[b]];
+    if (!bd.ray || l < 0) continue;
+    const V3 e = add(bd.ref, bd.orient * bd.ray_end);
+    m->rays.insert(m->rays.end(), {(float)bd.ref.x, (float)bd.ref.y, (float)bd.ref.z,
+                                   (float)e.x, (float)e.y, (float)e.z});
+    m->ray_link.push_back(l);
+  }
   m->final = true;
   return NPX_OK;
 }
@@ -375,6 +391,16 @@ npx_status npx_morph_get_tables(const npx_morph* m, npx_morph_tables* out) {
   out->pt_link = m->pt_link.data();
   out->parent = m->parent.data();
   out->joint = m->joint_rows.data();
+  return NPX_OK;
+}
+
+npx_status npx_morph_get_rays(const npx_morph* m, int32_t* n_rays, const float** rays,
+                              const int32_t** ray_link) {
+  if (!m || !n_rays || !rays || !ray_link) return bad(NPX_EINVAL, "null argument");
+  if (!m->final) return bad(NPX_ESTATE, "construction is not finalised");
+  *n_rays = (int32_t)m->ray_link.size();
+  *rays = m->rays.data();
+  *ray_link = m->ray_link.data();
   return NPX_OK;
 }
 

@@ -16,6 +16,7 @@
 
 #include "npx.h"
 #include "npx_internal.h"
+#include "npx_sensor_internal.h"
 
 namespace {
 thread_local std::string g_err;
@@ -81,6 +82,13 @@ struct npx_world {
   int* lp_off = nullptr;   // [total links + 1] point range of each link in lp_idx
   int* lp_idx = nullptr;   // [total points] point indices grouped by link
   unsigned long long* sub_mask = nullptr;  // [total links] links of each link's subtree
+  // range sensors: per morphology host copies, and their device tables
+  std::vector<std::vector<float>> ray_host;
+  std::vector<std::vector<int>> ray_link_host;
+  float* rays = nullptr;
+  int* ray_link = nullptr;
+  int2* ray_info = nullptr;
+  int ray_max = 0;
 
   npx::StepArgs args{};
   npx_launch launch{64, 0, 100, 1, 8};
@@ -564,7 +572,7 @@ void npx_destroy_world(npx_world* w) {
   void* bufs[] = {w->st, w->step, w->flags, w->tele, w->inst_morph_d, w->morph_info,
                   w->morph_mass, w->pts, w->pt_link, w->pt_orig, w->links, w->link_parent,
                   w->link_depth, w->ctrl, w->hf, w->order, w->queue, w->lp_off,
-                  w->lp_idx, w->sub_mask};
+                  w->lp_idx, w->sub_mask, w->rays, w->ray_link, w->ray_info};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete w;
@@ -661,6 +669,83 @@ npx_status npx_read_points(npx_world* w, float* dst, size_t bytes, int on_device
   } while (0);
   if (!on_device) (void)hipFree(buf);
   return rc;
+}
+
+npx_status npx_world_set_rays(npx_world* w, int32_t morph, int32_t n_rays, const float* rays,
+                              const int32_t* ray_link) {
+  if (!w) return fail(NPX_EINVAL, "null world");
+  if (morph < 0 || morph >= w->n_morphs) return fail(NPX_EINVAL, "morph %d out of range", morph);
+  if (n_rays < 0 || n_rays > npx::RAY_MAX)
+    return fail(NPX_EINVAL, "n_rays %d out of [0, %d]", n_rays, npx::RAY_MAX);
+  if (n_rays > 0 && (!rays || !ray_link)) return fail(NPX_EINVAL, "null ray table");
+  const int L = w->morph_links[morph];
+  for (int k = 0; k < n_rays; ++k) {
+    if (ray_link[k] < 0 || ray_link[k] >= L)
+      return fail(NPX_EINVAL, "ray %d: link %d out of [0, %d)", k, ray_link[k], L);
+    const float* r = rays + 6 * k;
+    for (int e = 0; e < 6; ++e)
+      if (!std::isfinite(r[e])) return fail(NPX_EINVAL, "ray %d: non-finite coordinate", k);
+    // a rigid ray keeps its length; the cells it crosses are at most
+    // s (|dx| + |dy|) + 3 <= s sqrt(2) length + 3
+    const double len = std::sqrt((double)(r[3] - r[0]) * (r[3] - r[0]) +
+                                 (double)(r[4] - r[1]) * (r[4] - r[1]) +
+                                 (double)(r[5] - r[2]) * (r[5] - r[2]));
+    if (w->args.hf_s * std::sqrt(2.0) * len + 4.0 > npx::RAY_MAX_CELLS)
+      return fail(NPX_EINVAL, "ray %d crosses more than %d cells", k, npx::RAY_MAX_CELLS);
+  }
+  npx_status st = sync_last(w);
+  if (st != NPX_OK) return st;
+  w->ray_host.resize(w->n_morphs);
+  w->ray_link_host.resize(w->n_morphs);
+  w->ray_host[morph].assign(rays, rays + 6 * (size_t)n_rays);
+  w->ray_link_host[morph].assign(ray_link, ray_link + n_rays);
+  std::vector<float> all;
+  std::vector<int> links;
+  std::vector<int2> info(w->n_morphs);
+  int rmax = 0;
+  for (int m = 0; m < w->n_morphs; ++m) {
+    const int n = (int)w->ray_link_host[m].size();
+    info[m] = make_int2((int)links.size(), n);
+    all.insert(all.end(), w->ray_host[m].begin(), w->ray_host[m].end());
+    links.insert(links.end(), w->ray_link_host[m].begin(), w->ray_link_host[m].end());
+    rmax = std::max(rmax, n);
+  }
+  HIP_TRY(hipDeviceSynchronize());
+  void* old[] = {w->rays, w->ray_link, w->ray_info};
+  for (void* b : old)
+    if (b) (void)hipFree(b);
+  w->rays = nullptr;
+  w->ray_link = nullptr;
+  w->ray_info = nullptr;
+  w->ray_max = 0;
+  const size_t nr = std::max<size_t>(links.size(), 1);
+  if (hipMalloc((void**)&w->rays, nr * 6 * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&w->ray_link, nr * sizeof(int)) != hipSuccess ||
+      hipMalloc((void**)&w->ray_info, info.size() * sizeof(int2)) != hipSuccess)
+    return fail(NPX_ENOMEM, "ray tables");
+  if (!links.empty()) {
+    HIP_TRY(hipMemcpy(w->rays, all.data(), all.size() * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(w->ray_link, links.data(), links.size() * sizeof(int),
+                      hipMemcpyHostToDevice));
+  }
+  HIP_TRY(hipMemcpy(w->ray_info, info.data(), info.size() * sizeof(int2), hipMemcpyHostToDevice));
+  w->ray_max = rmax;
+  return NPX_OK;
+}
+
+npx_status npx_world_ray_ranges(npx_world* w, float* dst, int64_t ld, void* hip_stream) {
+  if (!w || !dst) return fail(NPX_EINVAL, "null argument");
+  if (w->args.hf_bilinear)
+    return fail(NPX_EINVAL, "ray ranges read the height map as its look-up table; this world "
+                            "reads it bilinearly");
+  if (ld < std::max(w->ray_max, 1))
+    return fail(NPX_EINVAL, "ld %lld below the largest ray count %d", (long long)ld, w->ray_max);
+  if (w->ray_max == 0) return NPX_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const npx::RayTables r{w->rays, w->ray_link, w->ray_info};
+  HIP_TRY(npx::launch_ray_ranges(npx::world_view(w), r, dst, ld, st));
+  npx::note_stream(w, st);
+  return NPX_OK;
 }
 
 npx_status npx_get_launch(const npx_world* w, npx_launch* out) {

@@ -120,6 +120,13 @@ def lib():
         L.npx_finalize_construction.argtypes = [vp]
         L.npx_morph_get_tables.argtypes = [vp, C.POINTER(_MorphTables)]
         L.npx_morph_joint_index.argtypes = [vp, C.c_int]
+        L.npx_morph_get_rays.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.POINTER(C.c_float)),
+                                         C.POINTER(C.POINTER(C.c_int32))]
+        L.npx_morph_get_rays.restype = C.c_int
+        L.npx_world_set_rays.argtypes = [vp, C.c_int32, C.c_int32, vp, vp]
+        L.npx_world_set_rays.restype = C.c_int
+        L.npx_world_ray_ranges.argtypes = [vp, vp, C.c_int64, vp]
+        L.npx_world_ray_ranges.restype = C.c_int
         for name in ("npx_morph_new", "npx_simplify_mode", "npx_create_point", "npx_create_box",
                      "npx_create_cylinder", "npx_create_sphere", "npx_create_ray",
                      "npx_connect_bodies", "npx_create_joint", "npx_set_joint_limits",
@@ -350,6 +357,24 @@ class World:
         check(lib().npx_sur_widths(self.h, C.byref(a), C.byref(b)))
         return a.value, b.value
 
+    def set_rays(self, morph, rays, ray_link):
+        """Range-sensor rays of morphology `morph`: rays [n, 6] (start, end in its
+        construction frame), ray_link [n] (the link each rides on)."""
+        r = np.ascontiguousarray(rays, dtype=np.float32).reshape(-1, 6)
+        k = np.ascontiguousarray(ray_link, dtype=np.int32).reshape(-1)
+        if r.shape[0] != k.shape[0]:
+            raise ValueError("rays and ray_link differ in length")
+        check(lib().npx_world_set_rays(self.h, int(morph), int(k.shape[0]),
+                                       r.ctypes.data_as(C.c_void_p), k.ctypes.data_as(C.c_void_p)))
+        self._ray_max = max(getattr(self, "_ray_max", 0), int(k.shape[0]))
+
+    def ray_ranges(self, out, stream=None):
+        """Range of every ray at the current state into a device float32 tensor
+        [I, >= the largest ray count] (asynchronous on `stream`)."""
+        check(lib().npx_world_ray_ranges(self.h, _ptr(out), out.stride(0),
+                                         C.c_void_p(_stream_handle(stream))))
+        return out
+
     def rows(self, out, stream=None):
         """State rows [I, >= 13 + 2 J] of every instance into a device tensor."""
         check(lib().npx_world_rows(self.h, _ptr(out), out.stride(0),
@@ -470,6 +495,18 @@ class MorphBuilder:
                        parent=np.ctypeslib.as_array(t.parent, shape=(l,)).copy(),
                        joint=np.ctypeslib.as_array(t.joint, shape=(l * 8,)).reshape(l, 8).copy(),
                        name=name)
+
+    def rays(self):
+        """The finalised robot's range-sensor rays: ([n, 6] start and end in the
+        construction frame, [n] link of each)."""
+        n = C.c_int32()
+        r = C.POINTER(C.c_float)()
+        k = C.POINTER(C.c_int32)()
+        self._call(lib().npx_morph_get_rays(self.h, C.byref(n), C.byref(r), C.byref(k)))
+        if n.value == 0:
+            return np.zeros((0, 6), np.float32), np.zeros(0, np.int32)
+        return (np.ctypeslib.as_array(r, shape=(n.value * 6,)).reshape(-1, 6).copy(),
+                np.ctypeslib.as_array(k, shape=(n.value,)).copy())
 
     def close(self):
         if getattr(self, "h", None):

@@ -392,3 +392,17 @@ def test_bilinear_ground_windows():
         gw_t.step_n(600)
         d = np.abs(gw_b.read_state(N.F_COG)[:2] - gw_t.read_state(N.F_COG)[:2]).max()
     assert d > 1e-4, d
+
+
+def test_paper_mode_on_terrain_windows():
+    """The paper's operating point on the 2 cm terrain: 10 ms frames, joint
+    targets every 8 frames (Sec. III-B), contacts softened to 150 N/m per point
+    (stable at that frame length): 32 hexapods, 3 windows of 200 frames (2 s
+    each) against the oracle."""
+    say("case: paper mode on terrain, 32 hexapods x 3 windows")
+    w = W.hexapod_batch(32, seed=51, n_steps=600)
+    w.params.dt, w.params.K, w.params.k_n = 1e-2, 8, 150.0
+    ow = O.OracleWorld(w)
+    with N.World(w) as gw:
+        res = run_windows(ow, gw, list(range(32)), starts=[0, 200, 400], every=40)
+    assert_windows(res, "paper mode", ow)

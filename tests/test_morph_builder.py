@@ -145,3 +145,31 @@ def test_tree_order_and_errors():
         b.create_joint(p, q, (0, 0, 0), (0, 0, 0))
     with pytest.raises(N.NpxError):
         b.create_cylinder(0, 0, 0, 0, 0, 0, 0.01, 1.0)
+
+
+def test_rays_follow_their_body_and_only_glued_rays_are_sensors():
+    """A ray glued to a link is listed with its start and end moved and turned
+    with its body (fixed-axis roll-pitch-yaw about its start); a ray glued to
+    nothing is not listed; the list is unavailable before finalisation."""
+    b = N.MorphBuilder()
+    torso = b.create_box(0.2, 0.05, 0.1, 0, 0, 0, 1.0)
+    leg = b.create_box(0.02, 0.1, 0.02, 0.2, 0, -0.05, 0.2)
+    b.create_joint(torso, leg, (0.1, 0, 0), (0, 1, 0))
+    r0 = b.create_ray(0, 0, 0, 0, 0, -0.5)
+    r1 = b.create_ray(0.2, 0, -0.1, 0.5, 0, -0.1)
+    b.create_ray(1, 1, 1, 2, 2, 2)                    # glued to nothing
+    b.connect_bodies(torso, r0)
+    b.connect_bodies(leg, r1)
+    a, be, g = 0.4, -0.2, 0.9
+    b.rotate_body(r1, a, be, g)
+    b.move_body(r1, 0.25, 0.01, -0.12)
+    with pytest.raises(N.NpxError):
+        b.rays()
+    b.finalize_construction()
+    rays, links = b.rays()
+    assert rays.shape == (2, 6) and list(links) == [0, 1]
+    np.testing.assert_allclose(rays[0], [0, 0, 0, 0, 0, -0.5], atol=1e-7)
+    R = Rotation.from_euler("xyz", [a, be, g]).as_matrix()
+    start = np.array([0.25, 0.01, -0.12])
+    np.testing.assert_allclose(rays[1, :3], start, atol=1e-7)
+    np.testing.assert_allclose(rays[1, 3:], start + R @ [0.3, 0, 0], atol=1e-6)
