@@ -469,9 +469,19 @@ static int step_ws(const orc_morph* m, const orc_params* p, const float* ctrl, d
 
   /* S3: joint-angle determination every K steps; c, Q, v, omega are kept */
   if (n % p->K == 0) {
+    /* reading of the motors' speed (Sec. III-B: joints reach their targets only
+     * if the motors are fast enough): with a rate limit, a joint moves from its
+     * angle towards the command by at most max_rate K dt per update */
+    const int limited = p->max_rate > 0.0 && !isinf(p->max_rate);
+    const double dmax = p->max_rate * p->K * p->dt;
     for (int j = 0; j < J; ++j) {
       q_prev[j] = q[j];
-      q[j] = command(m, ctrl, j, t);
+      double qn = command(m, ctrl, j, t);
+      if (limited) {
+        if (qn > q[j] + dmax) qn = q[j] + dmax;
+        if (qn < q[j] - dmax) qn = q[j] - dmax;
+      }
+      q[j] = qn;
     }
     orc_fk(m, q, w->y, g_b, I_b, &M);
     for (int k = 0; k < N; ++k)

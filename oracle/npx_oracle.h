@@ -49,6 +49,9 @@ typedef struct {
   int hf_nx, hf_ny;
   double hf_s, hf_x0, hf_y0;
   const float* hf; /* [hf_ny][hf_nx] */
+  double max_rate; /* > 0: a joint turns at most max_rate rad/s, so one joint
+                      update moves it by at most max_rate K dt towards its
+                      command (the motors' speed, Sec. III-B); 0 or +inf: no limit */
 } orc_params;
 
 /* Per-instance state vector (double), fixed offsets; q and q_prev follow. */

@@ -43,7 +43,8 @@ class _Params(C.Structure):
     _fields_ = [("dt", C.c_double), ("K", C.c_int), ("g", C.c_double * 3), ("mu", C.c_double),
                 ("k_n", C.c_double), ("zeta", C.c_double), ("eps", C.c_double),
                 ("weighted", C.c_int), ("hf_bilinear", C.c_int), ("hf_nx", C.c_int), ("hf_ny", C.c_int), ("hf_s", C.c_double),
-                ("hf_x0", C.c_double), ("hf_y0", C.c_double), ("hf", C.POINTER(C.c_float))]
+                ("hf_x0", C.c_double), ("hf_y0", C.c_double), ("hf", C.POINTER(C.c_float)),
+                ("max_rate", C.c_double)]
 
 
 _lib = None
@@ -119,7 +120,8 @@ class OracleParams:
                          float(params.zeta), float(params.eps),
                          int(getattr(params, "friction_weighting", False)),
                          int(getattr(params, "hf_bilinear", False)), int(hf.nx), int(hf.ny),
-                         float(hf.s), float(hf.x0), float(hf.y0), _fptr(self.H))
+                         float(hf.s), float(hf.x0), float(hf.y0), _fptr(self.H),
+                         float(getattr(params, "max_joint_rate", 0.0)))
 
     def cell(self, x, y):
         i, j = C.c_int(), C.c_int()

@@ -82,6 +82,7 @@ class Params:
     eps: float = 1.0e-4         # LSQ spread threshold, m
     friction_weighting: bool = False  # friction fit weighted by each point's normal force
     hf_bilinear: bool = False   # height map read bilinearly between cell centres
+    max_joint_rate: float = 0.0  # rad/s a joint may turn (0: no limit)
 
 
 @dataclass

@@ -685,3 +685,69 @@ def test_bilinear_box_rests_on_a_slope_it_would_step_on():
     gaps = low[:, 2] - 0.02 * low[:, 0]
     assert np.all(gaps < 0) and np.all(gaps > -2e-3), gaps
     assert np.linalg.norm(st[O.V_:O.V_ + 3]) < 1e-3
+
+
+def _arm_in_flight(params):
+    """A box torso with one hinged arm, 5 m above flat ground (no contact), the
+    arm commanded sin(2 pi t) rad."""
+    pts = [[sx * 0.1, sy * 0.05, sz * 0.025, 0.125] for sx in (-1, 1) for sy in (-1, 1)
+           for sz in (-1, 1)] + [[0.2, 0, 0, 0.1], [0.3, 0, 0, 0.1]]
+    joint = np.zeros((2, 8), np.float32)
+    joint[1] = [0.1, 0, 0, 0, 1, 0, -10, 10]
+    arm = W.Morph(points=np.array(pts, np.float32), pt_link=np.array([0] * 8 + [1, 1], np.int32),
+                  parent=np.array([-1, 0], np.int32), joint=joint, name="arm")
+    w = W.Workload(params=params, hf=W.flat_ground(), morphs=[arm],
+                   inst_morph=np.zeros(1, np.int32),
+                   ctrl=[np.array([[1.0, 1.0, 0.0]], np.float32)],
+                   pose=np.array([[0, 0, 5.0, 1, 0, 0, 0]], np.float32))
+    return O.OracleWorld(w)
+
+
+@pytest.mark.parametrize("K", [1, 8])
+def test_joint_rate_limit_ramps_at_the_limit(K):
+    """A command sin(2 pi t) rad rises faster than 1 rad/s near t = 0, so a joint
+    limited to 1 rad/s ramps by exactly r K dt per update: after frames 0..99
+    it has moved on every update after the first (t = 0, command 0)."""
+    ow = _arm_in_flight(W.Params(K=K, max_joint_rate=1.0))
+    st = ow.init_state(0)
+    ow.run(0, st, 100)
+    d = 1.0 * K * 1e-3
+    moves = len(range(K, 100, K))
+    q, qp = st[O.HDR], st[O.HDR + 1]
+    assert abs(q - moves * d) < 1e-12 and abs((q - qp) - d) < 1e-12
+    # unlimited, the joint follows the command itself
+    ow0 = _arm_in_flight(W.Params(K=K))
+    st0 = ow0.init_state(0)
+    ow0.run(0, st0, 100)
+    assert abs(st0[O.HDR] - math.sin(2 * math.pi * (moves * K) * 1e-3)) < 1e-12
+
+
+def test_joint_rate_limit_bounds_every_update_and_vanishes_when_loose():
+    """On hexapods on the terrain: every update moves a joint by at most r K dt
+    and some updates move one by exactly that; a limit that never binds (1e6 rad/s), zero and
+    +inf all give the unlimited trajectory bit for bit."""
+    w = W.hexapod_batch(2, seed=8)
+    ref = O.OracleWorld(w)
+    st_ref = ref.init_state(1)
+    ref.run(1, st_ref, 300)
+    for r in (0.0, math.inf, 1e6):
+        w.params.max_joint_rate = r
+        ow = O.OracleWorld(w)
+        st = ow.init_state(1)
+        ow.run(1, st, 300)
+        assert np.array_equal(st, st_ref), r
+    w.params.max_joint_rate = 0.5
+    w.params.K = 4
+    ow = O.OracleWorld(w)
+    st = ow.init_state(1)
+    J = w.morphs[0].n_links - 1
+    d = 0.5 * 4 * 1e-3
+    binding = 0
+    for n in range(300):
+        before = st.copy()
+        ow.step(1, st)
+        if n % 4 == 0:
+            dq = st[O.HDR:O.HDR + J] - before[O.HDR:O.HDR + J]
+            assert np.all(np.abs(dq) <= d * (1 + 1e-12))
+            binding += int(np.sum(np.abs(dq) > d * (1 - 1e-12)))
+    assert binding > 0
