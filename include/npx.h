@@ -164,6 +164,11 @@ typedef struct {
                                       read bilinearly between the four around (held
                                       beyond the outer centres); other values are
                                       rejected */
+  double max_joint_rate;           /* rad/s a joint may turn (the motors' speed,
+                                      Sec. III-B): each joint update moves a joint
+                                      from its angle towards its command by at most
+                                      max_joint_rate K dt; 0 or +inf: no limit;
+                                      negative or NaN: rejected */
 } npx_world_desc;
 
 typedef struct npx_world npx_world;

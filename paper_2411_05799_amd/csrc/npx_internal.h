@@ -44,6 +44,7 @@ struct StepArgs {
   float dt, inv_dt;
   double dt_d;
   int K;
+  float rate_step;        // > 0: largest joint change per update (rate K dt)
   float gx, gy, gz;
   float mu;
   int mu_inf;

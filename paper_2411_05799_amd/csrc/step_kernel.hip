@@ -788,7 +788,9 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
       const bool take = upd && active;
 #pragma unroll
       for (int l = 0; l < LPL; ++l) {
-        const float qn = command(l);
+        float qn = command(l);
+        // motors' speed: at most rate K dt towards the command per update
+        if (a.rate_step > 0.f) qn = fminf(fmaxf(qn, q[l] - a.rate_step), q[l] + a.rate_step);
         dql[l] = take ? qn - q[l] : 0.f;
         qp[l] = take ? q[l] : qp[l];
         q[l] = take ? qn : q[l];

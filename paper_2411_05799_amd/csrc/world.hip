@@ -264,6 +264,7 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   if (!d || !out) return fail(NPX_EINVAL, "null argument");
   *out = nullptr;
   if (!(d->dt > 0) || d->joint_interval < 1) return fail(NPX_EINVAL, "dt must be > 0 and K >= 1");
+  if (!(d->max_joint_rate >= 0)) return fail(NPX_EINVAL, "max_joint_rate must be >= 0");
   if (d->n_instances <= 0 || d->n_instances > (1 << 26))
     return fail(NPX_EINVAL, "n_instances %lld out of range", (long long)d->n_instances);
   if (d->n_morphs <= 0 || !d->morphs || !d->instance_morph || !d->init_pose)
@@ -506,6 +507,9 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   a.inv_dt = (float)(1.0 / d->dt);
   a.dt_d = d->dt;
   a.K = d->joint_interval;
+  a.rate_step = (d->max_joint_rate > 0 && !std::isinf(d->max_joint_rate))
+                    ? (float)(d->max_joint_rate * d->joint_interval * d->dt)
+                    : 0.f;
   a.gx = (float)d->g[0];
   a.gy = (float)d->g[1];
   a.gz = (float)d->g[2];

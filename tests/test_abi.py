@@ -64,6 +64,11 @@ def test_bad_tables_rejected_before_device_use():
                     inst_morph=w.inst_morph, ctrl=w.ctrl, pose=w.pose)
     with pytest.raises(N.NpxError, match="hf_bilinear"):
         N.World(w6)
+    for rate in (-1.0, float("nan")):
+        w7 = W.Workload(params=W.Params(max_joint_rate=rate), hf=w.hf, morphs=w.morphs,
+                        inst_morph=w.inst_morph, ctrl=w.ctrl, pose=w.pose)
+        with pytest.raises(N.NpxError, match="max_joint_rate"):
+            N.World(w7)
 
 
 def test_missing_library_fails_loudly(monkeypatch):

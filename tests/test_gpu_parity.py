@@ -406,3 +406,23 @@ def test_paper_mode_on_terrain_windows():
     with N.World(w) as gw:
         res = run_windows(ow, gw, list(range(32)), starts=[0, 200, 400], every=40)
     assert_windows(res, "paper mode", ow)
+
+
+def test_joint_rate_limit_windows():
+    """Joints turning at most 1 rad/s (the motors' speed), joint targets every
+    8 frames, on the terrain: 32 hexapods, 3 windows of 200 frames against the
+    oracle, and the limit changes the trajectories."""
+    say("case: joint rate limit, 32 hexapods x 3 windows")
+    w = W.hexapod_batch(32, seed=61, n_steps=600)
+    w.params.K, w.params.max_joint_rate = 8, 1.0
+    ow = O.OracleWorld(w)
+    with N.World(w) as gw:
+        res = run_windows(ow, gw, list(range(32)), starts=[0, 200, 400], every=40)
+    assert_windows(res, "rate limit", ow)
+    w0 = W.hexapod_batch(32, seed=61, n_steps=600)
+    w0.params.K = 8
+    with N.World(w) as gw_l, N.World(w0) as gw_u:
+        gw_l.step_n(200)
+        gw_u.step_n(200)
+        d = np.abs(gw_l.read_state(N.F_JOINT) - gw_u.read_state(N.F_JOINT)).max()
+    assert d > 1e-3, d
