@@ -252,6 +252,33 @@ npx_status npx_world_set_rays(npx_world* w, int32_t morph, int32_t n_rays, const
 npx_status npx_world_ray_ranges(npx_world* w, float* dst, int64_t ld, void* hip_stream);
 
 /* ---------------------------------------------------------------------- */
+/* Machine-code controller (Sec. V, the interpreter's command table)       */
+/* ---------------------------------------------------------------------- */
+/* Foot contact sensors of morphology `morph`: sensor s reads 1 when any mass
+ * point of link links[s] is in contact (strictly below the ground, the step's
+ * own test), else 0; sensor numbers past n read 0. links: host [n], each in
+ * [0, n_links); 0 <= n <= 32. Synchronous. */
+npx_status npx_world_set_sensors(npx_world* w, int32_t morph, int32_t n, const int32_t* links);
+/* Runs every instance's machine-code program for n_updates joint updates:
+ * each update reads the foot sensors at the current state, executes n_instr
+ * instructions, writes the joint targets as the controller's commands
+ * (A = target, f = 0, phi = pi/2, replacing npx_set_controller's parameters)
+ * and advances the world by K frames; asynchronous on hip_stream.
+ * programs: device uint8 [n_instances][32]. Byte = 3-bit command, 5-bit
+ * argument: 0 move motor (joint) arg left, 1 right (target -/+ motor_step rad,
+ * held within the joint's limits; arg >= J does nothing), 2 accumulator =
+ * sensor arg, 3 accumulator = arg, 4 jump to address arg if the accumulator is
+ * non-zero, 5 accumulator = NOT accumulator, 6 increment, 7 decrement (8 bits,
+ * wrapping); the program counter wraps from 31 to 0.
+ * vm: device int32 [n_instances][2] (program counter, accumulator), read and
+ * written, carried between calls. targets: device float [n_instances][ld],
+ * ld >= J_max, read and written. 0 <= n_instr <= 4096; motor_step finite,
+ * >= 0. */
+npx_status npx_gp_run(npx_world* w, const uint8_t* programs, int32_t* vm, float* targets,
+                      int64_t ld_targets, int32_t n_updates, int32_t n_instr, float motor_step,
+                      void* hip_stream);
+
+/* ---------------------------------------------------------------------- */
 /* Launch shape (chosen by the autotuner or set by hand)                   */
 /* ---------------------------------------------------------------------- */
 typedef struct {

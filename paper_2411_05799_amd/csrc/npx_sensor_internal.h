@@ -18,4 +18,22 @@ struct RayTables {
 hipError_t launch_ray_ranges(const WorldView& v, const RayTables& r, float* dst, int64_t ld,
                              hipStream_t stream);
 
+constexpr int GP_BYTES = 32;  // program length (jumps name one of 32 addresses)
+constexpr int FOOT_MAX = 32;  // sensors per morphology (5-bit sensor numbers)
+
+struct GpArgs {
+  const uint8_t* prog;    // [n_inst][GP_BYTES]
+  int* vm;                // [n_inst][2] program counter, accumulator
+  float* targets;         // [n_inst][ld_targets] joint targets
+  int64_t ld_targets;
+  const int* foot_link;   // [total sensors] link of each foot sensor in its morphology
+  const int2* foot_info;  // [n_morphs] first sensor, sensor count
+  int n_instr;            // instructions per joint update
+  float step;             // motor step, rad
+  float* ctrl;            // the world's controller [n_inst][j_max][3]
+};
+
+// One joint update of the machine-code controller of every instance.
+hipError_t launch_gp(const WorldView& v, const GpArgs& g, hipStream_t stream);
+
 }  // namespace npx

@@ -69,16 +69,16 @@ __device__ float ray_range(const StepArgs& a, const float A[3], const float B[3]
   return len;
 }
 
-// One robot per block of one wave: lane l owns link l for the transforms and
-// rays l, l + 64, ... for the march.
-__global__ __launch_bounds__(64) void ray_kernel(WorldView v, RayTables r, float* dst,
-                                                 int64_t ld) {
-  __shared__ float T[64][12];  // link transforms in the construction frame: R, t
-  const int i = blockIdx.x, l = threadIdx.x;
+// The robot's frame at the current state, computed by the block's 64 lanes
+// together (every lane must call it): T[l] = link l's transform in the
+// construction frame (its hinge's, left-multiplied by its ancestors' hinges;
+// lane l owns link l), g_b = the body CoG in that frame, c and R = the world
+// CoG and the torso rotation. An end or point p of link l is then at
+// c + R (T[l] p - g_b), the mass points' transform.
+__device__ void robot_frame(const WorldView& v, int i, int mo, float (*T)[12], float gb[3],
+                            float c[3], float R[9]) {
+  const int l = threadIdx.x;
   const int I = v.a.n_inst;
-  const int mo = v.a.inst_morph[i];
-  const int2 ri = r.ray_info[mo];
-  if (ri.y == 0) return;  // the whole block leaves together
   const int4 mi = v.a.morph_info[mo];
   const int L = mi.w, lk0 = mi.z;
   const bool own = l < L;
@@ -105,7 +105,6 @@ __global__ __launch_bounds__(64) void ray_kernel(WorldView v, RayTables r, float
     for (int k = 0; k < 3; ++k) T[l][9 + k] = tj[k];
   }
   __syncthreads();
-  // a link's transform: its hinge's, left-multiplied by its ancestors' hinges
   float Rc[9], tc[3];
   for (int k = 0; k < 9; ++k) Rc[k] = Rj[k];
   for (int k = 0; k < 3; ++k) tc[k] = tj[k];
@@ -139,27 +138,132 @@ __global__ __launch_bounds__(64) void ray_kernel(WorldView v, RayTables r, float
       mc[rr] = ml * (Rc[3 * rr] * cg[0] + Rc[3 * rr + 1] * cg[1] + Rc[3 * rr + 2] * cg[2] + tc[rr]);
   }
   const float M = v.a.morph_mass[mo];
-  float gb[3];
   for (int rr = 0; rr < 3; ++rr) gb[rr] = wave_sum(mc[rr]) / M;
-  float c[3], R[9];
   for (int rr = 0; rr < 3; ++rr) c[rr] = v.a.st[(int64_t)rr * I + i];
   quat_to_mat(v.a.st[(int64_t)3 * I + i], v.a.st[(int64_t)4 * I + i], v.a.st[(int64_t)5 * I + i],
               v.a.st[(int64_t)6 * I + i], R);
+}
 
+__device__ __forceinline__ void to_world(const float (*T)[12], int k, const float p[3],
+                                         const float gb[3], const float c[3], const float R[9],
+                                         float P[3]) {
+  float y[3];
+  for (int rr = 0; rr < 3; ++rr)
+    y[rr] = T[k][3 * rr] * p[0] + T[k][3 * rr + 1] * p[1] + T[k][3 * rr + 2] * p[2] + T[k][9 + rr] -
+            gb[rr];
+  for (int rr = 0; rr < 3; ++rr)
+    P[rr] = c[rr] + (R[3 * rr] * y[0] + R[3 * rr + 1] * y[1] + R[3 * rr + 2] * y[2]);
+}
+
+// One robot per block of one wave: the robot's frame, then lanes 0..n-1 take
+// rays l, l + 64, ... for the march.
+__global__ __launch_bounds__(64) void ray_kernel(WorldView v, RayTables r, float* dst,
+                                                 int64_t ld) {
+  __shared__ float T[64][12];
+  const int i = blockIdx.x, l = threadIdx.x;
+  const int mo = v.a.inst_morph[i];
+  const int2 ri = r.ray_info[mo];
+  if (ri.y == 0) return;  // the whole block leaves together
+  float gb[3], c[3], R[9];
+  robot_frame(v, i, mo, T, gb, c, R);
   for (int k = l; k < ri.y; k += 64) {
     const float* ry = r.rays + (int64_t)(ri.x + k) * 6;
     const int kl = r.ray_link[ri.x + k];
     float P[2][3];
-    for (int e = 0; e < 2; ++e) {
-      const float* p = ry + 3 * e;
-      float y[3];
-      for (int rr = 0; rr < 3; ++rr)
-        y[rr] = T[kl][3 * rr] * p[0] + T[kl][3 * rr + 1] * p[1] + T[kl][3 * rr + 2] * p[2] +
-                T[kl][9 + rr] - gb[rr];
-      for (int rr = 0; rr < 3; ++rr)
-        P[e][rr] = c[rr] + (R[3 * rr] * y[0] + R[3 * rr + 1] * y[1] + R[3 * rr + 2] * y[2]);
-    }
+    to_world(T, kl, ry, gb, c, R, P[0]);
+    to_world(T, kl, ry + 3, gb, c, R, P[1]);
     dst[(int64_t)i * ld + k] = ray_range(v.a, P[0], P[1]);
+  }
+}
+
+// The machine-code controller of one robot per block (one wave): foot sensors
+// from the current state, then the program's next instructions on one lane
+// (the interpreter is serial), then the targets as the step's commands.
+__global__ __launch_bounds__(64) void gp_kernel(WorldView v, GpArgs g) {
+  __shared__ float T[64][12];
+  __shared__ float tgt[64], lo[64], hi[64];
+  const int i = blockIdx.x, l = threadIdx.x;
+  const int mo = v.a.inst_morph[i];
+  const int4 mi = v.a.morph_info[mo];
+  const int L = mi.w, lk0 = mi.z, J = L - 1;
+  float gb[3], c[3], R[9];
+  robot_frame(v, i, mo, T, gb, c, R);
+
+  // sensor s (lane s): any point of its foot link strictly below its cell
+  const int2 fi = g.foot_info[mo];
+  bool touch = false;
+  if (l < fi.y) {
+    const int link = g.foot_link[fi.x + l];
+    const int p1 = v.lp_off[lk0 + link + 1];
+    for (int p = v.lp_off[lk0 + link]; p < p1; ++p) {
+      const float4 rho = v.a.pts[v.lp_idx[p]];
+      const float pr[3] = {rho.x, rho.y, rho.z};
+      float P[3];
+      to_world(T, link, pr, gb, c, R, P);
+      const float h = v.a.hf_bilinear
+                          ? hf_bilinear(v.a.hf, v.a.hf_nx, v.a.hf_ny, v.a.hf_x0, v.a.hf_y0, v.a.hf_s,
+                                        P[0], P[1])
+                          : hf_lookup(v.a.hf, v.a.hf_nx, v.a.hf_ny, v.a.hf_x0, v.a.hf_y0, v.a.hf_s,
+                                      P[0], P[1]);
+      touch |= h - P[2] > 0.f;
+    }
+  }
+  const unsigned long long sense = __ballot(touch);
+
+  if (l < J) {
+    tgt[l] = g.targets[(int64_t)i * g.ld_targets + l];
+    const float* lk = v.a.links + (int64_t)(lk0 + l + 1) * LINK_F;
+    lo[l] = lk[6];
+    hi[l] = lk[7];
+  }
+  __syncthreads();
+  if (l == 0) {
+    const uint8_t* prog = g.prog + (int64_t)i * GP_BYTES;
+    int pc = g.vm[2 * (int64_t)i] & (GP_BYTES - 1);
+    unsigned acc = (unsigned)g.vm[2 * (int64_t)i + 1] & 0xFFu;
+    for (int e = 0; e < g.n_instr; ++e) {
+      const unsigned b = prog[pc];
+      const unsigned op = b >> 5, arg = b & 31u;
+      int nxt = (pc + 1) & (GP_BYTES - 1);
+      switch (op) {
+        case 0:  // move motor left
+        case 1:  // move motor right
+          if ((int)arg < J) {
+            const float t = op == 0 ? tgt[arg] - g.step : tgt[arg] + g.step;
+            tgt[arg] = fminf(fmaxf(t, lo[arg]), hi[arg]);
+          }
+          break;
+        case 2:  // read sensor
+          acc = (int)arg < fi.y ? (unsigned)((sense >> arg) & 1ull) : 0u;
+          break;
+        case 3:  // load
+          acc = arg;
+          break;
+        case 4:  // jump if true
+          if (acc != 0u) nxt = (int)arg;
+          break;
+        case 5:  // not
+          acc = ~acc & 0xFFu;
+          break;
+        case 6:  // inc
+          acc = (acc + 1u) & 0xFFu;
+          break;
+        default:  // dec
+          acc = (acc - 1u) & 0xFFu;
+          break;
+      }
+      pc = nxt;
+    }
+    g.vm[2 * (int64_t)i] = pc;
+    g.vm[2 * (int64_t)i + 1] = (int)acc;
+  }
+  __syncthreads();
+  if (l < J) {
+    g.targets[(int64_t)i * g.ld_targets + l] = tgt[l];
+    float* cr = g.ctrl + ((int64_t)i * v.a.j_max + l) * 3;
+    cr[0] = tgt[l];
+    cr[1] = 0.f;
+    cr[2] = 1.57079637f;  // pi/2: a constant command A sin(pi/2) = A
   }
 }
 
@@ -169,6 +273,12 @@ hipError_t launch_ray_ranges(const WorldView& v, const RayTables& r, float* dst,
                              hipStream_t stream) {
   if (v.a.n_inst <= 0) return hipSuccess;
   hipLaunchKernelGGL(ray_kernel, dim3((unsigned)v.a.n_inst), dim3(64), 0, stream, v, r, dst, ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_gp(const WorldView& v, const GpArgs& g, hipStream_t stream) {
+  if (v.a.n_inst <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gp_kernel, dim3((unsigned)v.a.n_inst), dim3(64), 0, stream, v, g);
   return hipGetLastError();
 }
 

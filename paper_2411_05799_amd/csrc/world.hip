@@ -89,6 +89,10 @@ struct npx_world {
   int* ray_link = nullptr;
   int2* ray_info = nullptr;
   int ray_max = 0;
+  // foot contact sensors of the machine-code controller, per morphology
+  std::vector<std::vector<int>> foot_host;
+  int* foot_link = nullptr;
+  int2* foot_info = nullptr;
 
   npx::StepArgs args{};
   npx_launch launch{64, 0, 100, 1, 8};
@@ -576,7 +580,8 @@ void npx_destroy_world(npx_world* w) {
   void* bufs[] = {w->st, w->step, w->flags, w->tele, w->inst_morph_d, w->morph_info,
                   w->morph_mass, w->pts, w->pt_link, w->pt_orig, w->links, w->link_parent,
                   w->link_depth, w->ctrl, w->hf, w->order, w->queue, w->lp_off,
-                  w->lp_idx, w->sub_mask, w->rays, w->ray_link, w->ray_info};
+                  w->lp_idx, w->sub_mask, w->rays, w->ray_link, w->ray_info,
+                  w->foot_link, w->foot_info};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete w;
@@ -734,6 +739,77 @@ npx_status npx_world_set_rays(npx_world* w, int32_t morph, int32_t n_rays, const
   }
   HIP_TRY(hipMemcpy(w->ray_info, info.data(), info.size() * sizeof(int2), hipMemcpyHostToDevice));
   w->ray_max = rmax;
+  return NPX_OK;
+}
+
+namespace {
+
+// Rebuilds the device tables of the foot sensors from the host lists.
+npx_status upload_feet(npx_world* w) {
+  w->foot_host.resize(w->n_morphs);
+  std::vector<int> links;
+  std::vector<int2> info(w->n_morphs);
+  for (int m = 0; m < w->n_morphs; ++m) {
+    info[m] = make_int2((int)links.size(), (int)w->foot_host[m].size());
+    links.insert(links.end(), w->foot_host[m].begin(), w->foot_host[m].end());
+  }
+  HIP_TRY(hipDeviceSynchronize());
+  if (w->foot_link) (void)hipFree(w->foot_link);
+  if (w->foot_info) (void)hipFree(w->foot_info);
+  w->foot_link = nullptr;
+  w->foot_info = nullptr;
+  if (hipMalloc((void**)&w->foot_link, std::max<size_t>(links.size(), 1) * sizeof(int)) !=
+          hipSuccess ||
+      hipMalloc((void**)&w->foot_info, info.size() * sizeof(int2)) != hipSuccess)
+    return fail(NPX_ENOMEM, "sensor tables");
+  if (!links.empty())
+    HIP_TRY(hipMemcpy(w->foot_link, links.data(), links.size() * sizeof(int),
+                      hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(w->foot_info, info.data(), info.size() * sizeof(int2), hipMemcpyHostToDevice));
+  return NPX_OK;
+}
+
+}  // namespace
+
+npx_status npx_world_set_sensors(npx_world* w, int32_t morph, int32_t n, const int32_t* links) {
+  if (!w) return fail(NPX_EINVAL, "null world");
+  if (morph < 0 || morph >= w->n_morphs) return fail(NPX_EINVAL, "morph %d out of range", morph);
+  if (n < 0 || n > npx::FOOT_MAX) return fail(NPX_EINVAL, "n %d out of [0, %d]", n, npx::FOOT_MAX);
+  if (n > 0 && !links) return fail(NPX_EINVAL, "null sensor list");
+  for (int k = 0; k < n; ++k)
+    if (links[k] < 0 || links[k] >= w->morph_links[morph])
+      return fail(NPX_EINVAL, "sensor %d: link %d out of [0, %d)", k, links[k],
+                  w->morph_links[morph]);
+  npx_status st = sync_last(w);
+  if (st != NPX_OK) return st;
+  w->foot_host.resize(w->n_morphs);
+  w->foot_host[morph].assign(links, links + n);
+  return upload_feet(w);
+}
+
+npx_status npx_gp_run(npx_world* w, const uint8_t* programs, int32_t* vm, float* targets,
+                      int64_t ld_targets, int32_t n_updates, int32_t n_instr, float motor_step,
+                      void* hip_stream) {
+  if (!w || !programs || !vm || !targets) return fail(NPX_EINVAL, "null argument");
+  if (ld_targets < w->j_max)
+    return fail(NPX_EINVAL, "ld_targets %lld below J_max %d", (long long)ld_targets, w->j_max);
+  if (n_updates < 0 || n_instr < 0 || n_instr > 4096)
+    return fail(NPX_EINVAL, "n_updates must be >= 0 and n_instr in [0, 4096]");
+  if (!(motor_step >= 0.f) || std::isinf(motor_step))
+    return fail(NPX_EINVAL, "motor_step must be finite and >= 0");
+  if (!w->foot_info) {
+    npx_status st = upload_feet(w);
+    if (st != NPX_OK) return st;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  const npx::GpArgs g{programs, vm, targets, ld_targets, w->foot_link, w->foot_info, n_instr,
+                      motor_step, w->ctrl};
+  for (int u = 0; u < n_updates; ++u) {
+    HIP_TRY(npx::launch_gp(npx::world_view(w), g, st));
+    npx_status r = run_steps(w, w->K, st);
+    if (r != NPX_OK) return r;
+  }
+  npx::note_stream(w, st);
   return NPX_OK;
 }
 

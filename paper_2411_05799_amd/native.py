@@ -127,6 +127,10 @@ def lib():
         L.npx_world_set_rays.restype = C.c_int
         L.npx_world_ray_ranges.argtypes = [vp, vp, C.c_int64, vp]
         L.npx_world_ray_ranges.restype = C.c_int
+        L.npx_world_set_sensors.argtypes = [vp, C.c_int32, C.c_int32, vp]
+        L.npx_world_set_sensors.restype = C.c_int
+        L.npx_gp_run.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int32, C.c_int32, C.c_float, vp]
+        L.npx_gp_run.restype = C.c_int
         for name in ("npx_morph_new", "npx_simplify_mode", "npx_create_point", "npx_create_box",
                      "npx_create_cylinder", "npx_create_sphere", "npx_create_ray",
                      "npx_connect_bodies", "npx_create_joint", "npx_set_joint_limits",
@@ -375,6 +379,20 @@ class World:
         check(lib().npx_world_ray_ranges(self.h, _ptr(out), out.stride(0),
                                          C.c_void_p(_stream_handle(stream))))
         return out
+
+    def set_sensors(self, morph, links):
+        """Foot contact sensors of morphology `morph`: the link of each."""
+        k = np.ascontiguousarray(links, dtype=np.int32).reshape(-1)
+        check(lib().npx_world_set_sensors(self.h, int(morph), int(k.shape[0]),
+                                          k.ctypes.data_as(C.c_void_p)))
+
+    def gp_run(self, programs, vm, targets, n_updates, n_instr, motor_step, stream=None):
+        """Machine-code programs (device uint8 [I, 32]) driving the robots for
+        n_updates joint updates; vm (int32 [I, 2]) and targets (float32 [I, >= J_max])
+        are device tensors carried between calls."""
+        check(lib().npx_gp_run(self.h, _ptr(programs), _ptr(vm), _ptr(targets), targets.stride(0),
+                               int(n_updates), int(n_instr), float(motor_step),
+                               C.c_void_p(_stream_handle(stream))))
 
     def rows(self, out, stream=None):
         """State rows [I, >= 13 + 2 J] of every instance into a device tensor."""
