@@ -76,6 +76,16 @@ def population_workload(n: int, cfg: GpConfig) -> W.Workload:
     return servo_workload(W.hexapod_batch(n, seed=cfg.terrain_seed, spread=0.0), cfg)
 
 
+def prepare(gw, w: W.Workload) -> None:
+    """Foot sensors on the leaf links, and a step shape fixed by the population
+    size (so that a kept program is re-evaluated bit for bit): with 8-frame
+    launches, 64 lanes per robot below 1,024 robots (one generation of 100:
+    86 ms against 104 ms at 32), 32 lanes from there on (4,096: 136 ms against
+    164 ms)."""
+    gw.set_sensors(0, foot_links(w.morphs[0]))
+    gw.set_launch(lanes_per_instance=64 if w.n_instances < 1024 else 32)
+
+
 def evaluate(programs: np.ndarray, cfg: GpConfig, stream=None) -> np.ndarray:
     """Fitness of every program: +x distance of the CoG after cfg.seconds."""
     import torch
@@ -83,7 +93,7 @@ def evaluate(programs: np.ndarray, cfg: GpConfig, stream=None) -> np.ndarray:
     w = population_workload(n, cfg)
     updates = int(round(cfg.seconds / (cfg.dt * cfg.K)))
     with N.World(w) as gw:
-        gw.set_sensors(0, foot_links(w.morphs[0]))
+        prepare(gw, w)
         x0 = gw.read_state(N.F_COG)[0].astype(np.float64)
         prog = torch.as_tensor(programs, device="cuda")
         vm = torch.zeros((n, 2), dtype=torch.int32, device="cuda")
