@@ -210,6 +210,10 @@ __global__ __launch_bounds__(64) void gp_kernel(WorldView v, GpArgs g) {
   }
   const unsigned long long sense = __ballot(touch);
 
+  // the program, targets and limits staged in LDS: the serial interpreter
+  // below then waits on no global load
+  __shared__ unsigned char prog[GP_BYTES];
+  if (l < GP_BYTES) prog[l] = g.prog[(int64_t)i * GP_BYTES + l];
   if (l < J) {
     tgt[l] = g.targets[(int64_t)i * g.ld_targets + l];
     const float* lk = v.a.links + (int64_t)(lk0 + l + 1) * LINK_F;
@@ -218,7 +222,6 @@ __global__ __launch_bounds__(64) void gp_kernel(WorldView v, GpArgs g) {
   }
   __syncthreads();
   if (l == 0) {
-    const uint8_t* prog = g.prog + (int64_t)i * GP_BYTES;
     int pc = g.vm[2 * (int64_t)i] & (GP_BYTES - 1);
     unsigned acc = (unsigned)g.vm[2 * (int64_t)i + 1] & 0xFFu;
     for (int e = 0; e < g.n_instr; ++e) {
