@@ -190,6 +190,10 @@ npx_status npx_world_dims(const npx_world* w, int64_t* n_instances, int32_t* j_m
  * is commanded A sin(2 pi f t + phi) rad at t = n dt, clamped to its limits.
  * n_floats must equal n_instances * J_max * 3. */
 #define NPX_CTRL_SINUSOID 0
+/* kind NPX_CTRL_TARGETS: params [n_instances][J_max] = joint target angles
+ * (rad), commanded from the next joint update on, clamped to the limits (held
+ * as the sinusoid rows (target, 0, pi/2)). n_floats = n_instances * J_max. */
+#define NPX_CTRL_TARGETS 1
 npx_status npx_set_controller(npx_world* w, int kind, const float* params, size_t n_floats,
                               int params_on_device);
 

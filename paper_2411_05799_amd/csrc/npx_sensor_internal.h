@@ -36,4 +36,10 @@ struct GpArgs {
 // One joint update of the machine-code controller of every instance.
 hipError_t launch_gp(const WorldView& v, const GpArgs& g, hipStream_t stream);
 
+// A joint target as a sinusoid row: A = target, f = 0, phi = pi/2 (the step's
+// command A sin(2 pi f t + phi) is then the target itself).
+constexpr float HALF_PI_F = 1.57079637f;
+// ctrl[3k..3k+2] = (targets[k], 0, pi/2) for k < n.
+hipError_t launch_targets(const float* targets, float* ctrl, int64_t n, hipStream_t stream);
+
 }  // namespace npx

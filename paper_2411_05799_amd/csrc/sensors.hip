@@ -266,11 +266,26 @@ __global__ __launch_bounds__(64) void gp_kernel(WorldView v, GpArgs g) {
     float* cr = g.ctrl + ((int64_t)i * v.a.j_max + l) * 3;
     cr[0] = tgt[l];
     cr[1] = 0.f;
-    cr[2] = 1.57079637f;  // pi/2: a constant command A sin(pi/2) = A
+    cr[2] = HALF_PI_F;  // a constant command A sin(pi/2) = A
   }
 }
 
+__global__ void targets_kernel(const float* t, float* ctrl, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  ctrl[3 * k] = t[k];
+  ctrl[3 * k + 1] = 0.f;
+  ctrl[3 * k + 2] = HALF_PI_F;
+}
+
 }  // namespace
+
+hipError_t launch_targets(const float* targets, float* ctrl, int64_t n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(targets_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                     targets, ctrl, n);
+  return hipGetLastError();
+}
 
 hipError_t launch_ray_ranges(const WorldView& v, const RayTables& r, float* dst, int64_t ld,
                              hipStream_t stream) {

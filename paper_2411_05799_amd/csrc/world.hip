@@ -598,6 +598,25 @@ npx_status npx_world_dims(const npx_world* w, int64_t* n_instances, int32_t* j_m
 npx_status npx_set_controller(npx_world* w, int kind, const float* params, size_t n_floats,
                               int on_device) {
   if (!w || !params) return fail(NPX_EINVAL, "null argument");
+  if (kind == NPX_CTRL_TARGETS) {
+    const size_t nt = (size_t)w->n_inst * w->j_max;
+    if (n_floats != nt) return fail(NPX_EINVAL, "targets need %zu floats, got %zu", nt, n_floats);
+    npx_status s = sync_last(w);
+    if (s != NPX_OK) return s;
+    if (on_device) {
+      HIP_TRY(npx::launch_targets(params, w->ctrl, (int64_t)nt, nullptr));
+      HIP_TRY(hipDeviceSynchronize());
+    } else {
+      std::vector<float> rows(3 * nt);
+      for (size_t k = 0; k < nt; ++k) {
+        rows[3 * k] = params[k];
+        rows[3 * k + 1] = 0.f;
+        rows[3 * k + 2] = npx::HALF_PI_F;
+      }
+      HIP_TRY(hipMemcpy(w->ctrl, rows.data(), rows.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    return NPX_OK;
+  }
   if (kind != NPX_CTRL_SINUSOID) return fail(NPX_EUNSUPPORTED, "controller kind %d", kind);
   const size_t need = (size_t)w->n_inst * w->j_max * 3;
   if (n_floats != need) return fail(NPX_EINVAL, "controller needs %zu floats, got %zu", need, n_floats);

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(PKG, "libnpx.so")
 NPX_OK = 0
 F_COG, F_QUAT, F_VEL, F_OMEGA, F_JOINT, F_JOINT_PREV, F_STEP, F_FLAGS, F_TELE, F_BODY = range(10)
 CTRL_SINUSOID = 0
+CTRL_TARGETS = 1
 TELE_N = 4
 
 
@@ -271,6 +272,19 @@ class World:
             return
         arr = pack_ctrl(ctrl, self.j_max) if isinstance(ctrl, list) else _f32(ctrl)
         check(lib().npx_set_controller(self.h, CTRL_SINUSOID, arr.ctypes.data_as(C.c_void_p),
+                                       arr.size, 0))
+
+    def set_targets(self, targets):
+        """Joint target angles [I, J_max] (numpy or a torch device tensor),
+        commanded from the next joint update on."""
+        if hasattr(targets, "data_ptr"):
+            if not targets.is_contiguous():
+                raise ValueError("targets must be contiguous")
+            check(lib().npx_set_controller(self.h, CTRL_TARGETS, C.c_void_p(targets.data_ptr()),
+                                           targets.numel(), 1))
+            return
+        arr = _f32(targets)
+        check(lib().npx_set_controller(self.h, CTRL_TARGETS, arr.ctypes.data_as(C.c_void_p),
                                        arr.size, 0))
 
     def step_n(self, n, stream=None):

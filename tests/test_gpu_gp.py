@@ -164,3 +164,35 @@ def test_evolution_keeps_its_best_and_refuses_bad_calls():
         torch.cuda.synchronize()
         assert np.allclose(tg[:, 0].cpu().numpy(), np.float32(0.05))
         assert np.all(vm.cpu().numpy()[:, 0] == 0)
+
+
+def test_targets_controller_kind():
+    """npx_set_controller with joint targets: after the next joint update the
+    joints sit exactly at the targets held within their limits, from host and
+    device targets alike, and the trajectory equals the one driven by the
+    equivalent sinusoid rows (target, 0, pi/2) bit for bit."""
+    say("case: controller kind targets")
+    import math
+    import torch
+    w = _world(8, seed=2)
+    m = w.morphs[0]
+    lo, hi = _limits(m)
+    rng = np.random.default_rng(6)
+    with N.World(w) as ga, N.World(w) as gb, N.World(w) as gc:
+        J = ga.j_max
+        t = rng.uniform(-1.0, 1.0, (8, J)).astype(np.float32)
+        ga.set_targets(t)
+        gb.set_targets(torch.as_tensor(t, device="cuda"))
+        rows = np.stack([t, np.zeros_like(t), np.full_like(t, np.float32(math.pi / 2))], axis=-1)
+        gc.set_controller(rows)
+        for g in (ga, gb, gc):
+            g.step_n(1)
+        want = np.clip(t, lo[None, :J], hi[None, :J]).T
+        for g in (ga, gb, gc):
+            assert np.array_equal(g.read_state(N.F_JOINT), want)
+        for g in (ga, gb, gc):
+            g.step_n(49)
+        body = [g.read_state(N.F_BODY) for g in (ga, gb, gc)]
+        assert np.array_equal(body[0], body[1]) and np.array_equal(body[0], body[2])
+        with pytest.raises(N.NpxError):
+            ga.set_targets(t[:, :-1])
