@@ -26,8 +26,8 @@ struct GpArgs {
   int* vm;                // [n_inst][2] program counter, accumulator
   float* targets;         // [n_inst][ld_targets] joint targets
   int64_t ld_targets;
-  const int* foot_link;   // [total sensors] link of each foot sensor in its morphology
-  const int2* foot_info;  // [n_morphs] first sensor, sensor count
+  const int4* foot_pairs; // [total pairs] sensor, point (global index), link in its morphology
+  const int4* foot_info;  // [n_morphs] first pair, pair count, sensor count
   int n_instr;            // instructions per joint update
   float step;             // motor step, rad
   float* ctrl;            // the world's controller [n_inst][j_max][3]

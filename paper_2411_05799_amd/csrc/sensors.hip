@@ -189,26 +189,27 @@ __global__ __launch_bounds__(64) void gp_kernel(WorldView v, GpArgs g) {
   float gb[3], c[3], R[9];
   robot_frame(v, i, mo, T, gb, c, R);
 
-  // sensor s (lane s): any point of its foot link strictly below its cell
-  const int2 fi = g.foot_info[mo];
-  bool touch = false;
-  if (l < fi.y) {
-    const int link = g.foot_link[fi.x + l];
-    const int p1 = v.lp_off[lk0 + link + 1];
-    for (int p = v.lp_off[lk0 + link]; p < p1; ++p) {
-      const float4 rho = v.a.pts[v.lp_idx[p]];
-      const float pr[3] = {rho.x, rho.y, rho.z};
-      float P[3];
-      to_world(T, link, pr, gb, c, R, P);
-      const float h = v.a.hf_bilinear
-                          ? hf_bilinear(v.a.hf, v.a.hf_nx, v.a.hf_ny, v.a.hf_x0, v.a.hf_y0, v.a.hf_s,
-                                        P[0], P[1])
-                          : hf_lookup(v.a.hf, v.a.hf_nx, v.a.hf_ny, v.a.hf_x0, v.a.hf_y0, v.a.hf_s,
-                                      P[0], P[1]);
-      touch |= h - P[2] > 0.f;
-    }
+  // sensor s: any point of its foot link strictly below its cell. The lanes
+  // take the morphology's (sensor, point) pairs, 64 at a time, and OR their
+  // sensors' bits together.
+  const int4 fi = g.foot_info[mo];
+  unsigned bits = 0u;
+  for (int q = l; q < fi.y; q += 64) {
+    const int4 pr = g.foot_pairs[fi.x + q];
+    const float4 rho = v.a.pts[pr.y];
+    const float pp[3] = {rho.x, rho.y, rho.z};
+    float P[3];
+    to_world(T, pr.z, pp, gb, c, R, P);
+    const float h = v.a.hf_bilinear
+                        ? hf_bilinear(v.a.hf, v.a.hf_nx, v.a.hf_ny, v.a.hf_x0, v.a.hf_y0, v.a.hf_s,
+                                      P[0], P[1])
+                        : hf_lookup(v.a.hf, v.a.hf_nx, v.a.hf_ny, v.a.hf_x0, v.a.hf_y0, v.a.hf_s,
+                                    P[0], P[1]);
+    if (h - P[2] > 0.f) bits |= 1u << pr.x;
   }
-  const unsigned long long sense = __ballot(touch);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) bits |= (unsigned)__shfl_xor((int)bits, o);
+  const unsigned long long sense = bits;
 
   // the program, targets and limits staged in LDS: the serial interpreter
   // below then waits on no global load
@@ -237,7 +238,7 @@ __global__ __launch_bounds__(64) void gp_kernel(WorldView v, GpArgs g) {
           }
           break;
         case 2:  // read sensor
-          acc = (int)arg < fi.y ? (unsigned)((sense >> arg) & 1ull) : 0u;
+          acc = (int)arg < fi.z ? (unsigned)((sense >> arg) & 1ull) : 0u;
           break;
         case 3:  // load
           acc = arg;

@@ -91,8 +91,10 @@ struct npx_world {
   int ray_max = 0;
   // foot contact sensors of the machine-code controller, per morphology
   std::vector<std::vector<int>> foot_host;
-  int* foot_link = nullptr;
-  int2* foot_info = nullptr;
+  std::vector<int> lp_off_host, lp_idx_host;  // host copies of lp_off / lp_idx
+  int4* foot_pairs = nullptr;  // (sensor, point, link, 0) of every sensed point
+  int4* foot_info = nullptr;   // per morphology: first pair, pair count, sensor count
+
 
   npx::StepArgs args{};
   npx_launch launch{64, 0, 100, 1, 8};
@@ -476,6 +478,8 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   H2D(w->link_depth, dep.data(), dep.size() * sizeof(int));
   H2D(w->lp_off, lpo.data(), lpo.size() * sizeof(int));
   H2D(w->lp_idx, lpi.data(), lpi.size() * sizeof(int));
+  w->lp_off_host = lpo;
+  w->lp_idx_host = lpi;
   H2D(w->sub_mask, subm.data(), subm.size() * sizeof(unsigned long long));
   H2D(w->hf, d->hf_heights, (size_t)d->hf_nx * d->hf_ny * sizeof(float));
   std::vector<int> ord = task_order(w);
@@ -581,7 +585,7 @@ void npx_destroy_world(npx_world* w) {
                   w->morph_mass, w->pts, w->pt_link, w->pt_orig, w->links, w->link_parent,
                   w->link_depth, w->ctrl, w->hf, w->order, w->queue, w->lp_off,
                   w->lp_idx, w->sub_mask, w->rays, w->ray_link, w->ray_info,
-                  w->foot_link, w->foot_info};
+                  w->foot_pairs, w->foot_info};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete w;
@@ -763,28 +767,38 @@ npx_status npx_world_set_rays(npx_world* w, int32_t morph, int32_t n_rays, const
 
 namespace {
 
-// Rebuilds the device tables of the foot sensors from the host lists.
+// Rebuilds the device tables of the foot sensors from the host lists: every
+// (sensor, point) pair of a morphology, so that the lanes of the controller
+// kernel take the sensed points in parallel.
 npx_status upload_feet(npx_world* w) {
   w->foot_host.resize(w->n_morphs);
-  std::vector<int> links;
-  std::vector<int2> info(w->n_morphs);
+  std::vector<int4> pairs;
+  std::vector<int4> info(w->n_morphs);
+  int lk0 = 0;
   for (int m = 0; m < w->n_morphs; ++m) {
-    info[m] = make_int2((int)links.size(), (int)w->foot_host[m].size());
-    links.insert(links.end(), w->foot_host[m].begin(), w->foot_host[m].end());
+    const int first = (int)pairs.size();
+    const std::vector<int>& feet = w->foot_host[m];
+    for (int sidx = 0; sidx < (int)feet.size(); ++sidx) {
+      const int gl = lk0 + feet[sidx];
+      for (int p = w->lp_off_host[gl]; p < w->lp_off_host[gl + 1]; ++p)
+        pairs.push_back(make_int4(sidx, w->lp_idx_host[p], feet[sidx], 0));
+    }
+    info[m] = make_int4(first, (int)pairs.size() - first, (int)feet.size(), 0);
+    lk0 += w->morph_links[m];
   }
   HIP_TRY(hipDeviceSynchronize());
-  if (w->foot_link) (void)hipFree(w->foot_link);
+  if (w->foot_pairs) (void)hipFree(w->foot_pairs);
   if (w->foot_info) (void)hipFree(w->foot_info);
-  w->foot_link = nullptr;
+  w->foot_pairs = nullptr;
   w->foot_info = nullptr;
-  if (hipMalloc((void**)&w->foot_link, std::max<size_t>(links.size(), 1) * sizeof(int)) !=
+  if (hipMalloc((void**)&w->foot_pairs, std::max<size_t>(pairs.size(), 1) * sizeof(int4)) !=
           hipSuccess ||
-      hipMalloc((void**)&w->foot_info, info.size() * sizeof(int2)) != hipSuccess)
+      hipMalloc((void**)&w->foot_info, info.size() * sizeof(int4)) != hipSuccess)
     return fail(NPX_ENOMEM, "sensor tables");
-  if (!links.empty())
-    HIP_TRY(hipMemcpy(w->foot_link, links.data(), links.size() * sizeof(int),
+  if (!pairs.empty())
+    HIP_TRY(hipMemcpy(w->foot_pairs, pairs.data(), pairs.size() * sizeof(int4),
                       hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(w->foot_info, info.data(), info.size() * sizeof(int2), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(w->foot_info, info.data(), info.size() * sizeof(int4), hipMemcpyHostToDevice));
   return NPX_OK;
 }
 
@@ -821,7 +835,7 @@ npx_status npx_gp_run(npx_world* w, const uint8_t* programs, int32_t* vm, float*
     if (st != NPX_OK) return st;
   }
   hipStream_t st = (hipStream_t)hip_stream;
-  const npx::GpArgs g{programs, vm, targets, ld_targets, w->foot_link, w->foot_info, n_instr,
+  const npx::GpArgs g{programs, vm, targets, ld_targets, w->foot_pairs, w->foot_info, n_instr,
                       motor_step, w->ctrl};
   for (int u = 0; u < n_updates; ++u) {
     HIP_TRY(npx::launch_gp(npx::world_view(w), g, st));
