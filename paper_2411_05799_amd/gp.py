@@ -80,7 +80,7 @@ def prepare(gw, w: W.Workload) -> None:
     """Foot sensors on the leaf links, and a step shape fixed by the population
     size (so that a kept program is re-evaluated bit for bit): with 8-frame
     launches, 64 lanes per robot below 1,024 robots (one generation of 100:
-    86 ms against 104 ms at 32), 32 lanes from there on (4,096: 136 ms against
+    80 ms against 104 ms at 32), 32 lanes from there on (4,096: 124 ms against
     164 ms)."""
     gw.set_sensors(0, foot_links(w.morphs[0]))
     gw.set_launch(lanes_per_instance=64 if w.n_instances < 1024 else 32)
