@@ -103,6 +103,11 @@ struct npx_world {
   bool has_last_stream = false;
   hipStream_t capture_stream = nullptr;
   std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+  // a block of controller updates (controller kernel + K frames, repeated),
+  // captured once for one set of controller arguments
+  hipGraph_t gp_graph = nullptr;
+  hipGraphExec_t gp_exec = nullptr;
+  npx::GpArgs gp_key{};
   int cu_count = 256;
 
   void drop_graphs() {
@@ -111,6 +116,10 @@ struct npx_world {
       (void)hipGraphDestroy(kv.second.first);
     }
     graphs.clear();
+    if (gp_exec) (void)hipGraphExecDestroy(gp_exec);
+    if (gp_graph) (void)hipGraphDestroy(gp_graph);
+    gp_exec = nullptr;
+    gp_graph = nullptr;
   }
 };
 
@@ -787,6 +796,7 @@ npx_status upload_feet(npx_world* w) {
     lk0 += w->morph_links[m];
   }
   HIP_TRY(hipDeviceSynchronize());
+  w->drop_graphs();  // captured controller launches hold the old table pointers
   if (w->foot_pairs) (void)hipFree(w->foot_pairs);
   if (w->foot_info) (void)hipFree(w->foot_info);
   w->foot_pairs = nullptr;
@@ -837,11 +847,53 @@ npx_status npx_gp_run(npx_world* w, const uint8_t* programs, int32_t* vm, float*
   hipStream_t st = (hipStream_t)hip_stream;
   const npx::GpArgs g{programs, vm, targets, ld_targets, w->foot_pairs, w->foot_info, n_instr,
                       motor_step, w->ctrl};
-  for (int u = 0; u < n_updates; ++u) {
+  // Whole blocks of updates replay one captured graph (the launches of a
+  // block, back to back, without a host round per launch); the rest, and
+  // every update when graphs are off, are launched one by one.
+  constexpr int GP_BLOCK = 25;
+  int u = 0;
+  if (w->launch.use_graph && n_updates >= GP_BLOCK) {
+    const npx::GpArgs& k = w->gp_key;
+    const bool same = w->gp_exec && k.prog == g.prog && k.vm == g.vm && k.targets == g.targets &&
+                      k.ld_targets == g.ld_targets && k.foot_pairs == g.foot_pairs &&
+                      k.foot_info == g.foot_info && k.n_instr == g.n_instr &&
+                      k.step == g.step && k.ctrl == g.ctrl;
+    if (!same) {
+      if (w->gp_exec) (void)hipGraphExecDestroy(w->gp_exec);
+      if (w->gp_graph) (void)hipGraphDestroy(w->gp_graph);
+      w->gp_exec = nullptr;
+      w->gp_graph = nullptr;
+      HIP_TRY(hipStreamBeginCapture(w->capture_stream, hipStreamCaptureModeThreadLocal));
+      hipError_t e = hipSuccess;
+      const npx::WorldView v = npx::world_view(w);
+      const int chunk = std::max(1, w->launch.chunk_steps);
+      for (int b = 0; b < GP_BLOCK && e == hipSuccess; ++b) {
+        e = npx::launch_gp(v, g, w->capture_stream);
+        for (int left = w->K; left > 0 && e == hipSuccess; left -= chunk)
+          e = enqueue_chunk(w, std::min(left, chunk), w->capture_stream);
+      }
+      hipGraph_t gr = nullptr;
+      hipError_t e2 = hipStreamEndCapture(w->capture_stream, &gr);
+      if (e != hipSuccess) return fail(NPX_EHIP, "capture of controller updates: %s", hipGetErrorString(e));
+      if (e2 != hipSuccess) return fail(NPX_EHIP, "end capture: %s", hipGetErrorString(e2));
+      hipGraphExec_t ge = nullptr;
+      if (hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(gr);
+        return fail(NPX_EHIP, "instantiating the controller updates failed");
+      }
+      w->gp_graph = gr;
+      w->gp_exec = ge;
+      w->gp_key = g;
+    }
+    for (; u + GP_BLOCK <= n_updates; u += GP_BLOCK) HIP_TRY(hipGraphLaunch(w->gp_exec, st));
+  }
+  for (; u < n_updates; ++u) {
     HIP_TRY(npx::launch_gp(npx::world_view(w), g, st));
     npx_status r = run_steps(w, w->K, st);
     if (r != NPX_OK) return r;
   }
+  w->last_stream = st;
+  w->has_last_stream = true;
   npx::note_stream(w, st);
   return NPX_OK;
 }

@@ -196,3 +196,31 @@ def test_targets_controller_kind():
         assert np.array_equal(body[0], body[1]) and np.array_equal(body[0], body[2])
         with pytest.raises(N.NpxError):
             ga.set_targets(t[:, :-1])
+
+
+def test_graph_blocks_equal_single_launches():
+    """Updates replayed from captured blocks of 25 equal updates launched one by
+    one, bit for bit (60 updates: two blocks and a remainder), also after the
+    controller's buffers and the sensor tables change (fresh capture)."""
+    say("case: gp / captured update blocks")
+    import torch
+    n = 24
+    w = _world(n, seed=21)
+    feet = GP.foot_links(w.morphs[0])
+    progs = torch.as_tensor(GP.random_programs(n, np.random.default_rng(8)), device="cuda")
+    out = []
+    for graph in (1, 0):
+        with N.World(w) as gw:
+            gw.set_sensors(0, feet)
+            gw.set_launch(use_graph=graph)
+            res = []
+            for rep in range(2):
+                vm = torch.zeros((n, 2), dtype=torch.int32, device="cuda")
+                tg = torch.zeros((n, gw.j_max), dtype=torch.float32, device="cuda")
+                gw.gp_run(progs, vm, tg, 60, 16, 0.05)
+                torch.cuda.synchronize()
+                res += [vm.cpu().numpy(), tg.cpu().numpy(), gw.read_state(N.F_BODY)]
+                gw.set_sensors(0, feet[:3])
+            out.append(res)
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
