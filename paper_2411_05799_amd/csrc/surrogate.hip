@@ -181,25 +181,29 @@ __global__ __launch_bounds__(256) void delta_kernel(WorldView v, const float* s0
   }
 }
 
-// ---- network inputs: one wave per instance, lanes over the features ---------
+// ---- network inputs: a segment of lanes per instance, lanes over the features
 // Values shared by the instance's features (heading, body entries in the
 // heading frame, ground height under the CoG) are computed once per wave;
 // each lane then writes its columns. STD: write the standardised value
 // (x - mean) * inv_std as OUT (the network's own input rows), zero in the
 // padding columns [nf, width) and in whole rows of instances past n_inst
 // below `rows`; otherwise the raw feature as float.
+// 16 lanes per instance (four per wave), for the same reason as the rollout
+// update below: the per-instance values are computed once per segment, so
+// narrow segments share each wave's instruction stream among more instances.
+constexpr int FEAT_G = 16, FEAT_IPB = 256 / FEAT_G;
 template <class OUT, bool STD>
 __global__ __launch_bounds__(256) void features_kernel(WorldView v, const float* s, int64_t lds,
                                                        int64_t frame, OUT* x, int64_t ldx,
                                                        int width, int rows, const float* mean,
                                                        const float* inv_std) {
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & (FEAT_G - 1);
+  const int i = blockIdx.x * FEAT_IPB + threadIdx.x / FEAT_G;
   const int J = v.a.j_max;
   const int nf = feature_width(J);
   if (i >= v.a.n_inst) {
     if (STD && i < rows)
-      for (int f = lane; f < width; f += 64) x[(int64_t)i * ldx + f] = static_cast<OUT>(0.f);
+      for (int f = lane; f < width; f += FEAT_G) x[(int64_t)i * ldx + f] = static_cast<OUT>(0.f);
     return;
   }
   const int4 mi = v.a.morph_info[v.a.inst_morph[i]];
@@ -225,7 +229,7 @@ __global__ __launch_bounds__(256) void features_kernel(WorldView v, const float*
   // targets of frames n .. n+9 (joint j of frame n + k at 13 + 2J + kJ + j);
   // the height patch and the padding.
   const int c_cmd = 13 + 2 * J, c_patch = 13 + 12 * J;
-  for (int f = lane; f < c_cmd; f += 64) {
+  for (int f = lane; f < c_cmd; f += FEAT_G) {
     float val = 0.f;
     if (f < 13) {
 #pragma unroll
@@ -240,11 +244,11 @@ __global__ __launch_bounds__(256) void features_kernel(WorldView v, const float*
     put(f, val);
   }
   {
-    // (k, j) of column c_cmd + lane, then stepped by 64 columns per pass
+    // (k, j) of column c_cmd + lane, then stepped by FEAT_G columns per pass
     // without a division in the loop
     int k = lane / J, j = lane - (lane / J) * J;
-    const int dk = 64 / J, dj = 64 - (64 / J) * J;
-    for (int f = c_cmd + lane; f < c_patch; f += 64) {
+    const int dk = FEAT_G / J, dj = FEAT_G - (FEAT_G / J) * J;
+    for (int f = c_cmd + lane; f < c_patch; f += FEAT_G) {
       put(f, j < Ji ? command(v, i, mi.z, j, n + k) : 0.f);
       k += dk;
       j += dj;
@@ -254,7 +258,7 @@ __global__ __launch_bounds__(256) void features_kernel(WorldView v, const float*
       }
     }
   }
-  for (int f = c_patch + lane; f < width; f += 64) {
+  for (int f = c_patch + lane; f < width; f += FEAT_G) {
     float val = 0.f;
     if (f < nf) {
       const int idx = f - c_patch;
@@ -268,15 +272,19 @@ __global__ __launch_bounds__(256) void features_kernel(WorldView v, const float*
   }
 }
 
-// ---- rollout update: one wave per instance, lanes over the columns ----------
+// ---- rollout update: a segment of lanes per instance, lanes over the columns
 // The body rows gain dy turned back from the heading frame of s (Q renormalised);
 // q and q_prev become what the step sets after frames n .. n+9 with joints
 // re-determined every frame.
+// 16 lanes per instance (four per wave): the per-instance body update is the
+// same few hundred instructions whatever the segment width, so narrow
+// segments share each wave's instruction stream among four instances.
+constexpr int ADV_G = 16;
 __global__ __launch_bounds__(256) void advance_kernel(WorldView v, float* s, int64_t lds,
                                                       const float* dy, int64_t lddy,
                                                       int64_t frame) {
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & (ADV_G - 1);
+  const int i = blockIdx.x * (256 / ADV_G) + threadIdx.x / ADV_G;
   if (i >= v.a.n_inst) return;
   float* r = s + (int64_t)i * lds;
   const float* d = dy + (int64_t)i * lddy;
@@ -293,7 +301,7 @@ __global__ __launch_bounds__(256) void advance_kernel(WorldView v, float* s, int
   const int J = v.a.j_max;
   const int4 mi = v.a.morph_info[v.a.inst_morph[i]];
   const int Ji = mi.w - 1;
-  for (int c = lane; c < 13 + 2 * J; c += 64) {
+  for (int c = lane; c < 13 + 2 * J; c += ADV_G) {
     float val = 0.f;
     if (c < 13) {
 #pragma unroll
@@ -600,7 +608,8 @@ npx_status npx_sur_features(npx_world* w, const float* s, int64_t lds, int64_t f
   if (s && lds < state_width(v.a.j_max)) return fail(NPX_EINVAL, "state stride too small");
   if (s && frame < 0) return fail(NPX_EINVAL, "state rows need a frame >= 0");
   hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL((features_kernel<float, false>), dim3((unsigned)((v.a.n_inst + 3) / 4)),
+  hipLaunchKernelGGL((features_kernel<float, false>),
+                     dim3((unsigned)((v.a.n_inst + FEAT_IPB - 1) / FEAT_IPB)),
                      dim3(256), 0, st, v, s, lds, s ? frame : (int64_t)-1, x, ldx,
                      feature_width(v.a.j_max), 0, nullptr, nullptr);
   HIP_TRY(hipGetLastError());
@@ -633,8 +642,8 @@ npx_status npx_sur_advance(npx_world* w, float* s, int64_t lds, const float* dy,
     return fail(NPX_EINVAL, "bad buffers, strides or frame");
   if (v.a.K != 1) return fail(NPX_EUNSUPPORTED, "the rollout update assumes joints set every frame");
   hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL(advance_kernel, dim3((unsigned)((v.a.n_inst + 3) / 4)), dim3(256), 0, st, v,
-                     s, lds, dy, lddy, frame);
+  hipLaunchKernelGGL(advance_kernel, dim3((unsigned)((v.a.n_inst + 256 / ADV_G - 1) / (256 / ADV_G))),
+                     dim3(256), 0, st, v, s, lds, dy, lddy, frame);
   HIP_TRY(hipGetLastError());
   npx::note_stream(w, st);
   return NPX_OK;
@@ -684,7 +693,7 @@ npx_status npx_sur_rollout(npx_sur* net, npx_world* w, float* s, int64_t lds, in
   npx::SurInput in{};
   if ((r = npx::sur_input(net, v.a.n_inst, &in)) != NPX_OK) return r;
   hipStream_t st = (hipStream_t)stream;
-  const unsigned blocks = (unsigned)((in.rows + 3) / 4);
+  const unsigned blocks = (unsigned)((in.rows + FEAT_IPB - 1) / FEAT_IPB);
   for (int c = 0; c < n_calls; ++c) {
     const int64_t frame = frame0 + (int64_t)c * HORIZON;
     if (in.bf16)
