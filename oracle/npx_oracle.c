@@ -207,16 +207,28 @@ void orc_fk(const orc_morph* m, const double* q, double* y, double* g_b, double*
 
 /* The x-y coordinates are scaled by s and turned into integer indices of a 2-D
  * table. Reading: index = floor(s (x - x0)), clamped onto the table (a NaN
- * coordinate maps to cell 0). The index is an integer decided by floating
- * point, so it is taken in the precision of the GPU path: the coordinate,
- * origin and scale are rounded to float32 and s (x - x0) is evaluated in
- * float32. Everything else in the oracle stays double. */
+ * coordinate maps to cell 0), evaluated in double like the rest of the
+ * oracle. */
 static int cell_index(double x, double x0, double s, int n) {
-  volatile float d = (float)x - (float)x0; /* float32 subtraction, no contraction */
-  float u = d * (float)s;
-  if (!(u >= 0.0f)) return 0;
-  if (u >= (float)(n - 1)) return n - 1;
-  return (int)floorf(u);
+  double u = s * (x - x0);
+  if (!(u >= 0.0)) return 0;
+  if (u >= (double)(n - 1)) return n - 1;
+  return (int)floor(u);
+}
+
+/* The interior cell edge nearest to x along one axis (the edges between cells
+ * sit at the integers 1..n-1 of u = s (x - x0)): returns the distance to it in
+ * metres (+inf when the axis has one cell or x is NaN) and writes the cell on
+ * its other side from cell i. */
+static double nearest_edge(double x, double x0, double s, int n, int i, int* other) {
+  double u = s * (x - x0);
+  *other = i;
+  if (n < 2 || !(u == u)) return INFINITY;
+  double e = floor(u + 0.5);
+  if (e < 1.0) e = 1.0;
+  if (e > (double)(n - 1)) e = (double)(n - 1);
+  *other = (i >= (int)e) ? (int)e - 1 : (int)e;
+  return fabs(u - e) / s;
 }
 
 void orc_cell(const orc_params* p, double x, double y, int* i, int* j) {
@@ -304,6 +316,77 @@ double orc_height(const orc_params* p, double x, double y) {
 }
 
 /* ------------------------------------------------------------------------- */
+/* fragile decisions (for the parity checks; no effect on the step's result    */
+/* unless a flip is requested)                                                */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+  double margin_m, margin_rel;
+  orc_fragile* log;
+  int log_cap, n_log;
+  const orc_fragile* flips;
+  int n_flips;
+} fragile_ctx;
+
+static int is_flipped(const fragile_ctx* fc, int stage, int point, int kind) {
+  if (!fc) return 0;
+  for (int i = 0; i < fc->n_flips; ++i)
+    if (fc->flips[i].stage == stage && fc->flips[i].point == point && fc->flips[i].kind == kind)
+      return 1;
+  return 0;
+}
+
+static void note_fragile(fragile_ctx* fc, int stage, int point, int kind, double dist) {
+  if (!fc) return;
+  if (fc->n_log < fc->log_cap) {
+    orc_fragile* e = fc->log + fc->n_log;
+    e->stage = stage;
+    e->point = point;
+    e->kind = kind;
+    e->dist = dist;
+  }
+  fc->n_log++;
+}
+
+/* Depth below the ground (stored height - z) of point k seen at `stage`: the
+ * step's own look-up, with the look-ups near a cell edge that could change the
+ * point's contact or depth logged (the point is at or below the higher of the
+ * two cells) and requested flips applied. */
+static double probe_depth(const orc_params* p, fragile_ctx* fc, int stage, int k, double x,
+                          double y, double z) {
+  if (p->hf_bilinear || !fc) return orc_height(p, x, y) - z;
+  int i = cell_index(x, p->hf_x0, p->hf_s, p->hf_nx);
+  int j = cell_index(y, p->hf_y0, p->hf_s, p->hf_ny);
+  int oi, oj;
+  const double ex = nearest_edge(x, p->hf_x0, p->hf_s, p->hf_nx, i, &oi);
+  const double ey = nearest_edge(y, p->hf_y0, p->hf_s, p->hf_ny, j, &oj);
+  const long nx = p->hf_nx;
+  const double h = p->hf[(long)j * nx + i];
+  if (ex < fc->margin_m) {
+    const double hb = p->hf[(long)j * nx + oi];
+    if (hb != h && z < fmax(h, hb) + fc->margin_m) note_fragile(fc, stage, k, ORC_FK_EDGE_X, ex);
+  }
+  if (ey < fc->margin_m) {
+    const double hb = p->hf[(long)oj * nx + i];
+    if (hb != h && z < fmax(h, hb) + fc->margin_m) note_fragile(fc, stage, k, ORC_FK_EDGE_Y, ey);
+  }
+  if (is_flipped(fc, stage, k, ORC_FK_EDGE_X)) i = oi;
+  if (is_flipped(fc, stage, k, ORC_FK_EDGE_Y)) j = oj;
+  return (double)p->hf[(long)j * nx + i] - z;
+}
+
+/* The contact test "strictly below the ground" of point k at `stage`, logged
+ * when |depth| is below the margin, inverted when flipped. */
+static int probe_contact(fragile_ctx* fc, int stage, int k, double d) {
+  int kap = d > 0.0;
+  if (fc) {
+    if (fabs(d) < fc->margin_m) note_fragile(fc, stage, k, ORC_FK_CONTACT, fabs(d));
+    if (is_flipped(fc, stage, k, ORC_FK_CONTACT)) kap = !kap;
+  }
+  return kap;
+}
+
+/* ------------------------------------------------------------------------- */
 /* friction least squares (Sec. III-C, eqs. 1-6)                              */
 /* ------------------------------------------------------------------------- */
 
@@ -322,8 +405,8 @@ int orc_lsq(int n, const double* src, const double* dst, double eps, double* a) 
  * eqs. (4)-(6) gains the factor w_i; the spread test and the
  * displacement-only fallback use the weighted spread and the total weight W
  * in place of n. */
-int orc_lsq_w(int n, const double* src, const double* dst, const double* wt, double eps,
-              double* a) {
+static int lsq_core(int n, const double* src, const double* dst, const double* wt, double eps,
+                    double* a, fragile_ctx* fc) {
   a[0] = a[1] = a[2] = 0.0;
   if (n <= 0) return 0;
   double A[9] = {0}, b[3] = {0};
@@ -343,11 +426,23 @@ int orc_lsq_w(int n, const double* src, const double* dst, const double* wt, dou
   }
   if (!(W > 0.0)) return 0;
   double spread = s2 - (sx * sx + sy * sy) / W;
-  if (n >= 2 && spread > W * eps * eps && solve3(A, b, a)) return 3;
+  int full = n >= 2 && spread > W * eps * eps;
+  if (fc && n >= 2) {
+    /* the spread is a difference of sums of size s2: its rounding scales with s2 */
+    const double gap = fabs(spread - W * eps * eps), scale = W * eps * eps + s2;
+    if (gap < fc->margin_rel * scale) note_fragile(fc, ORC_FR_FIT, -1, ORC_FK_SPREAD, gap / scale);
+    if (is_flipped(fc, ORC_FR_FIT, -1, ORC_FK_SPREAD)) full = !full;
+  }
+  if (full && solve3(A, b, a)) return 3;
   a[0] = b[0] / W;
   a[1] = b[1] / W;
   a[2] = 0.0;
   return 2;
+}
+
+int orc_lsq_w(int n, const double* src, const double* dst, const double* wt, double eps,
+              double* a) {
+  return lsq_core(n, src, dst, wt, eps, a, NULL);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -355,7 +450,7 @@ int orc_lsq_w(int n, const double* src, const double* dst, const double* wt, dou
 /* ------------------------------------------------------------------------- */
 
 typedef struct {
-  double *y, *r, *P, *Ps, *src, *dst, *f, *wt;
+  double *y, *r, *P, *Ps, *src, *dst, *f, *wt, *d;
   int* kap;
 } work_t;
 
@@ -369,12 +464,13 @@ static int work_alloc(work_t* w, int N) {
   w->kap = (int*)malloc(sizeof(int) * N);
   w->f = (double*)malloc(sizeof(double) * N);
   w->wt = (double*)malloc(sizeof(double) * N);
-  return w->y && w->r && w->P && w->Ps && w->src && w->dst && w->kap;
+  w->d = (double*)malloc(sizeof(double) * N);
+  return w->y && w->r && w->P && w->Ps && w->src && w->dst && w->kap && w->f && w->wt && w->d;
 }
 
 static void work_free(work_t* w) {
   free(w->y); free(w->r); free(w->P); free(w->Ps); free(w->src); free(w->dst); free(w->kap);
-  free(w->f); free(w->wt);
+  free(w->f); free(w->wt); free(w->d);
 }
 
 static int morph_ok(const orc_morph* m) {
@@ -406,18 +502,33 @@ static int inertia_regular(const double* I) {
   return tr > 0.0 && det3(I) > 1e-9 * tr * tr * tr;
 }
 
-static double torso_height(const orc_morph* m, const orc_params* p, const double* st,
-                           const double* g_b) {
-  (void)m;
+/* Height of the torso origin c - R g_b above the stored ground under it (the
+ * look-up logged and flippable like the step's own, stage S9). */
+static double torso_height(const orc_params* p, const double* st, const double* g_b,
+                           fragile_ctx* fc) {
   double R[9], Rg[3];
   quat_to_mat(st + ORC_Q, R);
   m3_vec(R, g_b, Rg);
   double o[3] = {st[ORC_C] - Rg[0], st[ORC_C + 1] - Rg[1], st[ORC_C + 2] - Rg[2]};
-  return o[2] - orc_height(p, o[0], o[1]);
+  if (p->hf_bilinear || !fc) return o[2] - orc_height(p, o[0], o[1]);
+  int i = cell_index(o[0], p->hf_x0, p->hf_s, p->hf_nx);
+  int j = cell_index(o[1], p->hf_y0, p->hf_s, p->hf_ny);
+  int oi, oj;
+  const double ex = nearest_edge(o[0], p->hf_x0, p->hf_s, p->hf_nx, i, &oi);
+  const double ey = nearest_edge(o[1], p->hf_y0, p->hf_s, p->hf_ny, j, &oj);
+  const long nx = p->hf_nx;
+  const double h = p->hf[(long)j * nx + i];
+  if (ex < fc->margin_m && p->hf[(long)j * nx + oi] != h)
+    note_fragile(fc, ORC_FR_S9, -1, ORC_FK_EDGE_X, ex);
+  if (ey < fc->margin_m && p->hf[(long)oj * nx + i] != h)
+    note_fragile(fc, ORC_FR_S9, -1, ORC_FK_EDGE_Y, ey);
+  if (is_flipped(fc, ORC_FR_S9, -1, ORC_FK_EDGE_X)) i = oi;
+  if (is_flipped(fc, ORC_FR_S9, -1, ORC_FK_EDGE_Y)) j = oj;
+  return o[2] - (double)p->hf[(long)j * nx + i];
 }
 
 static int step_ws(const orc_morph* m, const orc_params* p, const float* ctrl, double* st,
-                   double* diag, work_t* w) {
+                   double* diag, work_t* w, fragile_ctx* fc) {
   const int N = m->n_points, J = m->n_links - 1;
   if (st[ORC_FLAGS] != 0.0) return 0; /* frozen instance */
   const long n = (long)st[ORC_STEP];
@@ -443,8 +554,8 @@ static int step_ws(const orc_morph* m, const orc_params* p, const float* ctrl, d
     double Rr[3];
     m3_vec(R, w->r + 3 * k, Rr);
     for (int i = 0; i < 3; ++i) w->P[3 * k + i] = c[i] + Rr[i];
-    double d = orc_height(p, w->P[3 * k], w->P[3 * k + 1]) - w->P[3 * k + 2];
-    w->kap[k] = d > 0.0;
+    w->d[k] = probe_depth(p, fc, ORC_FR_S1, k, w->P[3 * k], w->P[3 * k + 1], w->P[3 * k + 2]);
+    w->kap[k] = probe_contact(fc, ORC_FR_S1, k, w->d[k]);
     n_contact += w->kap[k];
   }
 
@@ -457,8 +568,7 @@ static int step_ws(const orc_morph* m, const orc_params* p, const float* ctrl, d
     double wxa[3];
     cross3(om, arm, wxa);
     double uz = v[2] + wxa[2];
-    double d = orc_height(p, w->P[3 * k], w->P[3 * k + 1]) - w->P[3 * k + 2];
-    double f = p->k_n * d * (1.0 - p->zeta * uz);
+    double f = p->k_n * w->d[k] * (1.0 - p->zeta * uz);
     if (f < 0.0) f = 0.0;
     w->f[k] = f;
     double fz[3] = {0.0, 0.0, f}, tk[3];
@@ -519,8 +629,9 @@ static int step_ws(const orc_morph* m, const orc_params* p, const float* ctrl, d
     double Rr[3];
     m3_vec(R1, w->r + 3 * k, Rr);
     for (int i = 0; i < 3; ++i) w->Ps[3 * k + i] = c1[i] + Rr[i];
-    double ds = orc_height(p, w->Ps[3 * k], w->Ps[3 * k + 1]) - w->Ps[3 * k + 2];
-    if (w->kap[k] && ds > 0.0) {
+    if (!w->kap[k]) continue; /* only points in contact at P^n can join the set */
+    double ds = probe_depth(p, fc, ORC_FR_S5, k, w->Ps[3 * k], w->Ps[3 * k + 1], w->Ps[3 * k + 2]);
+    if (probe_contact(fc, ORC_FR_S5, k, ds)) {
       /* ground-plane coordinates about the predicted CoG c1 */
       w->src[2 * nS] = w->P[3 * k] - c1[0];
       w->src[2 * nS + 1] = w->P[3 * k + 1] - c1[1];
@@ -534,7 +645,7 @@ static int step_ws(const orc_morph* m, const orc_params* p, const float* ctrl, d
   /* S6: least-squares displacement and rotation of the contact points */
   double a[3];
   const double* wt = p->weighted ? w->wt : NULL;
-  int fit = orc_lsq_w(nS, w->src, w->dst, wt, p->eps, a);
+  int fit = lsq_core(nS, w->src, w->dst, wt, p->eps, a, fc);
 
   /* S7: cap by the maximum static friction mu F_N (the mean slip is weighted
    * like the fit) */
@@ -552,6 +663,15 @@ static int step_ws(const orc_morph* m, const orc_params* p, const float* ctrl, d
     Ff = M * sqrt(sbx * sbx + sby * sby) / (dt * dt);
     if (isinf(p->mu) || Ff <= p->mu * F) lam = 1.0;
     else lam = p->mu * F / Ff;
+  }
+  /* the slipping-frame count is the only thing the cap's comparison decides
+   * (lambda is continuous across it) */
+  int slipping = fit > 0 && lam < 1.0;
+  if (fc && fit > 0 && !isinf(p->mu)) {
+    const double gap = fabs(Ff - p->mu * F), scale = fmax(Ff, p->mu * F);
+    if (scale > 0.0 && gap < fc->margin_rel * scale)
+      note_fragile(fc, ORC_FR_FIT, -1, ORC_FK_CAP, gap / scale);
+    if (is_flipped(fc, ORC_FR_FIT, -1, ORC_FK_CAP)) slipping = !slipping;
   }
 
   /* S8: move back by the capped fitted motion (translation, then yaw about the
@@ -576,9 +696,9 @@ static int step_ws(const orc_morph* m, const orc_params* p, const float* ctrl, d
   om[2] = om1[2] - lam * alpha / dt;
 
   /* S9: telemetry and health */
-  st[ORC_TELE + 0] += torso_height(m, p, st, g_b);
+  st[ORC_TELE + 0] += torso_height(p, st, g_b, fc);
   st[ORC_TELE + 1] += n_contact;
-  st[ORC_TELE + 2] += (fit > 0 && lam < 1.0) ? 1.0 : 0.0;
+  st[ORC_TELE + 2] += slipping ? 1.0 : 0.0;
   int bad = 0;
   for (int i = 0; i < 13; ++i)
     if (!isfinite(st[i])) bad |= ORC_FLAG_NONFINITE;
@@ -647,7 +767,23 @@ int orc_step(const orc_morph* m, const orc_params* p, const float* ctrl, double*
     work_free(&w);
     return -1;
   }
-  int rc = step_ws(m, p, ctrl, st, diag, &w);
+  int rc = step_ws(m, p, ctrl, st, diag, &w, NULL);
+  work_free(&w);
+  return rc;
+}
+
+int orc_step_ex(const orc_morph* m, const orc_params* p, const float* ctrl, double* st,
+                double* diag, double margin_m, double margin_rel, orc_fragile* log,
+                int log_cap, int* n_log, const orc_fragile* flips, int n_flips) {
+  if (!morph_ok(m) || p->K < 1 || p->dt <= 0.0 || log_cap < 0 || n_flips < 0) return -1;
+  work_t w;
+  if (!work_alloc(&w, m->n_points)) {
+    work_free(&w);
+    return -1;
+  }
+  fragile_ctx fc = {margin_m, margin_rel, log, log ? log_cap : 0, 0, flips, flips ? n_flips : 0};
+  int rc = step_ws(m, p, ctrl, st, diag, &w, &fc);
+  if (n_log) *n_log = fc.n_log;
   work_free(&w);
   return rc;
 }
@@ -660,7 +796,7 @@ int orc_run(const orc_morph* m, const orc_params* p, const float* ctrl, double* 
     work_free(&w);
     return -1;
   }
-  for (long s = 0; s < n_steps; ++s) step_ws(m, p, ctrl, st, NULL, &w);
+  for (long s = 0; s < n_steps; ++s) step_ws(m, p, ctrl, st, NULL, &w, NULL);
   work_free(&w);
   return 0;
 }

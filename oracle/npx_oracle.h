@@ -83,6 +83,37 @@ enum {
 #define ORC_FLAG_NONFINITE 1
 #define ORC_FLAG_SPEED 2
 
+/* A fragile decision of one step: an integer outcome decided by floating point
+ * that a change of the inputs far below the parity tolerances could turn the
+ * other way. A float32 evaluation of the same step may take it either way, so
+ * the parity checks log these and, for a frame that disagrees, re-run the
+ * step with one of them taken the other way (a "flip"). */
+enum {
+  ORC_FR_S1 = 0,       /* stage: detection at P^n (S1, and the S2 force) */
+  ORC_FR_S5 = 1,       /* stage: detection at the predicted P* (S5) */
+  ORC_FR_FIT = 2,      /* stage: the friction fit and its cap (S6-S7) */
+  ORC_FR_S9 = 3        /* stage: the telemetry look-up under the torso origin */
+};
+enum {
+  ORC_FK_EDGE_X = 0,   /* look-up within the margin of a cell edge along x; flip:
+                          the cell on the other side of that edge */
+  ORC_FK_EDGE_Y = 1,   /* the same along y */
+  ORC_FK_CONTACT = 2,  /* |stored height - z| below the margin; flip: the contact
+                          test inverted */
+  ORC_FK_SPREAD = 3,   /* spread test of the fit within a relative margin of
+                          n eps^2; flip: the other branch (rotation fitted or not) */
+  ORC_FK_CAP = 4       /* friction estimate within a relative margin of mu F_N;
+                          only the slipping-frame counter depends on it (the cap
+                          factor is continuous there); flip: the count inverted */
+};
+typedef struct {
+  int stage;      /* ORC_FR_* */
+  int point;      /* point index k (-1 for the fit) */
+  int kind;       /* ORC_FK_* */
+  double dist;    /* distance to the edge or to zero depth (m), or the relative
+                     distance to the threshold */
+} orc_fragile;
+
 int orc_version(void);
 
 /* Forward kinematics at joint angles q: torso-frame points y [N][3], CoG g_b,
@@ -121,6 +152,17 @@ void orc_points(const orc_morph* m, const double* state, double* P);
 /* One step n -> n+1. Returns 0, or -1 on invalid input. */
 int orc_step(const orc_morph* m, const orc_params* p, const float* ctrl, double* state,
              double* diag);
+
+/* One step that also logs its fragile decisions: every look-up of a point at
+ * or below the higher of the two cells' heights (plus margin_m) whose
+ * coordinate lies within margin_m of a cell edge, every contact test with
+ * |depth| < margin_m, and the fit's spread test and cap within margin_rel of
+ * their thresholds. Up to log_cap entries go to log (n_log gets the count,
+ * which may exceed log_cap). flips[0..n_flips) are decisions taken the other
+ * way; margins of 0 and no flips give exactly orc_step. */
+int orc_step_ex(const orc_morph* m, const orc_params* p, const float* ctrl, double* state,
+                double* diag, double margin_m, double margin_rel, orc_fragile* log,
+                int log_cap, int* n_log, const orc_fragile* flips, int n_flips);
 
 /* n_steps steps of one instance. */
 int orc_run(const orc_morph* m, const orc_params* p, const float* ctrl, double* state,

@@ -19,6 +19,13 @@ SRC = os.path.join(HERE, "npx_oracle.c")
 # state-vector offsets (mirror of the enum in npx_oracle.h)
 C_, Q_, V_, W_, STEP, FLAGS, TELE, HDR = 0, 3, 7, 10, 13, 14, 15, 19
 D_FN, D_TAU, D_NC, D_NS, D_A, D_LAMBDA, D_FF, D_LEN = 0, 1, 4, 5, 6, 9, 10, 11
+# fragile decisions (mirror of the enums in npx_oracle.h)
+FR_S1, FR_S5, FR_FIT, FR_S9 = 0, 1, 2, 3
+FK_EDGE_X, FK_EDGE_Y, FK_CONTACT, FK_SPREAD, FK_CAP = 0, 1, 2, 3, 4
+STAGE_NAMES = {FR_S1: "S1 detection at P^n", FR_S5: "S5 detection at P*", FR_FIT: "fit",
+               FR_S9: "S9 torso look-up"}
+KIND_NAMES = {FK_EDGE_X: "cell edge x", FK_EDGE_Y: "cell edge y", FK_CONTACT: "contact sign",
+              FK_SPREAD: "spread test", FK_CAP: "static-friction cap"}
 
 
 def build(force: bool = True) -> str:
@@ -37,6 +44,10 @@ class _Morph(C.Structure):
     _fields_ = [("n_points", C.c_int), ("n_links", C.c_int),
                 ("points", C.POINTER(C.c_float)), ("pt_link", C.POINTER(C.c_int)),
                 ("parent", C.POINTER(C.c_int)), ("joint", C.POINTER(C.c_float))]
+
+
+class _Fragile(C.Structure):
+    _fields_ = [("stage", C.c_int), ("point", C.c_int), ("kind", C.c_int), ("dist", C.c_double)]
 
 
 class _Params(C.Structure):
@@ -70,6 +81,9 @@ def lib():
         L.orc_init_state.argtypes = [C.POINTER(_Morph), C.POINTER(_Params), fp, fp, dp]
         L.orc_points.argtypes = [C.POINTER(_Morph), dp, dp]
         L.orc_step.argtypes = [C.POINTER(_Morph), C.POINTER(_Params), fp, dp, dp]
+        L.orc_step_ex.argtypes = [C.POINTER(_Morph), C.POINTER(_Params), fp, dp, dp, C.c_double,
+                                  C.c_double, C.POINTER(_Fragile), C.c_int, C.POINTER(C.c_int),
+                                  C.POINTER(_Fragile), C.c_int]
         L.orc_run.argtypes = [C.POINTER(_Morph), C.POINTER(_Params), fp, dp, C.c_long]
         L.orc_run_batch.argtypes = [C.c_int, C.POINTER(_Morph), C.POINTER(C.c_int),
                                     C.POINTER(_Params), C.POINTER(fp), C.POINTER(dp),
@@ -188,6 +202,28 @@ class OracleWorld:
                             _dptr(d) if diag else None)
         assert rc == 0
         return d
+
+    def step_ex(self, i, st, margin_m=0.0, margin_rel=0.0, flips=(), diag=False, log_cap=256):
+        """One step of instance i that logs its fragile decisions (look-ups
+        within margin_m of a cell edge that could change a contact, contact
+        tests with |depth| < margin_m, fit thresholds within margin_rel) and
+        takes the decisions in `flips` the other way. Returns the log as
+        (stage, point, kind, distance) tuples (and the diagnostics if diag)."""
+        m = self.morph_of(i)
+        d = np.zeros(D_LEN) if diag else None
+        log = (_Fragile * log_cap)()
+        n_log = C.c_int(0)
+        fl = (_Fragile * max(1, len(flips)))()
+        for k, f in enumerate(flips):
+            fl[k] = _Fragile(int(f[0]), int(f[1]), int(f[2]), 0.0)
+        rc = lib().orc_step_ex(C.byref(m.c), C.byref(self.params.c), _fptr(self.ctrl[i]),
+                               _dptr(st), _dptr(d) if diag else None, float(margin_m),
+                               float(margin_rel), log, int(log_cap), C.byref(n_log), fl,
+                               len(flips))
+        assert rc == 0
+        out = [(log[k].stage, log[k].point, log[k].kind, log[k].dist)
+               for k in range(min(n_log.value, log_cap))]
+        return (out, d) if diag else out
 
     def run(self, i, st, n_steps):
         m = self.morph_of(i)
