@@ -5,27 +5,43 @@
 
 namespace npx {
 
-constexpr float kTwoPi = 6.28318530717958647692f;
 constexpr double kInvTwoPi = 0.15915494309189533577;
 
-// sin and cos of one angle. Quadrant reduction x = k pi/2 + r, |r| <= pi/4, with
-// pi/2 split in two parts and fused multiply-adds (Cody & Waite), then the
-// minimax polynomials of the Cephes library (S. L. Moshier) on the reduced
-// range. About 1 ulp for |x| < 1e4 rad; every angle of the step is far below.
-__device__ __forceinline__ void sin_cos(float x, float* s, float* c) {
-  const float k = rintf(x * 0.636619772367581343f);
-  float r = fmaf(-k, 1.57079637050628662109375f, x);
-  r = fmaf(-k, -4.37113900018624283e-8f, r);
+// sin and cos of r + q pi/2 for |r| <= pi/4: the minimax polynomials of the
+// Cephes library (S. L. Moshier) on the reduced range, then the quadrant.
+__device__ __forceinline__ void sin_cos_quadrant(float r, int q, float* s, float* c) {
   const float r2 = r * r;
   const float sr = fmaf(r * r2, fmaf(r2, fmaf(r2, -1.9515295891e-4f, 8.3321608736e-3f),
                                      -1.6666654611e-1f), r);
   const float cr = fmaf(r2 * r2, fmaf(r2, fmaf(r2, 2.443315711809948e-5f, -1.388731625493765e-3f),
                                       4.166664568298827e-2f), fmaf(-0.5f, r2, 1.f));
-  const int q = (int)k;
   const float ss = (q & 1) ? cr : sr;
   const float cc = (q & 1) ? sr : cr;
   *s = (q & 2) ? -ss : ss;
   *c = ((q + 1) & 2) ? -cc : cc;
+}
+
+// sin and cos of one angle. Quadrant reduction x = k pi/2 + r, |r| <= pi/4, with
+// pi/2 split in two parts and fused multiply-adds (Cody & Waite), then the
+// polynomials above. About 1 ulp for |x| < 1e4 rad; every angle of the step is
+// far below.
+__device__ __forceinline__ void sin_cos(float x, float* s, float* c) {
+  const float k = rintf(x * 0.636619772367581343f);
+  float r = fmaf(-k, 1.57079637050628662109375f, x);
+  r = fmaf(-k, -4.37113900018624283e-8f, r);
+  sin_cos_quadrant(r, (int)k, s, c);
+}
+
+// sin of 2 pi t for a phase t given in turns (double): the quarter-turn count
+// and the remainder are taken in double, so only the remainder, at most pi/4,
+// is rounded to float32 (about 4e-8 rad) before the polynomials.
+__device__ __forceinline__ float sin_turns(double t) {
+  const double x = 4.0 * (t - floor(t));
+  const double k = rint(x);
+  const float r = (float)((x - k) * 1.5707963267948966192);
+  float s, c;
+  sin_cos_quadrant(r, (int)k, &s, &c);
+  return s;
 }
 
 __device__ __forceinline__ void quat_to_mat(float w, float x, float y, float z, float R[9]) {
@@ -36,14 +52,31 @@ __device__ __forceinline__ void quat_to_mat(float w, float x, float y, float z, 
   R[6] = 2.f * (xz - wy);       R[7] = 2.f * (yz + wx);       R[8] = 1.f - 2.f * (xx + yy);
 }
 
-// Height-map look-up (Sec. III-A): floor(s (x - x0)) clamped onto the table;
-// fmaxf maps a NaN coordinate to cell 0.
-__device__ __forceinline__ float hf_lookup(const float* hf, int nx, int ny, float x0, float y0,
-                                           float s, float x, float y) {
-  float u = fminf(fmaxf((x - x0) * s, 0.f), (float)(nx - 1));
-  float w = fminf(fmaxf((y - y0) * s, 0.f), (float)(ny - 1));
-  int i = (int)u, j = (int)w;
-  return hf[j * nx + i];
+// Cell index of a coordinate on the height-map table (Sec. III-A): floor of
+// s (x - x0), clamped onto the table. It is an integer decided by arithmetic,
+// so it is taken in double from the float32 coordinate: the index is then the
+// exact floor for the point's own position, where float32 rounding of
+// s (x - x0) would move points lying within ~1e-6 m of a cell edge across it.
+// The coordinate is first held in [lo, hi] (float32 bounds chosen on the host
+// half a cell outside the first and last cell edges; fmaxf sends a NaN to lo),
+// so the scaled value u = s x - s x0 (one FMA against the host's double
+// -s x0) lies in about [-1/2, n - 1/2] and its truncation towards zero is the
+// clamped floor.
+struct HfAxis {
+  double s;      // cells per metre
+  double ms0;    // -s x0
+  float lo, hi;  // clamp range of the coordinate, as above
+};
+
+__device__ __forceinline__ int hf_index(float x, const HfAxis& ax) {
+  const float xc = fminf(fmaxf(x, ax.lo), ax.hi);
+  return (int)fma((double)xc, ax.s, ax.ms0);
+}
+
+// Height-map look-up (Sec. III-A): the stored height of the point's cell.
+__device__ __forceinline__ float hf_lookup(const float* hf, int nx, const HfAxis& ax,
+                                           const HfAxis& ay, float x, float y) {
+  return hf[hf_index(y, ay) * nx + hf_index(x, ax)];
 }
 
 // Bilinear reading of the same table (the smoother-ground option): entry (i, j)

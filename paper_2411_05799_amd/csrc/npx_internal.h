@@ -6,6 +6,7 @@
 #include <cstdint>
 
 #include "npx.h"
+#include "npx_device.h"
 
 namespace npx {
 
@@ -53,6 +54,7 @@ struct StepArgs {
   const float* hf;
   int hf_nx, hf_ny;
   float hf_s, hf_x0, hf_y0;
+  HfAxis hf_ax, hf_ay;    // cell index along x and y (see hf_index)
   float hf_max;           // highest entry of the height map
   int hf_bilinear;        // 1: read the table bilinearly between cell centres
   float* st;              // [state_rows(j_max)][n_inst]

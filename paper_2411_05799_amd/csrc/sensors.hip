@@ -203,8 +203,7 @@ __global__ __launch_bounds__(64) void gp_kernel(WorldView v, GpArgs g) {
     const float h = v.a.hf_bilinear
                         ? hf_bilinear(v.a.hf, v.a.hf_nx, v.a.hf_ny, v.a.hf_x0, v.a.hf_y0, v.a.hf_s,
                                       P[0], P[1])
-                        : hf_lookup(v.a.hf, v.a.hf_nx, v.a.hf_ny, v.a.hf_x0, v.a.hf_y0, v.a.hf_s,
-                                    P[0], P[1]);
+                        : hf_lookup(v.a.hf, v.a.hf_nx, v.a.hf_ax, v.a.hf_ay, P[0], P[1]);
     if (h - P[2] > 0.f) bits |= 1u << pr.x;
   }
 #pragma unroll

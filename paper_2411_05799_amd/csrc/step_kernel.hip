@@ -91,7 +91,7 @@ __device__ __forceinline__ void group_fence(int p) {
 template <bool BIL>
 __device__ __forceinline__ float hf_at(const StepArgs& a, float x, float y) {
   if constexpr (BIL) return hf_bilinear(a.hf, a.hf_nx, a.hf_ny, a.hf_x0, a.hf_y0, a.hf_s, x, y);
-  return hf_lookup(a.hf, a.hf_nx, a.hf_ny, a.hf_x0, a.hf_y0, a.hf_s, x, y);
+  return hf_lookup(a.hf, a.hf_nx, a.hf_ax, a.hf_ay, x, y);
 }
 
 // The bits of a wave-wide lane mask that belong to segment `seg` (G lanes),
@@ -451,11 +451,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
   // S0: commanded angle of this lane's joints at frame n, clamped to the limits
   auto command = [&](int l) __attribute__((always_inline)) {
     const double t = (double)n * a.dt_d;
-    double ph = (double)k_f[l] * t + k_ph[l];
-    ph -= floor(ph);
-    float sq, cq;
-    sin_cos(kTwoPi * (float)ph, &sq, &cq);
-    const float qh = k_A[l] * sq;
+    const float qh = k_A[l] * sin_turns((double)k_f[l] * t + k_ph[l]);
     return lj[l] ? fminf(fmaxf(qh, k_lo[l]), k_hi[l]) : 0.f;
   };
 
@@ -551,10 +547,16 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
         Eb[6] = 2.f * (x * z - w0 * y); Eb[7] = 2.f * (y * z + w0 * x); Eb[8] = -2.f * (x * x + y * y);
       }
 
-      // S5 + S6 moments over the friction set in the ground plane about the
-      // predicted CoG c1: source xi = P^n - c1 = R r_old - (c1 - c), slip
-      // delta = P* - P^n. The normal equations (4)-(6) need n, sum xi,
-      // sum |xi|^2, sum delta and sum xi x delta.
+      // S5 + S6 moments over the friction set in the ground plane: source
+      // xi = P^n - c1 = R r_old - (c1 - c), slip delta = P* - P^n. The normal
+      // equations (4)-(6) need n, sum xi, sum |xi|^2, sum delta and
+      // sum xi x delta. The sums over xi are taken about one point of the set
+      // itself (the first one found; eta = xi - o = U - U_o with U = R r_old):
+      // about the CoG, or about any point far from the set, a foot-sized set
+      // 0.3 m away leaves D = sum |xi|^2 - |sum xi|^2 / n to a float32
+      // difference of two nearly equal numbers. The fit is covariant in its
+      // origin: the rotation a3 is the same and the displacement about c1 is
+      // a = b - a3 J o (J: quarter turn), o = U_o - dt v1.
       //
       // Only points in contact at P^n can be in the friction set, and they are
       // few (the feet), so they are first compacted into an LDS list (slot by
@@ -569,61 +571,77 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
         n_cand += __popcll(m);
       }
       __builtin_amdgcn_wave_barrier();
-      const float dcx = c1[0] - c[0], dcy = c1[1] - c[1];
+      // The trial displacement of the CoG enters the slip as dt v1 itself, not
+      // as c1 - c: c1 is rounded to float32 (half an ulp, 1.2e-7 m at |c| ~ 2 m),
+      // and a fit that took that rounding for slip would return it as a
+      // velocity change of 1.2e-7 m / dt.
+      const float dcx = dt * v1[0], dcy = dt * v1[1];
       float mn = 0.f, Sx = 0.f, Sy = 0.f, S2 = 0.f, Dx = 0.f, Dy = 0.f, Cd = 0.f, Wt = 0.f;
-      for (int e = sl; e < n_cand; e += G) {
-        const int kk = pt_off + cand[e];
-        const float4 rho = a.pts[kk];
-        const int lk = a.pt_link[kk];
-        // r = T rho - g_b at the new joint angles, and its increment this frame
-        const float4 t0 = T[lk][0], t1 = T[lk][1], t2 = T[lk][2];
-        const float rx = t0.x * rho.x + t0.y * rho.y + t0.z * rho.z + t0.w - gb[0];
-        const float ry = t1.x * rho.x + t1.y * rho.y + t1.z * rho.z + t1.w - gb[1];
-        const float rz = t2.x * rho.x + t2.y * rho.y + t2.z * rho.z + t2.w - gb[2];
-        const float ux = R1[0] * rx + R1[1] * ry + R1[2] * rz;
-        const float uy = R1[3] * rx + R1[4] * ry + R1[5] * rz;
-        const float uz = R1[6] * rx + R1[7] * ry + R1[8] * rz;
-        const float Px = c1[0] + ux, Py = c1[1] + uy, Pz = c1[2] + uz;
-        if (hf_at<BIL>(a, Px, Py) - Pz > 0.f) {
-          float drx = 0.f, dry = 0.f, drz = 0.f;
-          if (fk_now) {
-            const float4 d0 = dT[lk][0], d1 = dT[lk][1], d2 = dT[lk][2];
-            drx = d0.x * rho.x + d0.y * rho.y + d0.z * rho.z + d0.w - dgb[0];
-            dry = d1.x * rho.x + d1.y * rho.y + d1.z * rho.z + d1.w - dgb[1];
-            drz = d2.x * rho.x + d2.y * rho.y + d2.z * rho.z + d2.w - dgb[2];
+      float ox_ = 0.f, oy_ = 0.f;  // origin of the moments (about c), see above
+      bool have_o = false;
+      for (int e0 = 0; __any(e0 < n_cand); e0 += G) {
+        const int e = e0 + sl;
+        bool inS = false;
+        float Ux = 0.f, Uy = 0.f, dx = 0.f, dy = 0.f, wk = 1.f;
+        if (e < n_cand) {
+          const int kk = pt_off + cand[e];
+          const float4 rho = a.pts[kk];
+          const int lk = a.pt_link[kk];
+          // r = T rho - g_b at the new joint angles, and its increment this frame
+          const float4 t0 = T[lk][0], t1 = T[lk][1], t2 = T[lk][2];
+          const float rx = t0.x * rho.x + t0.y * rho.y + t0.z * rho.z + t0.w - gb[0];
+          const float ry = t1.x * rho.x + t1.y * rho.y + t1.z * rho.z + t1.w - gb[1];
+          const float rz = t2.x * rho.x + t2.y * rho.y + t2.z * rho.z + t2.w - gb[2];
+          const float ux = R1[0] * rx + R1[1] * ry + R1[2] * rz;
+          const float uy = R1[3] * rx + R1[4] * ry + R1[5] * rz;
+          const float uz = R1[6] * rx + R1[7] * ry + R1[8] * rz;
+          const float Px = c1[0] + ux, Py = c1[1] + uy, Pz = c1[2] + uz;
+          if (hf_at<BIL>(a, Px, Py) - Pz > 0.f) {
+            inS = true;
+            float drx = 0.f, dry = 0.f, drz = 0.f;
+            if (fk_now) {
+              const float4 d0 = dT[lk][0], d1 = dT[lk][1], d2 = dT[lk][2];
+              drx = d0.x * rho.x + d0.y * rho.y + d0.z * rho.z + d0.w - dgb[0];
+              dry = d1.x * rho.x + d1.y * rho.y + d1.z * rho.z + d1.w - dgb[1];
+              drz = d2.x * rho.x + d2.y * rho.y + d2.z * rho.z + d2.w - dgb[2];
+            }
+            const float qx = rx - drx, qy = ry - dry, qz = rz - drz;  // r_old
+            Ux = R[0] * qx + R[1] * qy + R[2] * qz;
+            Uy = R[3] * qx + R[4] * qy + R[5] * qz;
+            const float Uz = R[6] * qx + R[7] * qy + R[8] * qz;
+            dx = (Eb[0] * Ux + Eb[1] * Uy + Eb[2] * Uz) + (R1[0] * drx + R1[1] * dry + R1[2] * drz) +
+                 dcx;
+            dy = (Eb[3] * Ux + Eb[4] * Uy + Eb[5] * Uz) + (R1[3] * drx + R1[4] * dry + R1[5] * drz) +
+                 dcy;
+            if (a.fric_w) {
+              // weighted by the force pressing the point at P^n, the normal
+              // force of detection recomputed from the point before this
+              // frame's joint update (the position P^n = c + U)
+              const float dn = hf_at<BIL>(a, c[0] + Ux, c[1] + Uy) - (c[2] + Uz);
+              const float vz = v[2] + (w[0] * Uy - w[1] * Ux);
+              wk = dn > 0.f ? fmaxf(a.kn * dn * (1.f - a.zeta * vz), 0.f) : 0.f;
+            }
           }
-          const float ox = rx - drx, oy = ry - dry, oz = rz - drz;  // r_old
-          const float Ux = R[0] * ox + R[1] * oy + R[2] * oz;
-          const float Uy = R[3] * ox + R[4] * oy + R[5] * oz;
-          const float Uz = R[6] * ox + R[7] * oy + R[8] * oz;
-          const float sx = Ux - dcx, sy = Uy - dcy;
-          const float dx = (Eb[0] * Ux + Eb[1] * Uy + Eb[2] * Uz) +
-                           (R1[0] * drx + R1[1] * dry + R1[2] * drz) + dcx;
-          const float dy = (Eb[3] * Ux + Eb[4] * Uy + Eb[5] * Uz) +
-                           (R1[3] * drx + R1[4] * dry + R1[5] * drz) + dcy;
+        }
+        // the origin: U of the segment's first friction-set point
+        const unsigned long long m = seg_bits<G>(__ballot(inS), seg);
+        const int src = seg * G + (m ? (int)__builtin_ctzll(m) : sl);
+        const float bx = __shfl(Ux, src), by = __shfl(Uy, src);
+        if (!have_o && m != 0ull) {
+          ox_ = bx;
+          oy_ = by;
+          have_o = true;
+        }
+        if (inS) {
+          const float sx = Ux - ox_, sy = Uy - oy_;
           mn += 1.f;
-          if (a.fric_w) {
-            // weighted by the force pressing the point at P^n, the normal
-            // force of detection recomputed from the point before this
-            // frame's joint update (the position P^n = c + U)
-            const float dn = hf_at<BIL>(a, c[0] + Ux, c[1] + Uy) - (c[2] + Uz);
-            const float vz = v[2] + (w[0] * Uy - w[1] * Ux);
-            const float wk = dn > 0.f ? fmaxf(a.kn * dn * (1.f - a.zeta * vz), 0.f) : 0.f;
-            Wt += wk;
-            Sx += wk * sx;
-            Sy += wk * sy;
-            S2 += wk * (sx * sx + sy * sy);
-            Dx += wk * dx;
-            Dy += wk * dy;
-            Cd += wk * (sx * dy - sy * dx);
-          } else {
-            Sx += sx;
-            Sy += sy;
-            S2 += sx * sx + sy * sy;
-            Dx += dx;
-            Dy += dy;
-            Cd += sx * dy - sy * dx;
-          }
+          Wt += wk;
+          Sx += wk * sx;
+          Sy += wk * sy;
+          S2 += wk * (sx * sx + sy * sy);
+          Dx += wk * dx;
+          Dy += wk * dy;
+          Cd += wk * (sx * dy - sy * dx);
         }
       }
       mn = seg_sum<G>(mn);
@@ -644,8 +662,8 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
         const float inv_n = rcp(Wn);
         const float D = S2 - (Sx * Sx + Sy * Sy) * inv_n;
         if (mn >= 2.f && D > Wn * a.eps * a.eps) a3 = (Cd - (Sx * Dy - Sy * Dx) * inv_n) * rcp(D);
-        a1 = (Dx + Sy * a3) * inv_n;
-        a2 = (Dy - Sx * a3) * inv_n;
+        a1 = (Dx + Sy * a3) * inv_n + a3 * (oy_ - dcy);
+        a2 = (Dy - Sx * a3) * inv_n - a3 * (ox_ - dcx);
         const float sbx = Dx * inv_n, sby = Dy * inv_n;
         const float Ff = M * __builtin_amdgcn_sqrtf(sbx * sbx + sby * sby) * (inv_dt * inv_dt);
         lam = (a.mu_inf || Ff <= a.mu * F) ? 1.f : a.mu * F * rcp(Ff);
@@ -673,7 +691,9 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
         Q2[2] = ch * Q1[2] + sh * Q1[1];
         Q2[3] = ch * Q1[3] + sh * Q1[0];
       }
-      const float c2[3] = {c1[0] - lam * a1, c1[1] - lam * a2, c1[2]};
+      // c'' = c + (dt v1 - lam a): the small trial step and correction first,
+      // one rounding onto the position
+      const float c2[3] = {c[0] + (dcx - lam * a1), c[1] + (dcy - lam * a2), c1[2]};
       const float v2[3] = {v1[0] - lam * a1 * inv_dt, v1[1] - lam * a2 * inv_dt, v1[2]};
       const float w2[3] = {w1[0], w1[1], w1[2] - lam * alpha * inv_dt};
 

@@ -64,17 +64,14 @@ __device__ __forceinline__ float command(const WorldView& v, int i, int lk_off, 
   const float* cp = v.a.ctrl + ((int64_t)i * v.a.j_max + j) * 3;
   const float* lk = v.a.links + (int64_t)(lk_off + j + 1) * LINK_F;
   const double t = (double)n * v.a.dt_d;
-  double ph = (double)cp[1] * t + (double)cp[2] * npx::kInvTwoPi;
-  ph -= floor(ph);
-  float sq, cq;
-  npx::sin_cos(npx::kTwoPi * (float)ph, &sq, &cq);
+  const float sq = npx::sin_turns((double)cp[1] * t + (double)cp[2] * npx::kInvTwoPi);
   return fminf(fmaxf(cp[0] * sq, lk[6]), lk[7]);
 }
 
 __device__ __forceinline__ float hf(const WorldView& v, float x, float y) {
   if (v.a.hf_bilinear)
     return npx::hf_bilinear(v.a.hf, v.a.hf_nx, v.a.hf_ny, v.a.hf_x0, v.a.hf_y0, v.a.hf_s, x, y);
-  return npx::hf_lookup(v.a.hf, v.a.hf_nx, v.a.hf_ny, v.a.hf_x0, v.a.hf_y0, v.a.hf_s, x, y);
+  return npx::hf_lookup(v.a.hf, v.a.hf_nx, v.a.hf_ax, v.a.hf_ay, x, y);
 }
 
 // ---- heading frame -------------------------------------------------------------

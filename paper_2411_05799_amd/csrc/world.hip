@@ -125,6 +125,23 @@ struct npx_world {
 
 namespace {
 
+// One axis of the height-map cell index (npx::hf_index): the scale, -s x0 in
+// double, and a float32 range [lo, hi] half a cell beyond the table's first and
+// last cell edges (rounded outwards), so that s (lo - x0) is about -1/2 and
+// s (hi - x0) about n - 1/2: every clamped coordinate truncates to the cell
+// floor(s (x - x0)) clamped onto [0, n - 1].
+npx::HfAxis hf_axis(double x0, double s, int n) {
+  npx::HfAxis a;
+  a.s = s;
+  a.ms0 = -s * x0;
+  const double lo = x0 - 0.5 / s, hi = x0 + ((double)n - 0.5) / s;
+  a.lo = (float)lo;
+  if ((double)a.lo > lo) a.lo = std::nextafter(a.lo, -INFINITY);
+  a.hi = (float)hi;
+  if ((double)a.hi < hi) a.hi = std::nextafter(a.hi, INFINITY);
+  return a;
+}
+
 size_t field_bytes(const npx_world* w, int field, size_t* row0, size_t* rows, int* kind) {
   // kind 0 float rows of st, 1 step, 2 flags, 3 tele
   const size_t I = (size_t)w->n_inst;
@@ -542,6 +559,8 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   a.hf_ny = d->hf_ny;
   a.hf_s = (float)d->hf_s;
   a.hf_x0 = (float)d->hf_x0;
+  a.hf_ax = hf_axis(d->hf_x0, d->hf_s, d->hf_nx);
+  a.hf_ay = hf_axis(d->hf_y0, d->hf_s, d->hf_ny);
   a.hf_y0 = (float)d->hf_y0;
   a.hf_max = -INFINITY;
   for (size_t k = 0; k < (size_t)d->hf_nx * d->hf_ny; ++k) a.hf_max = std::max(a.hf_max, d->hf_heights[k]);
