@@ -16,8 +16,7 @@ from oracle import oracle as O
 from paper_2411_05799_amd import native as N
 from paper_2411_05799_amd import workloads as W
 
-from _helpers import (ANG_TOL, MAX_ILL_FRACTION, POS_TOL, STAT_TOL, gpu_available, judge_windows,
-                      read_states, run_windows, write_states)
+from _helpers import STAT_TOL, assert_windows as _assert_windows, gpu_available, read_states, run_windows
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_available(), reason="needs a HIP device")]
@@ -28,23 +27,12 @@ def say(msg):
     sys.stdout.flush()
 
 
-def assert_windows(results, label, ow):
-    """Every window within 1e-4 m / 1e-3 rad, except windows the FP64 oracle itself
-    does not determine to that tolerance at float32 resolution, where the GPU must
-    stay within 3x the oracle's own noisy-ensemble spread (a sanity bound caps
-    such windows at half of all)."""
-    worst = max(results, key=lambda r: max(r[2].cog, r[2].pts) / POS_TOL
-                + max(r[2].joint, r[2].orient) / ANG_TOL)
-    say(f"{label}: {len(results)} windows, worst (start {worst[0]}, inst {worst[1]}): {worst[2]}")
-    bad, ill = judge_windows(ow, results)
-    for s, i, st in ill:
-        say(f"  ill-conditioned window start {s} inst {i}: gpu {st}; oracle spread "
-            f"{st.spread[0]:.2e} m {st.spread[1]:.2e} rad")
-    for s, i, st in bad:
-        sp = st.spread
-        say(f"  FAIL start {s} inst {i}: gpu {st}; oracle spread {sp[0]:.2e} m {sp[1]:.2e} rad")
-    assert not bad, f"{len(bad)} windows out of tolerance"
-    assert len(ill) <= MAX_ILL_FRACTION * len(results), f"{len(ill)} ill-conditioned windows"
+def assert_windows(results, label, ow=None):
+    """Every GPU frame is the oracle's frame from the same state (to float32
+    rounding, or with a logged fragile decision taken the other way), and every
+    window is within 1e-4 m / 1e-3 rad, or beyond it with every frame verified
+    (at most a tenth of the windows)."""
+    _assert_windows(results, label, say=say)
 
 
 def test_placement_matches_oracle():
@@ -136,7 +124,7 @@ def test_config2_full_size_sampled_windows():
     with N.World(w) as gw:
         from bench import pick_launch
         pick_launch(gw, w)
-        res = run_windows(ow, gw, idx, starts=[0, 200, 400, 600, 800], every=40)
+        res = run_windows(ow, gw, idx, starts=[0, 200, 400, 600, 800])
     assert_windows(res, "config2", ow)
 
 
@@ -150,7 +138,7 @@ def test_launch_shapes_ragged_batch(lanes):
     for persistent in (0, 1):
         with N.World(w) as gw:
             gw.set_launch(lanes_per_instance=lanes, persistent=persistent, waves_per_cu=2)
-            res = run_windows(ow, gw, [0, 17, 36], starts=[0, 300], every=50)
+            res = run_windows(ow, gw, [0, 17, 36], starts=[0, 300])
         assert_windows(res, f"lanes {lanes} persistent {persistent}", ow)
 
 
@@ -160,7 +148,7 @@ def test_uneven_morphologies():
     w = W.config3(n_inst=48)
     ow = O.OracleWorld(w)
     with N.World(w) as gw:
-        res = run_windows(ow, gw, list(range(0, 48, 5)), starts=[0, 400], every=50)
+        res = run_windows(ow, gw, list(range(0, 48, 5)), starts=[0, 400])
     assert_windows(res, "uneven", ow)
 
 
@@ -189,7 +177,7 @@ def test_max_size_robot():
                    pose=np.array([[0, 0, 0.3, 1, 0, 0, 0]], np.float32))
     ow = O.OracleWorld(w)
     with N.World(w) as gw:
-        res = run_windows(ow, gw, [0], starts=[0, 200, 600], every=50)
+        res = run_windows(ow, gw, [0], starts=[0, 200, 600])
     assert_windows(res, "max robot", ow)
 
 
@@ -219,7 +207,7 @@ def test_degenerate_bodies_and_paper_mode():
                        pose=np.array([xyz + [1, 0, 0, 0]], np.float32))
         ow = O.OracleWorld(w)
         with N.World(w) as gw:
-            res = run_windows(ow, gw, [0], starts=[0, 200], every=25)
+            res = run_windows(ow, gw, [0], starts=[0, 200])
         assert_windows(res, f"{m.name} dt={p.dt} K={p.K} mu={p.mu}", ow)
 
 
@@ -351,7 +339,7 @@ def test_robot_built_with_construction_api():
                    pose=np.array([[0, 0, 0.16, 1, 0, 0, 0]], np.float32))
     ow = O.OracleWorld(w)
     with N.World(w) as gw:
-        res = run_windows(ow, gw, [0], starts=[0, 400], every=40)
+        res = run_windows(ow, gw, [0], starts=[0, 400])
     assert_windows(res, "construction-API quadruped", ow)
 
 
@@ -365,7 +353,7 @@ def test_force_weighted_friction_windows():
     w.params.friction_weighting = True
     ow = O.OracleWorld(w)
     with N.World(w) as gw:
-        res = run_windows(ow, gw, list(range(32)), starts=[0, 200, 400], every=40)
+        res = run_windows(ow, gw, list(range(32)), starts=[0, 200, 400])
     assert_windows(res, "weighted", ow)
     w0 = W.hexapod_batch(32, seed=31, hf=W.octave_terrain(5), n_steps=600)
     with N.World(w) as gw_w, N.World(w0) as gw_u:
@@ -384,7 +372,7 @@ def test_bilinear_ground_windows():
     w.params.hf_bilinear = True
     ow = O.OracleWorld(w)
     with N.World(w) as gw:
-        res = run_windows(ow, gw, list(range(32)), starts=[0, 200, 400], every=40)
+        res = run_windows(ow, gw, list(range(32)), starts=[0, 200, 400])
     assert_windows(res, "bilinear", ow)
     w0 = W.hexapod_batch(32, seed=41, hf=W.octave_terrain(6), n_steps=600)
     with N.World(w) as gw_b, N.World(w0) as gw_t:
@@ -404,23 +392,25 @@ def test_paper_mode_on_terrain_windows():
     w.params.dt, w.params.K, w.params.k_n = 1e-2, 8, 150.0
     ow = O.OracleWorld(w)
     with N.World(w) as gw:
-        res = run_windows(ow, gw, list(range(32)), starts=[0, 200, 400], every=40)
+        res = run_windows(ow, gw, list(range(32)), starts=[0, 200, 400])
     assert_windows(res, "paper mode", ow)
 
 
 def test_joint_rate_limit_windows():
-    """Joints turning at most 1 rad/s (the motors' speed), joint targets every
-    8 frames, on the terrain: 32 hexapods, 3 windows of 200 frames against the
-    oracle, and the limit changes the trajectories."""
-    say("case: joint rate limit, 32 hexapods x 3 windows")
+    """Joints turning at most 1 rad/s (the motors' speed, Sec. III-B) at the
+    paper's operating point: 10 ms frames, joint targets every 8 frames,
+    contacts at 150 N/m per point, on the terrain: 32 hexapods, 3 windows of
+    200 frames (2 s each) against the oracle, and the limit changes the
+    trajectories."""
+    say("case: joint rate limit at 10 ms frames, 32 hexapods x 3 windows")
     w = W.hexapod_batch(32, seed=61, n_steps=600)
-    w.params.K, w.params.max_joint_rate = 8, 1.0
+    w.params.dt, w.params.K, w.params.k_n, w.params.max_joint_rate = 1e-2, 8, 150.0, 1.0
     ow = O.OracleWorld(w)
     with N.World(w) as gw:
-        res = run_windows(ow, gw, list(range(32)), starts=[0, 200, 400], every=40)
+        res = run_windows(ow, gw, list(range(32)), starts=[0, 200, 400])
     assert_windows(res, "rate limit", ow)
     w0 = W.hexapod_batch(32, seed=61, n_steps=600)
-    w0.params.K = 8
+    w0.params.dt, w0.params.K, w0.params.k_n = 1e-2, 8, 150.0
     with N.World(w) as gw_l, N.World(w0) as gw_u:
         gw_l.step_n(200)
         gw_u.step_n(200)
