@@ -107,14 +107,20 @@ class Workload:
 # geometry helpers (point placement only)
 # ----------------------------------------------------------------------------
 
+def _cross(a, b):
+    """Cross product of two 3-vectors (the component formulas, as numpy's)."""
+    return np.array([a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2],
+                     a[0] * b[1] - a[1] * b[0]])
+
+
 def _ring(center, direction, radius, n):
     """n points on a circle of given radius around `center`, normal `direction`."""
     d = np.asarray(direction, dtype=np.float64)
     d = d / np.linalg.norm(d)
     helper = np.array([0.0, 0.0, 1.0]) if abs(d[2]) < 0.9 else np.array([1.0, 0.0, 0.0])
-    e1 = np.cross(d, helper)
+    e1 = _cross(d, helper)
     e1 /= np.linalg.norm(e1)
-    e2 = np.cross(d, e1)
+    e2 = _cross(d, e1)
     ang = 2.0 * np.pi * np.arange(n) / n
     return (np.asarray(center, dtype=np.float64)[None, :]
             + radius * (np.cos(ang)[:, None] * e1[None, :] + np.sin(ang)[:, None] * e2[None, :]))

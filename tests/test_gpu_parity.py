@@ -16,7 +16,8 @@ from oracle import oracle as O
 from paper_2411_05799_amd import native as N
 from paper_2411_05799_amd import workloads as W
 
-from _helpers import STAT_TOL, assert_windows as _assert_windows, gpu_available, read_states, run_windows
+from _helpers import (STAT_TOL, assert_windows as _assert_windows, gpu_available, read_states,
+                      round_state as H_round, run_windows, write_states)
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_available(), reason="needs a HIP device")]
@@ -150,6 +151,129 @@ def test_uneven_morphologies():
     with N.World(w) as gw:
         res = run_windows(ow, gw, list(range(0, 48, 5)), starts=[0, 400])
     assert_windows(res, "uneven", ow)
+
+
+_C3 = {}
+
+
+def config3_world():
+    """Config 3: 16,384 random legged robots (4/6/8 legs of 2-4 joints, 200-600
+    points) on the octave terrain; generated once for the module."""
+    if "w" not in _C3:
+        _C3["w"] = W.config3(n_inst=16_384, n_steps=10_000)
+    return _C3["w"]
+
+
+def test_config3_full_size_sampled_windows():
+    """The 16,384-robot uneven batch in one world at the launch shape the
+    autotuner picks for it (the bench's: lanes per robot, links per lane,
+    persistent task queue, hipGraph chunks): 32 sampled robots x 5 windows of
+    200 frames against the oracle."""
+    say("case: config3 16384 uneven robots, 32 sampled x 5 windows")
+    w = config3_world()
+    ow = O.OracleWorld(w)
+    rng = np.random.default_rng(3)
+    idx = sorted(rng.choice(w.n_instances, size=32, replace=False).tolist())
+    with N.World(w) as gw:
+        from bench import pick_launch
+        pick_launch(gw, w)
+        say(f"launch: {gw.get_launch().as_dict()}")
+        res = run_windows(ow, gw, idx, starts=[0, 200, 400, 600, 800])
+    assert_windows(res, "config3", ow)
+
+
+def _state_at(gw, idx, frames, J_of):
+    """GPU states of instances idx (float64 oracle layout) at the given frame
+    counts, stepping the world forward from its current frame 0."""
+    out, at = {}, 0
+    for f in sorted(set(frames)):
+        gw.step_n(f - at)
+        at = f
+        got = read_states(gw, idx, J_of)
+        for i, st, ff in zip(idx, got, frames):
+            if ff == f:
+                out[i] = st
+    return out
+
+
+def test_config3_long_horizon_statistics_and_flags():
+    """10,000 frames of the 16,384-robot uneven batch at the autotuned launch,
+    512 robots sampled. Statistics: mean distance walked and mean torso height
+    of the robots neither side flags within 2% of the oracle's (or 3 standard
+    errors of the paired difference when that is wider: per robot, contact on
+    the terrain is chaotic over 10 s). Health flags: some random morphologies
+    run away under the method (spin or speed past the limits) on one float32
+    or float64 realization of their trajectory and not on the other, so the
+    flag rates must agree (within 3 standard errors of the paired difference),
+    and every robot flagged by one side only must run away on the other side
+    too when started from the first side's state 50 frames before its flag
+    (within 150 frames): the same run-away, reached on another chaotic path."""
+    say("case: config3 long horizon, 512 sampled x 10k frames, health flags")
+    n = 10_000
+    w = config3_world()
+    rng = np.random.default_rng(33)
+    idx = np.sort(rng.choice(w.n_instances, size=512, replace=False))
+    J_of = lambda i: w.morphs[int(w.inst_morph[i])].n_joints
+    with N.World(w) as gw:
+        from bench import pick_launch
+        pick_launch(gw, w)          # tunes on scratch copies: the state is untouched
+        launch = gw.get_launch().as_dict()
+        g_c0 = gw.read_state(N.F_COG)[:2].astype(np.float64)
+        gw.step_n(n)
+        cog = gw.read_state(N.F_COG)[:2]
+        tele = gw.read_state(N.F_TELE)
+        gflags = gw.read_state(N.F_FLAGS)
+        gstep = gw.read_state(N.F_STEP)
+    say(f"launch {launch}; GPU flagged {int((gflags != 0).sum())} of {w.n_instances} robots")
+    ow = O.OracleWorld(w)
+    states = [ow.init_state(int(i)) for i in idx]
+    c0 = np.array([s[:2] for s in states])
+    ow.run_batch(states, n, idx=idx)
+    of = np.array([int(s[O.FLAGS]) != 0 for s in states])
+    gf = gflags[idx] != 0
+    diff = gf.astype(float) - of.astype(float)
+    se = max(np.std(diff, ddof=1) / np.sqrt(len(idx)), 1.0 / len(idx))
+    say(f"flagged among {len(idx)} sampled: GPU {int(gf.sum())}, oracle {int(of.sum())}, both "
+        f"{int((gf & of).sum())}")
+    assert abs(diff.mean()) <= 3 * se, (gf.sum(), of.sum())
+    # one-sided flags: the other side from this side's state 50 frames before
+    gpu_only = [int(i) for i, a, b in zip(idx, gf, of) if a and not b]
+    orc_only = [int(i) for i, a, b in zip(idx, gf, of) if b and not a]
+    if gpu_only:
+        with N.World(w) as gw:
+            gw.set_launch(**launch)     # the same trajectories, bit for bit
+            back = {i: max(0, int(gstep[i]) - 50) for i in gpu_only}
+            snap = _state_at(gw, gpu_only, [back[i] for i in gpu_only], J_of)
+        for i in gpu_only:
+            st = snap[i].copy()
+            ow.run(i, st, 150)
+            say(f"  robot {i}: GPU flag at frame {int(gstep[i])}; oracle from the GPU state at "
+                f"frame {back[i]}: flags {int(st[O.FLAGS])} at frame {int(st[O.STEP])}")
+            assert int(st[O.FLAGS]) != 0, i
+    for i in orc_only:
+        k = int(np.nonzero(idx == i)[0][0])
+        st = ow.init_state(i)
+        ow.run(i, st, max(0, int(states[k][O.STEP]) - 50))
+        sub = W.subset(w, [i])
+        with N.World(sub) as g1:
+            write_states(g1, [0], [H_round(st)], lambda _: J_of(i))
+            g1.step_n(150)
+            f1 = int(g1.read_state(N.F_FLAGS)[0])
+            s1 = int(g1.read_state(N.F_STEP)[0])
+        say(f"  robot {i}: oracle flag at frame {int(states[k][O.STEP])}; GPU from the oracle "
+            f"state 50 frames before: flags {f1} at frame {s1}")
+        assert f1 != 0, i
+    ok = ~gf & ~of
+    d_ref = np.linalg.norm(np.array([s[:2] for s in states]) - c0, axis=1)[ok]
+    d_gpu = np.linalg.norm(cog[:, idx].T - g_c0[:, idx].T, axis=1)[ok]
+    h_ref = np.array([s[O.TELE] for s in states])[ok] / n
+    h_gpu = tele[0, idx][ok] / n
+    for name, r, g in (("distance walked", d_ref, d_gpu), ("torso height", h_ref, h_gpu)):
+        dm = abs(g.mean() - r.mean())
+        se = np.std(g - r, ddof=1) / np.sqrt(len(r))
+        say(f"{name}: oracle mean {r.mean():.5f} gpu mean {g.mean():.5f} "
+            f"(diff {dm / abs(r.mean()):.2%}, 3 SE = {3 * se / abs(r.mean()):.2%}) over {len(r)} robots")
+        assert dm <= max(STAT_TOL * abs(r.mean()), 3 * se)
 
 
 def max_robot():
