@@ -201,6 +201,20 @@ npx_status npx_set_controller(npx_world* w, int kind, const float* params, size_
  * (a hipStream_t; NULL = default stream). */
 npx_status npx_step_n(npx_world* w, int64_t n, void* hip_stream);
 
+/* npx_step_n for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same frames, bit for bit, for the world's launch settings, with no
+ * allocation of any kind. Chunks of launch.chunk_steps frames are launched
+ * directly (no graph is instantiated); in persistent mode their task-queue
+ * counters, one per chunk, are a static device array of NPX_NOALLOC_MAX_CHUNKS
+ * ints that every GPU holds until the process ends, cleared by a fill kernel
+ * at the start of each call. All calls on one GPU share that array: calls
+ * that overlap on one GPU (concurrent streams, threads) race. Returns
+ * NPX_EINVAL when n needs more than NPX_NOALLOC_MAX_CHUNKS chunk launches
+ * (nothing is launched then), NPX_EHIP on a launch error. */
+#define NPX_NOALLOC_MAX_CHUNKS 4096
+npx_status npx_step_n_noalloc(npx_world* w, int64_t n, void* hip_stream);
+
 /* State fields, SoA [comp][n_instances]. */
 enum {
   NPX_F_COG = 0,        /* float [3][I]  world centre of gravity */

@@ -79,6 +79,8 @@ struct Shape {
 bool pick_shape(int G, int n_max, int l_max, Shape* out);
 hipError_t launch_step(const StepArgs& a, const Shape& s, int grid, hipStream_t stream);
 hipError_t launch_zero(int* p, hipStream_t stream);
+// Clears n ints on the stream with a fill kernel (graph-capturable).
+hipError_t launch_zero_n(int* p, int n, hipStream_t stream);
 // Max resident blocks of one wave per CU for a shape (occupancy query).
 int resident_blocks_per_cu(const Shape& s);
 

@@ -912,6 +912,11 @@ void step_kernel(const StepArgs a) {
 
 __global__ void zero_kernel(int* p) { *p = 0; }
 
+__global__ void zero_n_kernel(int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
 }  // namespace
 
 // The built shapes: (G, PPL, LPL).
@@ -969,6 +974,12 @@ int resident_blocks_per_cu(const Shape& s) {
 
 hipError_t launch_zero(int* p, hipStream_t stream) {
   hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(1), 0, stream, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_n(int* p, int n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_n_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, p, n);
   return hipGetLastError();
 }
 

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -169,7 +170,10 @@ npx_status sync_last(npx_world* w) {
 
 // Launches `steps` frames (state stays in registers) as one kernel, plus the
 // queue reset in persistent mode.
-hipError_t enqueue_chunk(npx_world* w, int steps, hipStream_t s) {
+// One launch of `steps` frames. In persistent mode the task-queue counter is
+// the world's own, cleared before the launch, or `cleared_queue`, a counter the
+// caller has already cleared on the stream.
+hipError_t enqueue_chunk(npx_world* w, int steps, hipStream_t s, int* cleared_queue = nullptr) {
   npx::StepArgs a = w->args;
   a.n_steps = steps;
   const int ipw = 64 / w->shape.G;
@@ -178,9 +182,13 @@ hipError_t enqueue_chunk(npx_world* w, int steps, hipStream_t s) {
   if (w->launch.persistent) {
     int per_cu = std::max(1, std::min(w->launch.waves_per_cu, npx::resident_blocks_per_cu(w->shape)));
     grid = std::min(a.n_blocks, per_cu * w->cu_count);
-    a.queue = w->queue;
-    hipError_t e = npx::launch_zero(w->queue, s);
-    if (e != hipSuccess) return e;
+    if (cleared_queue) {
+      a.queue = cleared_queue;
+    } else {
+      a.queue = w->queue;
+      hipError_t e = npx::launch_zero(w->queue, s);
+      if (e != hipSuccess) return e;
+    }
   } else {
     a.queue = nullptr;
   }
@@ -664,6 +672,70 @@ npx_status npx_step_n(npx_world* w, int64_t n, void* hip_stream) {
   if (n < 0) return fail(NPX_EINVAL, "n must be >= 0");
   if (n == 0) return NPX_OK;
   return run_steps(w, n, (hipStream_t)hip_stream);
+}
+
+// ---- stepping without allocation ---------------------------------------------
+//
+// The persistent-queue counters of npx_step_n_noalloc, one per chunk launch of
+// a call, live in this file-scope device array: every GPU the library runs on
+// holds its own copy until the process ends. Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the symbol):
+// the per-device address comes from hipGetSymbolAddress, taken once per device
+// with that device current.
+static __device__ __align__(256) int scratch[NPX_NOALLOC_MAX_CHUNKS];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int* g_scratch[kMaxDevices] = {};
+
+npx_status scratch_counters(int device, int** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(NPX_EINVAL, "device %d out of range", device);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[device]) {
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != device) HIP_TRY(hipSetDevice(device));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p)
+      return fail(NPX_EHIP, "hipGetSymbolAddress of the step counters: %s", hipGetErrorString(e));
+    g_scratch[device] = (int*)p;
+  }
+  *out = g_scratch[device];
+  return NPX_OK;
+}
+}  // namespace
+
+npx_status npx_step_n_noalloc(npx_world* w, int64_t n, void* hip_stream) {
+  if (!w) return fail(NPX_EINVAL, "null world");
+  if (n < 0) return fail(NPX_EINVAL, "n must be >= 0");
+  if (n == 0) return NPX_OK;
+  const int chunk = std::max(1, w->launch.chunk_steps);
+  const int64_t n_chunks = (n + chunk - 1) / chunk;
+  if (n_chunks > NPX_NOALLOC_MAX_CHUNKS)
+    return fail(NPX_EINVAL,
+                "npx_step_n_noalloc: %lld frames in chunks of %d need %lld launches; its static "
+                "counters hold %d (split the call or raise chunk_steps)",
+                (long long)n, chunk, (long long)n_chunks, NPX_NOALLOC_MAX_CHUNKS);
+  hipStream_t s = (hipStream_t)hip_stream;
+  int* q = nullptr;
+  if (w->launch.persistent) {
+    const npx_status rc = scratch_counters(w->device, &q);
+    if (rc != NPX_OK) return rc;
+    HIP_TRY(npx::launch_zero_n(q, (int)n_chunks, s));
+  }
+  int64_t left = n;
+  for (int64_t k = 0; left > 0; ++k) {
+    const int c = (int)std::min<int64_t>(left, chunk);
+    const hipError_t e = enqueue_chunk(w, c, s, q ? q + k : nullptr);
+    if (e != hipSuccess) return fail(NPX_EHIP, "step launch: %s", hipGetErrorString(e));
+    left -= c;
+  }
+  w->last_stream = s;
+  w->has_last_stream = true;
+  return NPX_OK;
 }
 
 npx_status npx_read_state(npx_world* w, int field, void* dst, size_t bytes, int on_device) {

@@ -93,6 +93,7 @@ def lib():
                                      C.POINTER(C.c_int32)]
         L.npx_set_controller.argtypes = [vp, C.c_int, vp, C.c_size_t, C.c_int]
         L.npx_step_n.argtypes = [vp, C.c_int64, vp]
+        L.npx_step_n_noalloc.argtypes = [vp, C.c_int64, vp]
         L.npx_read_state.argtypes = [vp, C.c_int, vp, C.c_size_t, C.c_int]
         L.npx_write_state.argtypes = [vp, C.c_int, vp, C.c_size_t, C.c_int]
         L.npx_read_points.argtypes = [vp, vp, C.c_size_t, C.c_int]
@@ -291,6 +292,11 @@ class World:
         """Advance n frames asynchronously on `stream` (a torch.cuda.Stream or raw handle)."""
         s = _stream_handle(stream)
         check(lib().npx_step_n(self.h, int(n), C.c_void_p(s)))
+
+    def step_n_noalloc(self, n, stream=None):
+        """npx_step_n without any allocation (direct launches, static counters)."""
+        s = _stream_handle(stream)
+        check(lib().npx_step_n_noalloc(self.h, int(n), C.c_void_p(s)))
 
     def _field_shape(self, field):
         I = self.n_instances
