@@ -321,7 +321,7 @@ double orc_height(const orc_params* p, double x, double y) {
 /* ------------------------------------------------------------------------- */
 
 typedef struct {
-  double margin_m, margin_rel;
+  double margin_m, margin_spread, margin_cap;
   orc_fragile* log;
   int log_cap, n_log;
   const orc_fragile* flips;
@@ -430,7 +430,8 @@ static int lsq_core(int n, const double* src, const double* dst, const double* w
   if (fc && n >= 2) {
     /* the spread is a difference of sums of size s2: its rounding scales with s2 */
     const double gap = fabs(spread - W * eps * eps), scale = W * eps * eps + s2;
-    if (gap < fc->margin_rel * scale) note_fragile(fc, ORC_FR_FIT, -1, ORC_FK_SPREAD, gap / scale);
+    if (gap < fc->margin_spread * scale)
+      note_fragile(fc, ORC_FR_FIT, -1, ORC_FK_SPREAD, gap / scale);
     if (is_flipped(fc, ORC_FR_FIT, -1, ORC_FK_SPREAD)) full = !full;
   }
   if (full && solve3(A, b, a)) return 3;
@@ -669,7 +670,7 @@ static int step_ws(const orc_morph* m, const orc_params* p, const float* ctrl, d
   int slipping = fit > 0 && lam < 1.0;
   if (fc && fit > 0 && !isinf(p->mu)) {
     const double gap = fabs(Ff - p->mu * F), scale = fmax(Ff, p->mu * F);
-    if (scale > 0.0 && gap < fc->margin_rel * scale)
+    if (scale > 0.0 && gap < fc->margin_cap * scale)
       note_fragile(fc, ORC_FR_FIT, -1, ORC_FK_CAP, gap / scale);
     if (is_flipped(fc, ORC_FR_FIT, -1, ORC_FK_CAP)) slipping = !slipping;
   }
@@ -773,15 +774,17 @@ int orc_step(const orc_morph* m, const orc_params* p, const float* ctrl, double*
 }
 
 int orc_step_ex(const orc_morph* m, const orc_params* p, const float* ctrl, double* st,
-                double* diag, double margin_m, double margin_rel, orc_fragile* log,
-                int log_cap, int* n_log, const orc_fragile* flips, int n_flips) {
+                double* diag, const double* margins, orc_fragile* log, int log_cap,
+                int* n_log, const orc_fragile* flips, int n_flips) {
   if (!morph_ok(m) || p->K < 1 || p->dt <= 0.0 || log_cap < 0 || n_flips < 0) return -1;
   work_t w;
   if (!work_alloc(&w, m->n_points)) {
     work_free(&w);
     return -1;
   }
-  fragile_ctx fc = {margin_m, margin_rel, log, log ? log_cap : 0, 0, flips, flips ? n_flips : 0};
+  fragile_ctx fc = {margins ? margins[0] : 0.0, margins ? margins[1] : 0.0,
+                    margins ? margins[2] : 0.0, log, log ? log_cap : 0, 0,
+                    flips, flips ? n_flips : 0};
   int rc = step_ws(m, p, ctrl, st, diag, &w, &fc);
   if (n_log) *n_log = fc.n_log;
   work_free(&w);

@@ -154,15 +154,17 @@ int orc_step(const orc_morph* m, const orc_params* p, const float* ctrl, double*
              double* diag);
 
 /* One step that also logs its fragile decisions: every look-up of a point at
- * or below the higher of the two cells' heights (plus margin_m) whose
- * coordinate lies within margin_m of a cell edge, every contact test with
- * |depth| < margin_m, and the fit's spread test and cap within margin_rel of
- * their thresholds. Up to log_cap entries go to log (n_log gets the count,
- * which may exceed log_cap). flips[0..n_flips) are decisions taken the other
- * way; margins of 0 and no flips give exactly orc_step. */
+ * or below the higher of the two cells' heights (plus margins[0] metres) whose
+ * coordinate lies within margins[0] of a cell edge, the telemetry look-up
+ * within margins[0] of an edge between cells of different height, every
+ * contact test with |depth| < margins[0], the fit's spread test within
+ * margins[1] (relative) of its threshold and the static-friction comparison
+ * within margins[2] (relative). Up to log_cap entries go to log (n_log gets
+ * the count, which may exceed log_cap). flips[0..n_flips) are decisions taken
+ * the other way; zero margins and no flips give exactly orc_step. */
 int orc_step_ex(const orc_morph* m, const orc_params* p, const float* ctrl, double* state,
-                double* diag, double margin_m, double margin_rel, orc_fragile* log,
-                int log_cap, int* n_log, const orc_fragile* flips, int n_flips);
+                double* diag, const double* margins, orc_fragile* log, int log_cap,
+                int* n_log, const orc_fragile* flips, int n_flips);
 
 /* n_steps steps of one instance. */
 int orc_run(const orc_morph* m, const orc_params* p, const float* ctrl, double* state,

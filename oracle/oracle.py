@@ -81,8 +81,8 @@ def lib():
         L.orc_init_state.argtypes = [C.POINTER(_Morph), C.POINTER(_Params), fp, fp, dp]
         L.orc_points.argtypes = [C.POINTER(_Morph), dp, dp]
         L.orc_step.argtypes = [C.POINTER(_Morph), C.POINTER(_Params), fp, dp, dp]
-        L.orc_step_ex.argtypes = [C.POINTER(_Morph), C.POINTER(_Params), fp, dp, dp, C.c_double,
-                                  C.c_double, C.POINTER(_Fragile), C.c_int, C.POINTER(C.c_int),
+        L.orc_step_ex.argtypes = [C.POINTER(_Morph), C.POINTER(_Params), fp, dp, dp, dp,
+                                  C.POINTER(_Fragile), C.c_int, C.POINTER(C.c_int),
                                   C.POINTER(_Fragile), C.c_int]
         L.orc_run.argtypes = [C.POINTER(_Morph), C.POINTER(_Params), fp, dp, C.c_long]
         L.orc_run_batch.argtypes = [C.c_int, C.POINTER(_Morph), C.POINTER(C.c_int),
@@ -203,12 +203,15 @@ class OracleWorld:
         assert rc == 0
         return d
 
-    def step_ex(self, i, st, margin_m=0.0, margin_rel=0.0, flips=(), diag=False, log_cap=256):
+    def step_ex(self, i, st, margin_m=0.0, margin_rel=0.0, flips=(), diag=False, log_cap=256,
+                margin_cap=None):
         """One step of instance i that logs its fragile decisions (look-ups
         within margin_m of a cell edge that could change a contact, contact
-        tests with |depth| < margin_m, fit thresholds within margin_rel) and
-        takes the decisions in `flips` the other way. Returns the log as
-        (stage, point, kind, distance) tuples (and the diagnostics if diag)."""
+        tests with |depth| < margin_m, the fit's spread test within margin_rel
+        and its static-friction comparison within margin_cap (default
+        margin_rel) of their thresholds) and takes the decisions in `flips` the
+        other way. Returns the log as (stage, point, kind, distance) tuples
+        (and the diagnostics if diag)."""
         m = self.morph_of(i)
         d = np.zeros(D_LEN) if diag else None
         log = (_Fragile * log_cap)()
@@ -216,10 +219,11 @@ class OracleWorld:
         fl = (_Fragile * max(1, len(flips)))()
         for k, f in enumerate(flips):
             fl[k] = _Fragile(int(f[0]), int(f[1]), int(f[2]), 0.0)
+        margins = np.array([margin_m, margin_rel,
+                            margin_rel if margin_cap is None else margin_cap], np.float64)
         rc = lib().orc_step_ex(C.byref(m.c), C.byref(self.params.c), _fptr(self.ctrl[i]),
-                               _dptr(st), _dptr(d) if diag else None, float(margin_m),
-                               float(margin_rel), log, int(log_cap), C.byref(n_log), fl,
-                               len(flips))
+                               _dptr(st), _dptr(d) if diag else None, _dptr(margins), log,
+                               int(log_cap), C.byref(n_log), fl, len(flips))
         assert rc == 0
         out = [(log[k].stage, log[k].point, log[k].kind, log[k].dist)
                for k in range(min(n_log.value, log_cap))]
