@@ -40,7 +40,8 @@ struct StepArgs {
   const int* pt_orig;     // [total points] index in the morphology's own point order
   const float* links;     // [total links][LINK_F]
   const int* link_parent; // [total links]
-  const int* link_depth;  // [total links]
+  const int* fk_task;     // chain-composition passes (row | link << 2 | parent << 9, -1 idle)
+  const int2* fk_info;    // [morphs][3] first entry and pass count for G = 16, 32, 64
   const float* ctrl;      // [n_inst][j_max][3] A f phi
   float dt, inv_dt;
   double dt_d;

@@ -111,9 +111,22 @@ enum Mode { kStep = 0, kPlace = 1, kPoints = 2 };
 // LDS rows of one link: [R row 0 | t0], [R row 1 | t1], [R row 2 | t2].
 using LinkT = float4[3];
 
+// A link's constants for one launch (LDS). With a the unit hinge axis, o the
+// anchor and K = [a]x (so K^2 = a a^T - 1): a and the upper limit; u = K o and
+// the lower limit; w = K^2 o and the controller's amplitude; a_x a_y, a_x a_z,
+// a_y a_z and its frequency; the diagonal of K^2 (a_i^2 - 1) and the link's
+// mass; the CoG; the inertia about the CoG (xx yy zz xy, then xz yz) with the
+// last two half extents of the box of the link's points; the box centre and
+// first half extent; the controller's phase in turns.
+struct LinkConst {
+  float4 ax_hi, u_lo, w_A, aa_f, kd_m, cog, I0, I1_box, box0;
+  double ph;
+};
+
 template <int G, int PPL, int LPL, int MODE, bool BIL>
 __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT, int* cand,
-                                          int* touch, int* lpar, int tb, int seg, int sl) {
+                                          int* touch, LinkConst* LK, int tb, int seg,
+                                          int sl) {
   constexpr int IPW = 64 / G;
   const int I = a.n_inst;
   const int task = tb * IPW + seg;
@@ -144,43 +157,36 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
     qp[l] = lj[l] ? st[(size_t)(BODY_ROWS + a.j_max + j) * I + inst] : 0.f;
   }
 
-  // ---- this lane's link constants, read once per launch: hinge anchor and
-  // unit axis, limits, mass, CoG and inertia, parent, and the
-  // joint's controller (amplitude, frequency, phase in turns)
-  float k_ao[LPL][3], k_ax[LPL][3], k_lo[LPL], k_hi[LPL], k_m[LPL], k_c[LPL][3], k_I[LPL][6];
-  float k_box[LPL][6];  // box of the link's points: centre, half extents
-  float k_A[LPL], k_f[LPL];
-  double k_ph[LPL];
-  int k_par[LPL];
+  // ---- this lane's link constants, staged in LDS once per launch (each lane
+  // writes and reads only its own links' entries, so no barrier is needed);
+  // held in registers they would be spilled under the 256-register cap
 #pragma unroll
   for (int l = 0; l < LPL; ++l) {
-    const float* lk = a.links + (size_t)lrow[l] * LINK_F;
-    float x = lk[3], y = lk[4], z = lk[5];
-    const float n2 = x * x + y * y + z * z;
-    const float inv = n2 > 0.f ? __builtin_amdgcn_rsqf(n2) : 0.f;
-    k_ax[l][0] = x * inv;
-    k_ax[l][1] = y * inv;
-    k_ax[l][2] = z * inv;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      k_ao[l][i] = lk[i];
-      k_c[l][i] = lk[LK_COG + i];
-    }
-#pragma unroll
-    for (int i = 0; i < 6; ++i) k_I[l][i] = lk[LK_INERTIA + i];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) k_box[l][i] = lk[LK_BOX + i];
-    k_lo[l] = lk[6];
-    k_hi[l] = lk[7];
-    k_m[l] = lk[LK_MASS];
-    k_par[l] = a.link_parent[lrow[l]];
-    if (lv[l]) lpar[sl + l * G] = k_par[l];  // read by descendants after the next barrier
     const int li = sl + l * G;
+    const float* lk = a.links + (size_t)lrow[l] * LINK_F;
+    const float n2 = lk[3] * lk[3] + lk[4] * lk[4] + lk[5] * lk[5];
+    const float inv = n2 > 0.f ? __builtin_amdgcn_rsqf(n2) : 0.f;
+    const float x = lk[3] * inv, y = lk[4] * inv, z = lk[5] * inv;
+    const float o[3] = {lk[0], lk[1], lk[2]};
+    const float ao = x * o[0] + y * o[1] + z * o[2];
     const float* cp = a.ctrl + ((size_t)inst * a.j_max + (lj[l] ? li - 1 : 0)) * 3;
-    k_A[l] = cp[0];
-    k_f[l] = cp[1];
-    k_ph[l] = (double)cp[2] * kInvTwoPi;
+    LinkConst k;
+    k.ax_hi = make_float4(x, y, z, lk[7]);
+    k.u_lo = make_float4(y * o[2] - z * o[1], z * o[0] - x * o[2], x * o[1] - y * o[0], lk[6]);
+    k.w_A = make_float4(x * ao - o[0], y * ao - o[1], z * ao - o[2], cp[0]);
+    k.aa_f = make_float4(x * y, x * z, y * z, cp[1]);
+    k.kd_m = make_float4(x * x - 1.f, y * y - 1.f, z * z - 1.f, lk[LK_MASS]);
+    k.cog = make_float4(lk[LK_COG], lk[LK_COG + 1], lk[LK_COG + 2], 0.f);
+    k.I0 = make_float4(lk[LK_INERTIA], lk[LK_INERTIA + 1], lk[LK_INERTIA + 2], lk[LK_INERTIA + 3]);
+    k.I1_box = make_float4(lk[LK_INERTIA + 4], lk[LK_INERTIA + 5], lk[LK_BOX + 4], lk[LK_BOX + 5]);
+    k.box0 = make_float4(lk[LK_BOX], lk[LK_BOX + 1], lk[LK_BOX + 2], lk[LK_BOX + 3]);
+    k.ph = (double)cp[2] * kInvTwoPi;
+    LK[li] = k;
   }
+  // chain-composition passes of this robot's morphology for G-lane segments
+  const int2 fki = a.fk_info[mi * 3 + (G == 16 ? 0 : (G == 32 ? 1 : 2))];
+  const int fk_np = valid ? fki.y : 0;
+  const int* fk_t = a.fk_task + fki.x + sl;
 
   // ---- the link of each of this lane's points (6 bits per slot, five slots
   // per register), read once per launch
@@ -220,25 +226,28 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
   // Forward kinematics at angles q, with the increment from angles q - dql
   // (dql = 0: no joint moved). Writes T, dT for every link of the segment.
   auto forward_kinematics = [&](const float* dql) __attribute__((always_inline)) {
-    // Each joint's own rotation about its hinge and its increment go into the
-    // link's LDS rows first; the level pass below then composes them in place
-    // with the parent's final transform, so they are not held in registers.
+    // Each joint's own transform about its hinge and its increment go into the
+    // link's LDS rows: with K = [a]x, the rotation is Rj = 1 + s K + (1 - c) K^2
+    // (Rodrigues) and its translation o - Rj o = -(s u + (1 - c) w). The
+    // increment over the last joint step, Rj(q) - Rj(q - dq) = -Rj(q) E with
+    // E = sin t K + (1 - cos t) K^2 at t = -dq, reduces by K^3 = -K to
+    // -(alpha K + beta K^2), alpha = sin t c - (1 - cos t) s,
+    // beta = sin t s + (1 - cos t) c, and moves the origin by alpha u + beta w.
 #pragma unroll
     for (int l = 0; l < LPL; ++l) {
-      const float ao[3] = {k_ao[l][0], k_ao[l][1], k_ao[l][2]};
-      const float x = k_ax[l][0], y = k_ax[l][1], z = k_ax[l][2];
-      // Rj = cos 1 + sin K + (1 - cos) a a^T with K = [a]x (Rodrigues)
+      const int li = sl + l * G;
+      const float4 k0 = LK[li].ax_hi, k1 = LK[li].u_lo, k2 = LK[li].w_A;
+      const float4 k3 = LK[li].aa_f, k4 = LK[li].kd_m;
+      const float x = k0.x, y = k0.y, z = k0.z;
+      const float xy = k3.x, xz = k3.y, yz = k3.z;
       float s, co;
       sin_cos(q[l], &s, &co);
       const float C1 = 1.f - co;
-      const float R0[9] = {co + x * x * C1,    x * y * C1 - z * s, x * z * C1 + y * s,
-                           y * x * C1 + z * s, co + y * y * C1,    y * z * C1 - x * s,
-                           z * x * C1 - y * s, z * y * C1 + x * s, co + z * z * C1};
-      // increment Rj(q) - Rj(q - dq) = -Rj(q) E(-dq), E(t) = sin t K + (1 - cos t) K^2,
-      // K^2 = a a^T - 1, with 1 - cos t = 2 sin^2(t/2) to keep small angles exact
+      const float sx = s * x, sy = s * y, sz = s * z;
       // the joint increment is a fraction of a degree per frame: below 0.1 rad
       // sin t = t (1 - t^2/6 (1 - t^2/20)) and 1 - cos t = t^2/2 (1 - t^2/12
-      // (1 - t^2/30)) to float32 precision (the next terms are 1e-10 relative)
+      // (1 - t^2/30)) to float32 precision (the next terms are 1e-10 relative);
+      // 1 - cos t = 2 sin^2(t/2) above keeps it exact for larger steps
       float se, ve;
       const float tq = -dql[l];
       if (!__any(!(fabsf(tq) < 0.1f))) {
@@ -251,30 +260,21 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
         sin_cos(0.5f * tq, &sh, &ch);
         ve = 2.f * sh * sh;
       }
-      const float E[9] = {ve * (x * x - 1.f), ve * x * y - se * z,  ve * x * z + se * y,
-                          ve * y * x + se * z, ve * (y * y - 1.f),  ve * y * z - se * x,
-                          ve * z * x - se * y, ve * z * y + se * x, ve * (z * z - 1.f)};
-      float dRj[9], tj[3], dtj[3];
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-          dRj[3 * i + k] =
-              -(R0[3 * i] * E[k] + R0[3 * i + 1] * E[3 + k] + R0[3 * i + 2] * E[6 + k]);
-      }
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        tj[i] = ao[i] - (R0[3 * i] * ao[0] + R0[3 * i + 1] * ao[1] + R0[3 * i + 2] * ao[2]);
-        dtj[i] = -(dRj[3 * i] * ao[0] + dRj[3 * i + 1] * ao[1] + dRj[3 * i + 2] * ao[2]);
-      }
-      const int li = sl + l * G;
+      const float al = se * co - ve * s, be = se * s + ve * co;
+      const float ax_ = al * x, ay_ = al * y, az_ = al * z;
       if (lj[l]) {
-        T[li][0] = make_float4(R0[0], R0[1], R0[2], tj[0]);
-        T[li][1] = make_float4(R0[3], R0[4], R0[5], tj[1]);
-        T[li][2] = make_float4(R0[6], R0[7], R0[8], tj[2]);
-        dT[li][0] = make_float4(dRj[0], dRj[1], dRj[2], dtj[0]);
-        dT[li][1] = make_float4(dRj[3], dRj[4], dRj[5], dtj[1]);
-        dT[li][2] = make_float4(dRj[6], dRj[7], dRj[8], dtj[2]);
+        T[li][0] = make_float4(fmaf(C1, k4.x, 1.f), fmaf(C1, xy, -sz), fmaf(C1, xz, sy),
+                               -(s * k1.x + C1 * k2.x));
+        T[li][1] = make_float4(fmaf(C1, xy, sz), fmaf(C1, k4.y, 1.f), fmaf(C1, yz, -sx),
+                               -(s * k1.y + C1 * k2.y));
+        T[li][2] = make_float4(fmaf(C1, xz, -sy), fmaf(C1, yz, sx), fmaf(C1, k4.z, 1.f),
+                               -(s * k1.z + C1 * k2.z));
+        dT[li][0] = make_float4(-be * k4.x, fmaf(-be, xy, az_), fmaf(-be, xz, -ay_),
+                                al * k1.x + be * k2.x);
+        dT[li][1] = make_float4(fmaf(-be, xy, -az_), -be * k4.y, fmaf(-be, yz, ax_),
+                                al * k1.y + be * k2.y);
+        dT[li][2] = make_float4(fmaf(-be, xz, ay_), fmaf(-be, yz, -ax_), -be * k4.z,
+                                al * k1.z + be * k2.z);
       }
     }
     if (sl == 0) {
@@ -283,87 +283,39 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
       T[0][2] = make_float4(0.f, 0.f, 1.f, 0.f);
       dT[0][0] = dT[0][1] = dT[0][2] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    // Each link's transform and increment from its own joint transform and its
-    // ancestors', composed up the chain by left-multiplying with the next
-    // ancestor (A, dA):  R <- Ra R,  t <- Ra t + ta,  dR <- dRa R + (Ra - dRa) dR,
-    // dt <- dRa t + dta + (Ra - dRa) dt.  A link at depth d needs d - 1 steps;
-    // only joint transforms are read, so one barrier separates the phases.
-    __syncthreads();
-    float cR[LPL][9], ct[LPL][3], cdR[LPL][9], cdt[LPL][3];
-#pragma unroll
-    for (int l = 0; l < LPL; ++l) {
-      const int li = sl + l * G;
-      const float4 j0 = T[li][0], j1 = T[li][1], j2 = T[li][2];
-      const float4 e0 = dT[li][0], e1 = dT[li][1], e2 = dT[li][2];
-      const float R0[9] = {j0.x, j0.y, j0.z, j1.x, j1.y, j1.z, j2.x, j2.y, j2.z};
-      const float dR0[9] = {e0.x, e0.y, e0.z, e1.x, e1.y, e1.z, e2.x, e2.y, e2.z};
-#pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        cR[l][i] = R0[i];
-        cdR[l][i] = dR0[i];
+    // Links of depth 1 hang from the torso (identity): their joint transform
+    // is final. Deeper links, level by level, one matrix row per lane: row i of
+    // the link's transform and increment from row i of the parent's final ones
+    // (P, dP) and the link's joint transform (J, dJ):
+    //   T_i = P_i J,  dT_i = dP_i J + (P_i - dP_i) dJ   (3x4 rows, affine).
+    // A lane reads the whole J before any lane of the wave writes a row of it,
+    // and the next pass reads what this one wrote, so program order within the
+    // wave is the only ordering needed.
+    __builtin_amdgcn_wave_barrier();
+    int fk_next = fk_np > 0 ? fk_t[0] : -1;
+    for (int p = 0; __any(p < fk_np); ++p) {
+      const int task = fk_next;
+      fk_next = p + 1 < fk_np ? fk_t[(p + 1) * G] : -1;
+      if (task >= 0) {
+        const int i = task & 3, lk = (task >> 2) & 127, pa = task >> 9;
+        const float4 P = T[pa][i], dP = dT[pa][i];
+        const float4 j0 = T[lk][0], j1 = T[lk][1], j2 = T[lk][2];
+        const float4 e0 = dT[lk][0], e1 = dT[lk][1], e2 = dT[lk][2];
+        const float ox = P.x - dP.x, oy = P.y - dP.y, oz = P.z - dP.z;
+        const float4 r = make_float4(P.x * j0.x + P.y * j1.x + P.z * j2.x,
+                                     P.x * j0.y + P.y * j1.y + P.z * j2.y,
+                                     P.x * j0.z + P.y * j1.z + P.z * j2.z,
+                                     P.x * j0.w + P.y * j1.w + P.z * j2.w + P.w);
+        const float4 d = make_float4(
+            dP.x * j0.x + dP.y * j1.x + dP.z * j2.x + ox * e0.x + oy * e1.x + oz * e2.x,
+            dP.x * j0.y + dP.y * j1.y + dP.z * j2.y + ox * e0.y + oy * e1.y + oz * e2.y,
+            dP.x * j0.z + dP.y * j1.z + dP.z * j2.z + ox * e0.z + oy * e1.z + oz * e2.z,
+            dP.x * j0.w + dP.y * j1.w + dP.z * j2.w + ox * e0.w + oy * e1.w + oz * e2.w + dP.w);
+        T[lk][i] = r;
+        dT[lk][i] = d;
       }
-      ct[l][0] = j0.w;
-      ct[l][1] = j1.w;
-      ct[l][2] = j2.w;
-      cdt[l][0] = e0.w;
-      cdt[l][1] = e1.w;
-      cdt[l][2] = e2.w;
-      int anc = lj[l] ? k_par[l] : 0;
-      for (int it = 1; it < a.max_depth; ++it) {
-        if (anc >= 1) {
-          const float4 p0 = T[anc][0], p1 = T[anc][1], p2 = T[anc][2];
-          const float4 d0 = dT[anc][0], d1 = dT[anc][1], d2 = dT[anc][2];
-          const float Ra[9] = {p0.x, p0.y, p0.z, p1.x, p1.y, p1.z, p2.x, p2.y, p2.z};
-          const float ta[3] = {p0.w, p1.w, p2.w};
-          const float dRa[9] = {d0.x, d0.y, d0.z, d1.x, d1.y, d1.z, d2.x, d2.y, d2.z};
-          const float dta[3] = {d0.w, d1.w, d2.w};
-          float R[9], t[3], dR[9], dtt[3];
-#pragma unroll
-          for (int i = 0; i < 3; ++i) {
-            const float Po[3] = {Ra[3 * i] - dRa[3 * i], Ra[3 * i + 1] - dRa[3 * i + 1],
-                                 Ra[3 * i + 2] - dRa[3 * i + 2]};
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-              R[3 * i + k] = Ra[3 * i] * cR[l][k] + Ra[3 * i + 1] * cR[l][3 + k] +
-                             Ra[3 * i + 2] * cR[l][6 + k];
-              dR[3 * i + k] = dRa[3 * i] * cR[l][k] + dRa[3 * i + 1] * cR[l][3 + k] +
-                              dRa[3 * i + 2] * cR[l][6 + k] + Po[0] * cdR[l][k] +
-                              Po[1] * cdR[l][3 + k] + Po[2] * cdR[l][6 + k];
-            }
-            t[i] = Ra[3 * i] * ct[l][0] + Ra[3 * i + 1] * ct[l][1] + Ra[3 * i + 2] * ct[l][2] +
-                   ta[i];
-            dtt[i] = dRa[3 * i] * ct[l][0] + dRa[3 * i + 1] * ct[l][1] +
-                     dRa[3 * i + 2] * ct[l][2] + Po[0] * cdt[l][0] + Po[1] * cdt[l][1] +
-                     Po[2] * cdt[l][2] + dta[i];
-          }
-#pragma unroll
-          for (int i = 0; i < 9; ++i) {
-            cR[l][i] = R[i];
-            cdR[l][i] = dR[i];
-          }
-#pragma unroll
-          for (int i = 0; i < 3; ++i) {
-            ct[l][i] = t[i];
-            cdt[l][i] = dtt[i];
-          }
-          anc = lpar[anc];
-        }
-      }
+      __builtin_amdgcn_wave_barrier();
     }
-    __syncthreads();
-#pragma unroll
-    for (int l = 0; l < LPL; ++l) {
-      const int li = sl + l * G;
-      if (lj[l]) {
-        T[li][0] = make_float4(cR[l][0], cR[l][1], cR[l][2], ct[l][0]);
-        T[li][1] = make_float4(cR[l][3], cR[l][4], cR[l][5], ct[l][1]);
-        T[li][2] = make_float4(cR[l][6], cR[l][7], cR[l][8], ct[l][2]);
-        dT[li][0] = make_float4(cdR[l][0], cdR[l][1], cdR[l][2], cdt[l][0]);
-        dT[li][1] = make_float4(cdR[l][3], cdR[l][4], cdR[l][5], cdt[l][1]);
-        dT[li][2] = make_float4(cdR[l][6], cdR[l][7], cdR[l][8], cdt[l][2]);
-      }
-    }
-    __syncthreads();
     // mass properties: over links, m p, R I R^T + m (|p|^2 1 - p p^T), and m dp
     float acc[12];
 #pragma unroll
@@ -375,8 +327,9 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
         const float4 r0 = T[li][0], r1 = T[li][1], r2 = T[li][2];
         const float4 d0 = dT[li][0], d1 = dT[li][1], d2 = dT[li][2];
         const float R[9] = {r0.x, r0.y, r0.z, r1.x, r1.y, r1.z, r2.x, r2.y, r2.z};
-        const float lc[3] = {k_c[l][0], k_c[l][1], k_c[l][2]};
-        const float m = k_m[l];
+        const float4 cm = LK[li].cog, i0 = LK[li].I0, i1 = LK[li].I1_box;
+        const float lc[3] = {cm.x, cm.y, cm.z};
+        const float m = LK[li].kd_m.w;
         float p[3];
         p[0] = R[0] * lc[0] + R[1] * lc[1] + R[2] * lc[2] + r0.w;
         p[1] = R[3] * lc[0] + R[4] * lc[1] + R[5] * lc[2] + r1.w;
@@ -388,7 +341,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
         acc[10] += m * (d1.x * lc[0] + d1.y * lc[1] + d1.z * lc[2] + d1.w);
         acc[11] += m * (d2.x * lc[0] + d2.y * lc[1] + d2.z * lc[2] + d2.w);
         // A = R I (I symmetric: xx yy zz xy xz yz)
-        const float* S = k_I[l];
+        const float S[6] = {i0.x, i0.y, i0.z, i0.w, i1.x, i1.y};
         const float Ifull[9] = {S[0], S[3], S[4], S[3], S[1], S[5], S[4], S[5], S[2]};
         float A[9];
 #pragma unroll
@@ -451,8 +404,9 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
   // S0: commanded angle of this lane's joints at frame n, clamped to the limits
   auto command = [&](int l) __attribute__((always_inline)) {
     const double t = (double)n * a.dt_d;
-    const float qh = k_A[l] * sin_turns((double)k_f[l] * t + k_ph[l]);
-    return lj[l] ? fminf(fmaxf(qh, k_lo[l]), k_hi[l]) : 0.f;
+    const int li = sl + l * G;
+    const float qh = LK[li].w_A.w * sin_turns((double)LK[li].aa_f.w * t + LK[li].ph);
+    return lj[l] ? fminf(fmaxf(qh, LK[li].u_lo.w), LK[li].ax_hi.w) : 0.f;
   };
 
   float dql[LPL];
@@ -745,7 +699,8 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
       const int li = sl + l * G;
       if (lv[l]) {
         const float4 r0 = T[li][0], r1 = T[li][1], r2 = T[li][2];
-        const float* bx = k_box[l];
+        const float4 b0 = LK[li].box0, b1 = LK[li].I1_box;
+        const float bx[6] = {b0.x, b0.y, b0.z, b0.w, b1.z, b1.w};
         const float y0 = r0.x * bx[0] + r0.y * bx[1] + r0.z * bx[2] + r0.w - gb[0];
         const float y1 = r1.x * bx[0] + r1.y * bx[1] + r1.z * bx[2] + r1.w - gb[1];
         const float y2 = r2.x * bx[0] + r2.y * bx[1] + r2.z * bx[2] + r2.w - gb[2];
@@ -889,7 +844,7 @@ void step_kernel(const StepArgs a) {
   __shared__ LinkT dT[IPW][LMAX];
   __shared__ int cand[IPW][G * PPL];  // contact points of a frame, compacted
   __shared__ int touch[IPW][LMAX];    // links that may reach the ground this frame
-  __shared__ int lpar[IPW][LMAX];     // parent of every link of the robot
+  __shared__ LinkConst LK[IPW][LMAX]; // constants of every link of the robot
   const int lane = threadIdx.x;
   const int seg = lane / G;
   const int sl = lane - seg * G;
@@ -904,8 +859,8 @@ void step_kernel(const StepArgs a) {
       tb = blockIdx.x;
     }
     if (tb >= a.n_blocks) break;
-    run_block<G, PPL, LPL, MODE, BIL>(a, T[seg], dT[seg], cand[seg], touch[seg], lpar[seg], tb, seg,
-                                 sl);
+    run_block<G, PPL, LPL, MODE, BIL>(a, T[seg], dT[seg], cand[seg], touch[seg], LK[seg], tb,
+                                      seg, sl);
     __syncthreads();
   }
 }

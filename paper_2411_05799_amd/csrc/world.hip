@@ -75,7 +75,8 @@ struct npx_world {
   int* pt_orig = nullptr;  // [total points] index of each point in its morphology's own order
   float* links = nullptr;
   int* link_parent = nullptr;
-  int* link_depth = nullptr;
+  int* fk_task = nullptr;   // row-composition schedule of the step kernel (see fk_schedule)
+  int2* fk_info = nullptr;  // [morphs][3] (first entry, passes) for segments of 16, 32, 64 lanes
   float* ctrl = nullptr;
   float* hf = nullptr;
   int* order = nullptr;
@@ -244,6 +245,39 @@ std::vector<int> task_order(const npx_world* w) {
   return ord;
 }
 
+// Schedule of the step kernel's chain composition for one morphology: links
+// of depth >= 2 take their final transform as parent's final transform times
+// their own joint transform, one matrix row per lane, level by level (a level
+// needs its parents' level done). For each segment width G in {16, 32, 64}
+// a level's links fill passes of G lanes, at most G / 3 links (three rows
+// each) per pass: the rows of one link share a pass, since each row's lane
+// reads the whole joint transform that the link's lanes then overwrite. An
+// entry is row | link << 2 | parent << 9, or -1 for an idle lane. fki gets
+// (first entry, pass count) per width.
+void fk_schedule(const npx_morph_tables& m, const std::vector<int>& depth, std::vector<int>& fkt,
+                 std::vector<int2>& fki) {
+  int dmax = 0;
+  for (int l = 0; l < m.n_links; ++l) dmax = std::max(dmax, depth[l]);
+  for (int G : {16, 32, 64}) {
+    const int first = (int)fkt.size();
+    int passes = 0;
+    for (int d = 2; d <= dmax; ++d) {
+      std::vector<int> lv;
+      for (int l = 1; l < m.n_links; ++l)
+        if (depth[l] == d) lv.push_back(l);
+      const size_t per = G / 3;
+      for (size_t l0 = 0; l0 < lv.size(); l0 += per, ++passes)
+        for (int k = 0; k < G; ++k) {
+          const size_t t = l0 + k / 3;
+          fkt.push_back(k / 3 < (int)per && t < lv.size()
+                            ? (k % 3) | (lv[t] << 2) | (m.parent[lv[t]] << 9)
+                            : -1);
+        }
+    }
+    fki.push_back(make_int2(first, passes));
+  }
+}
+
 npx_status check_tables(const npx_morph_tables& m, int idx) {
   if (m.n_points <= 0 || m.n_points > NPX_MAX_POINTS)
     return fail(NPX_EINVAL, "morph %d: n_points %d out of [1, %d]", idx, m.n_points, NPX_MAX_POINTS);
@@ -343,7 +377,8 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   std::vector<int4> info(d->n_morphs);
   std::vector<float> mass(d->n_morphs);
   std::vector<float4> pts;
-  std::vector<int> ptl, pto, par, dep;
+  std::vector<int> ptl, pto, par, fkt;
+  std::vector<int2> fki;
   std::vector<std::vector<int>> slot_of(d->n_morphs);  // position of each point in pts
   std::vector<float> lk;
   for (int mi = 0; mi < d->n_morphs; ++mi) {
@@ -410,7 +445,6 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
     for (int l = 0; l < m.n_links; ++l) {
       w->max_depth = std::max(w->max_depth, depth[l]);
       par.push_back(m.parent[l]);
-      dep.push_back(depth[l]);
       const float* j = m.joint + 8 * l;
       float row[npx::LINK_F];
       for (int i = 0; i < 8; ++i) row[i] = l == 0 ? 0.f : j[i];
@@ -435,6 +469,7 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
       }
       lk.insert(lk.end(), row, row + npx::LINK_F);
     }
+    fk_schedule(m, depth, fkt, fki);
   }
   w->j_max = std::max(1, w->l_max - 1);
   // points grouped by link (stable), for per-link sums outside the step kernel
@@ -485,7 +520,9 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   ALLOC(w->pt_orig, pto.size());
   ALLOC(w->links, lk.size());
   ALLOC(w->link_parent, par.size());
-  ALLOC(w->link_depth, dep.size());
+  if (fkt.empty()) fkt.push_back(-1);  // no link deeper than 1: no passes, one unread entry
+  ALLOC(w->fk_task, fkt.size());
+  ALLOC(w->fk_info, fki.size());
   ALLOC(w->ctrl, I * w->j_max * 3);
   ALLOC(w->hf, (size_t)d->hf_nx * d->hf_ny);
   ALLOC(w->order, I);
@@ -509,7 +546,8 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   H2D(w->pt_orig, pto.data(), pto.size() * sizeof(int));
   H2D(w->links, lk.data(), lk.size() * sizeof(float));
   H2D(w->link_parent, par.data(), par.size() * sizeof(int));
-  H2D(w->link_depth, dep.data(), dep.size() * sizeof(int));
+  H2D(w->fk_task, fkt.data(), fkt.size() * sizeof(int));
+  H2D(w->fk_info, fki.data(), fki.size() * sizeof(int2));
   H2D(w->lp_off, lpo.data(), lpo.size() * sizeof(int));
   H2D(w->lp_idx, lpi.data(), lpi.size() * sizeof(int));
   w->lp_off_host = lpo;
@@ -543,7 +581,8 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   a.pt_orig = w->pt_orig;
   a.links = w->links;
   a.link_parent = w->link_parent;
-  a.link_depth = w->link_depth;
+  a.fk_task = w->fk_task;
+  a.fk_info = w->fk_info;
   a.ctrl = w->ctrl;
   a.dt = (float)d->dt;
   a.inv_dt = (float)(1.0 / d->dt);
@@ -619,7 +658,7 @@ void npx_destroy_world(npx_world* w) {
   if (w->capture_stream) (void)hipStreamDestroy(w->capture_stream);
   void* bufs[] = {w->st, w->step, w->flags, w->tele, w->inst_morph_d, w->morph_info,
                   w->morph_mass, w->pts, w->pt_link, w->pt_orig, w->links, w->link_parent,
-                  w->link_depth, w->ctrl, w->hf, w->order, w->queue, w->lp_off,
+                  w->fk_task, w->fk_info, w->ctrl, w->hf, w->order, w->queue, w->lp_off,
                   w->lp_idx, w->sub_mask, w->rays, w->ray_link, w->ray_info,
                   w->foot_pairs, w->foot_info};
   for (void* b : bufs)
