@@ -58,7 +58,8 @@ __device__ __forceinline__ void quat_to_mat(float w, float x, float y, float z, 
 // exact floor for the point's own position, where float32 rounding of
 // s (x - x0) would move points lying within ~1e-6 m of a cell edge across it.
 // The coordinate is first held in [lo, hi] (float32 bounds chosen on the host
-// half a cell outside the first and last cell edges; fmaxf sends a NaN to lo),
+// half a cell outside the first and last cell edges) by one median-of-three
+// (which takes a NaN coordinate to the smaller bound, lo),
 // so the scaled value u = s x - s x0 (one FMA against the host's double
 // -s x0) lies in about [-1/2, n - 1/2] and its truncation towards zero is the
 // clamped floor.
@@ -69,7 +70,7 @@ struct HfAxis {
 };
 
 __device__ __forceinline__ int hf_index(float x, const HfAxis& ax) {
-  const float xc = fminf(fmaxf(x, ax.lo), ax.hi);
+  const float xc = __builtin_amdgcn_fmed3f(x, ax.lo, ax.hi);
   return (int)fma((double)xc, ax.s, ax.ms0);
 }
 

@@ -32,8 +32,10 @@
 // and with two or three contact points that noise dominates the fitted
 // rotation. The slip is therefore built from increments that float32 holds
 // accurately: the joint-angle increment is pushed down the link tree as a
-// transform increment dT (forward kinematics of the change), and the body
-// rotation increment comes straight from the rotation quaternion:
+// transform increment dT (forward kinematics of the change; the CoG's own move
+// in the body frame, one offset shared by every point, is the difference of
+// the two CoGs), and the body rotation increment comes straight from the
+// rotation quaternion:
 //   delta = (R1 - R) r_old + R1 dr + (c1 - c),  R1 - R = (R(dq) - I) R.
 #include "npx_device.h"
 #include "npx_internal.h"
@@ -48,10 +50,10 @@ __device__ __forceinline__ float dpp(float x) {
       float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
 }
 
-__device__ __forceinline__ float swap_sum16(float x) {
-  auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, x),
-                                            __builtin_bit_cast(unsigned, x), false, false);
-  return __builtin_bit_cast(float, (unsigned)r[0]) + __builtin_bit_cast(float, (unsigned)r[1]);
+// The value of the lane 16 apart within the 32-lane half (LDS crossbar, no
+// VALU move): swizzle with and-mask 31, xor-mask 16.
+__device__ __forceinline__ float xor16(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, x), 0x401F));
 }
 
 __device__ __forceinline__ float swap_sum32(float x) {
@@ -60,20 +62,40 @@ __device__ __forceinline__ float swap_sum32(float x) {
   return __builtin_bit_cast(float, (unsigned)r[0]) + __builtin_bit_cast(float, (unsigned)r[1]);
 }
 
-// Sum over the G-lane segment, result in every lane of it: lanes exchange with
-// quad partners, then the mirrored half-row and row (DPP), then the other row
-// (permlane16 swap) and the other half-wave (permlane32 swap). Each step adds
-// two operands in an order every lane shares.
+// Sums over the G-lane segment of N values at once, results in every lane of
+// it: lanes exchange with quad partners, then the mirrored half-row and row
+// (DPP), then the other row (swizzle) and the other half-wave (permlane32
+// swap). Each step adds two operands in an order every lane shares, and takes
+// all N values before the next step, so no add waits on the one before.
+template <int G, int N>
+__device__ __forceinline__ void seg_sum_n(float (&x)[N]) {
+  static_assert(G == 16 || G == 32 || G == 64, "segment of 16, 32 or 64 lanes");
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] += dpp<0xB1>(x[i]);   // quad_perm [1,0,3,2]
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] += dpp<0x4E>(x[i]);   // quad_perm [2,3,0,1]
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] += dpp<0x141>(x[i]);  // row_half_mirror
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] += dpp<0x140>(x[i]);  // row_mirror
+  if constexpr (G >= 32) {
+    float o[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) o[i] = xor16(x[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] += o[i];
+  }
+  if constexpr (G >= 64) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = swap_sum32(x[i]);
+  }
+}
+
 template <int G>
 __device__ __forceinline__ float seg_sum(float x) {
-  static_assert(G == 16 || G == 32 || G == 64, "segment of 16, 32 or 64 lanes");
-  x += dpp<0xB1>(x);   // quad_perm [1,0,3,2]
-  x += dpp<0x4E>(x);   // quad_perm [2,3,0,1]
-  x += dpp<0x141>(x);  // row_half_mirror
-  x += dpp<0x140>(x);  // row_mirror
-  if constexpr (G >= 32) x = swap_sum16(x);
-  if constexpr (G >= 64) x = swap_sum32(x);
-  return x;
+  float v[1] = {x};
+  seg_sum_n<G>(v);
+  return v[0];
 }
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -221,7 +243,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
   // not kept: a point is rebuilt from its construction-frame position and its
   // link's transform in LDS where it is needed, which keeps the registers of a
   // lane independent of its point count
-  float gb[3], dgb[3], Ib[6], Iinv[6];
+  float gb[3] = {0.f, 0.f, 0.f}, dgb[3], Ib[6], Iinv[6];
 
   // Forward kinematics at angles q, with the increment from angles q - dql
   // (dql = 0: no joint moved). Writes T, dT for every link of the segment.
@@ -316,16 +338,15 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
       }
       __builtin_amdgcn_wave_barrier();
     }
-    // mass properties: over links, m p, R I R^T + m (|p|^2 1 - p p^T), and m dp
-    float acc[12];
+    // mass properties: over links, m p and R I R^T + m (|p|^2 1 - p p^T)
+    float acc[9];
 #pragma unroll
-    for (int i = 0; i < 12; ++i) acc[i] = 0.f;
+    for (int i = 0; i < 9; ++i) acc[i] = 0.f;
 #pragma unroll
     for (int l = 0; l < LPL; ++l) {
       if (lv[l]) {
         const int li = sl + l * G;
         const float4 r0 = T[li][0], r1 = T[li][1], r2 = T[li][2];
-        const float4 d0 = dT[li][0], d1 = dT[li][1], d2 = dT[li][2];
         const float R[9] = {r0.x, r0.y, r0.z, r1.x, r1.y, r1.z, r2.x, r2.y, r2.z};
         const float4 cm = LK[li].cog, i0 = LK[li].I0, i1 = LK[li].I1_box;
         const float lc[3] = {cm.x, cm.y, cm.z};
@@ -337,9 +358,6 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
         acc[0] += m * p[0];
         acc[1] += m * p[1];
         acc[2] += m * p[2];
-        acc[9] += m * (d0.x * lc[0] + d0.y * lc[1] + d0.z * lc[2] + d0.w);
-        acc[10] += m * (d1.x * lc[0] + d1.y * lc[1] + d1.z * lc[2] + d1.w);
-        acc[11] += m * (d2.x * lc[0] + d2.y * lc[1] + d2.z * lc[2] + d2.w);
         // A = R I (I symmetric: xx yy zz xy xz yz)
         const float S[6] = {i0.x, i0.y, i0.z, i0.w, i1.x, i1.y};
         const float Ifull[9] = {S[0], S[3], S[4], S[3], S[1], S[5], S[4], S[5], S[2]};
@@ -360,12 +378,15 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
         acc[8] += A[3] * R[6] + A[4] * R[7] + A[5] * R[8] - m * p[1] * p[2];
       }
     }
-#pragma unroll
-    for (int i = 0; i < 12; ++i) acc[i] = seg_sum<G>(acc[i]);
+    seg_sum_n<G>(acc);
+    // the CoG's move in the body frame over the joint step, from the CoG
+    // before it: both are rounded sums of a few centimetres (a few 1e-9 m),
+    // the same offset for every point of the friction set
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      gb[i] = acc[i] * invM;
-      dgb[i] = acc[9 + i] * invM;
+      const float g = acc[i] * invM;
+      dgb[i] = g - gb[i];
+      gb[i] = g;
     }
     const float gg = gb[0] * gb[0] + gb[1] * gb[1] + gb[2] * gb[2];
     Ib[0] = acc[3] - M * (gg - gb[0] * gb[0]);
@@ -598,14 +619,12 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
           Cd += wk * (sx * dy - sy * dx);
         }
       }
-      mn = seg_sum<G>(mn);
+      {
+        float m7[7] = {mn, Sx, Sy, S2, Dx, Dy, Cd};
+        seg_sum_n<G>(m7);
+        mn = m7[0]; Sx = m7[1]; Sy = m7[2]; S2 = m7[3]; Dx = m7[4]; Dy = m7[5]; Cd = m7[6];
+      }
       const float Wn = a.fric_w ? seg_sum<G>(Wt) : mn;  // total weight (count if unweighted)
-      Sx = seg_sum<G>(Sx);
-      Sy = seg_sum<G>(Sy);
-      S2 = seg_sum<G>(S2);
-      Dx = seg_sum<G>(Dx);
-      Dy = seg_sum<G>(Dy);
-      Cd = seg_sum<G>(Cd);
 
       // S6 closed form of eqs. (4)-(6) and S7 static-friction cap. In these
       // moments a3 = [sum xi x delta - (Sx Dy - Sy Dx)/n] / (sum |xi|^2 - |S|^2/n),
@@ -751,10 +770,11 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
       if (__ballot(hit) != 0ull) kap_slots |= 1u << p;
       group_fence(p);
     }
-    F = seg_sum<G>(F);
-    tx = seg_sum<G>(tx);
-    ty = seg_sum<G>(ty);
-    nc = seg_sum<G>(nc);
+    {
+      float f4[4] = {F, tx, ty, nc};
+      seg_sum_n<G>(f4);
+      F = f4[0]; tx = f4[1]; ty = f4[2]; nc = f4[3];
+    }
 
     // S3: joint-angle determination every K frames (c, Q, v, w kept)
     const bool upd = (n % a.K) == 0;
