@@ -44,12 +44,20 @@ __device__ __forceinline__ float sin_turns(double t) {
   return s;
 }
 
+// Every sum is an explicit fused multiply-add on a lone product, so no two
+// inlined copies can contract differently: the matrix of a quaternion has
+// the same bits wherever it is computed.
 __device__ __forceinline__ void quat_to_mat(float w, float x, float y, float z, float R[9]) {
-  float xx = x * x, yy = y * y, zz = z * z;
-  float xy = x * y, xz = x * z, yz = y * z, wx = w * x, wy = w * y, wz = w * z;
-  R[0] = 1.f - 2.f * (yy + zz); R[1] = 2.f * (xy - wz);       R[2] = 2.f * (xz + wy);
-  R[3] = 2.f * (xy + wz);       R[4] = 1.f - 2.f * (xx + zz); R[5] = 2.f * (yz - wx);
-  R[6] = 2.f * (xz - wy);       R[7] = 2.f * (yz + wx);       R[8] = 1.f - 2.f * (xx + yy);
+  const float yy_zz = fmaf(y, y, z * z), xx_zz = fmaf(x, x, z * z), xx_yy = fmaf(x, x, y * y);
+  R[0] = fmaf(-2.f, yy_zz, 1.f);
+  R[1] = 2.f * fmaf(x, y, -(w * z));
+  R[2] = 2.f * fmaf(x, z, w * y);
+  R[3] = 2.f * fmaf(x, y, w * z);
+  R[4] = fmaf(-2.f, xx_zz, 1.f);
+  R[5] = 2.f * fmaf(y, z, -(w * x));
+  R[6] = 2.f * fmaf(x, z, -(w * y));
+  R[7] = 2.f * fmaf(y, z, w * x);
+  R[8] = fmaf(-2.f, xx_yy, 1.f);
 }
 
 // Cell index of a coordinate on the height-map table (Sec. III-A): floor of

@@ -448,6 +448,10 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
   // start of the next (S1-S3). A second inlined copy of the kinematics could
   // round differently and make a trajectory depend on where launches begin.
   bool fk_pending = true, fk_now = false;
+  // the torso rotation of Q, kept beside it: set from the same conversion of
+  // the same quaternion wherever Q changes, so it is bitwise quat_to_mat(Q)
+  float Rq[9];
+  quat_to_mat(Q[0], Q[1], Q[2], Q[3], Rq);
   unsigned kap = 0u;
   unsigned kap_slots = 0u;  // slots with a contact point in some lane of the wave
   float F = 0.f, tx = 0.f, ty = 0.f, nc = 0.f;
@@ -456,8 +460,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
     fk_pending = false;
     if (MODE == kStep && s > 0) {
       const bool active = valid && fl == 0;
-      float R[9];
-      quat_to_mat(Q[0], Q[1], Q[2], Q[3], R);
+      const float* R = Rq;
       // S4: trial step. Body-frame Euler equation: I_b dw_b = tau_b - w_b x I_b w_b
       float v1[3], w1[3], c1[3], Q1[4], dq[4];
       v1[0] = v[0] + dt * a.gx;
@@ -695,6 +698,8 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
         }
   #pragma unroll
         for (int i = 0; i < 4; ++i) Q[i] = Q2[i];
+  #pragma unroll
+        for (int i = 0; i < 9; ++i) Rq[i] = R2[i];
         tele[0] += (double)th;
         tele[1] += (double)nc;
         tele[2] += (mn > 0.f && Wn > 0.f && lam < 1.f) ? 1.0 : 0.0;
@@ -704,8 +709,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
     }
     if (MODE != kStep || s == a.n_steps) break;
     const bool active = valid && fl == 0;
-    float R[9];
-    quat_to_mat(Q[0], Q[1], Q[2], Q[3], R);
+    const float* R = Rq;
 
     // S1 + S2: detection at P^n and normal forces.
     // Broad phase: a link whose box of points lies wholly above the highest

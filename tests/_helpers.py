@@ -271,9 +271,12 @@ def check_frame(ow, i, before, got, tol=FRAME_TOL):
 
 
 class WindowStats:
-    def __init__(self, start, inst):
+    def __init__(self, start, inst, start_state=None, length=0):
         self.start_frame = start
         self.inst = inst
+        self.start_state = start_state  # the window's (float32-rounded) start state
+        self.length = length
+        self.storage = None     # the float32-storage oracle's window deviation, when computed
         self.cog = self.pts = self.joint = self.orient = 0.0
         self.frames = 0
         self.flips = []         # (frame, decisions) of frames explained by a flip
@@ -334,7 +337,7 @@ def run_windows(ow, gw, idx, starts, length=200, check_points=True, tol=FRAME_TO
         start = {i: round_state(traj[i]) for i in idx}
         write_states(gw, idx, [start[i] for i in idx], J_of)
         refs = {i: start[i].copy() for i in idx}
-        stats = {i: WindowStats(s, i) for i in idx}
+        stats = {i: WindowStats(s, i, start[i].copy(), length) for i in idx}
         before = states_from(reader.read(), J_of, idx)
         for k in range(length):
             gw.step_n(1)
@@ -381,9 +384,30 @@ def summarize(label, results):
     return line, over
 
 
-def assert_windows(results, label, say=print):
-    """Every frame verified; every window within tolerance, or (at most
-    MAX_ATTRIBUTED_FRACTION of them) beyond it with every frame verified."""
+def storage_window(ow, r):
+    """The window of r run twice by the oracle from its start state: in float64,
+    and with the state rounded to float32 after every frame (float32 storage of
+    the state and nothing else). Returns the deviation between the two runs, as
+    a WindowStats measured like the GPU's window."""
+    i, J = r.inst, ow.morph_of(r.inst).n_joints
+    a, b = r.start_state.copy(), r.start_state.copy()
+    out = WindowStats(r.start_frame, i)
+    for _ in range(r.length):
+        ow.step(i, a)
+        ow.step(i, b)
+        b = round_state(b)
+        out.update(a, b, ow.points(i, a), ow.points(i, b), J)
+    return out
+
+
+def assert_windows(results, label, say=print, ow=None):
+    """Every frame verified; every window within tolerance, or beyond it with
+    every frame verified. A window beyond tolerance whose start, run by the
+    oracle with only its state rounded to float32 after each frame, also leaves
+    the tolerance is limited by float32 storage of the state (chaotic contact
+    amplifies that rounding alone past 1e-4 m within the window); at most
+    MAX_ATTRIBUTED_FRACTION of the windows may be beyond tolerance without that
+    explanation."""
     line, over = summarize(label, results)
     say(line)
     for r in results:
@@ -391,7 +415,17 @@ def assert_windows(results, label, say=print):
             say(f"  frame {frame} inst {r.inst}: flipped "
                 + "; ".join(f"{describe(d)} at {d[3]:.1e}" for d in decs))
     for r in over:
-        say(f"  beyond tolerance, every frame verified: start {r.start_frame} inst {r.inst}: {r}")
+        if ow is not None and r.start_state is not None and r.length:
+            r.storage = storage_window(ow, r)
+        lim = r.storage is not None and not r.storage.ok()
+        say(f"  beyond tolerance, every frame verified: start {r.start_frame} inst {r.inst}: {r}"
+            + (f"; float32 storage alone: {r.storage}" if r.storage is not None else ""))
+    unexplained = [r for r in over if r.storage is None or r.storage.ok()]
+    if ow is not None and over:
+        note = (f"{label}: of {len(over)} windows beyond tolerance, {len(over) - len(unexplained)} "
+                f"leave it under float32 storage of the state alone")
+        say(note)
+        REPORT.append(note)
     bad = [r for r in results if not r.verified()]
     for r in bad:
         for frame, e, cands in r.failed[:3]:
@@ -399,5 +433,6 @@ def assert_windows(results, label, say=print):
                 + ", ".join(f"{k} {v:.2e}" for k, v in e.items())
                 + f"; fragile decisions tried: {len(cands)}")
     assert not bad, f"{label}: {len(bad)} windows with frames that match no oracle frame"
-    assert len(over) <= MAX_ATTRIBUTED_FRACTION * len(results), \
-        f"{label}: {len(over)} of {len(results)} windows beyond tolerance"
+    assert len(unexplained) <= MAX_ATTRIBUTED_FRACTION * len(results), \
+        f"{label}: {len(unexplained)} of {len(results)} windows beyond tolerance, not explained " \
+        f"by float32 storage of the state"

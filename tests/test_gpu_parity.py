@@ -33,8 +33,9 @@ def assert_windows(results, label, ow=None):
     """Every GPU frame is the oracle's frame from the same state (to float32
     rounding, or with a logged fragile decision taken the other way), and every
     window is within 1e-4 m / 1e-3 rad, or beyond it with every frame verified
-    (at most a tenth of the windows)."""
-    _assert_windows(results, label, say=say)
+    (at most a tenth of the windows, not counting windows that float32
+    storage of the state alone takes beyond the tolerance)."""
+    _assert_windows(results, label, say=say, ow=ow)
 
 
 def test_placement_matches_oracle():
