@@ -102,6 +102,64 @@ static int solve3(const double* A_in, const double* b_in, double* x) {
   return 1;
 }
 
+/* Gaussian elimination with partial pivoting on an n x n system (n <= 6),
+ * on copies. Returns 0 when a pivot vanishes. */
+static int solve_n(int n, const double* A_in, const double* b_in, double* x) {
+  double A[36], b[6];
+  memcpy(A, A_in, sizeof(double) * n * n);
+  memcpy(b, b_in, sizeof(double) * n);
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (fabs(A[n * r + col]) > fabs(A[n * piv + col])) piv = r;
+    if (A[n * piv + col] == 0.0) return 0;
+    if (piv != col) {
+      for (int k = 0; k < n; ++k) {
+        double t = A[n * col + k];
+        A[n * col + k] = A[n * piv + k];
+        A[n * piv + k] = t;
+      }
+      double t = b[col];
+      b[col] = b[piv];
+      b[piv] = t;
+    }
+    for (int r = col + 1; r < n; ++r) {
+      double f = A[n * r + col] / A[n * col + col];
+      for (int k = col; k < n; ++k) A[n * r + k] -= f * A[n * col + k];
+      b[r] -= f * b[col];
+    }
+  }
+  for (int r = n - 1; r >= 0; --r) {
+    double s = b[r];
+    for (int k = r + 1; k < n; ++k) s -= A[n * r + k] * x[k];
+    x[r] = s / A[n * r + r];
+  }
+  return 1;
+}
+
+/* Smallest eigenvalue of a symmetric 3x3 matrix: the roots of its
+ * characteristic cubic in trigonometric form. With q = tr A / 3 and
+ * B = (A - q 1) / p, p^2 = |A - q 1|_F^2 / 6, the eigenvalues are
+ * q + 2 p cos(phi + 2 pi k / 3), phi = acos(det B / 2) / 3; k = 1 gives the
+ * smallest. */
+static double sym3_min_eig(const double* A) {
+  const double q = (A[0] + A[4] + A[8]) / 3.0;
+  const double off = A[1] * A[1] + A[2] * A[2] + A[5] * A[5];
+  const double d0 = A[0] - q, d1 = A[4] - q, d2 = A[8] - q;
+  const double p2 = d0 * d0 + d1 * d1 + d2 * d2 + 2.0 * off;
+  if (!(p2 > 0.0)) return q;
+  const double pp = sqrt(p2 / 6.0);
+  double B[9];
+  for (int i = 0; i < 9; ++i) B[i] = A[i] / pp;
+  B[0] -= q / pp; B[4] -= q / pp; B[8] -= q / pp;
+  double r = 0.5 * det3(B);
+  r = r < -1.0 ? -1.0 : (r > 1.0 ? 1.0 : r);
+  const double phi = acos(r) / 3.0;
+  return q + 2.0 * pp * cos(phi + 2.0 * acos(-1.0) / 3.0);
+}
+
+double orc_sym3_min_eig(const double* A) { return sym3_min_eig(A); }
+
 /* Rotation matrix of a unit quaternion (w, x, y, z). */
 static void quat_to_mat(const double* Q, double* R) {
   double w = Q[0], x = Q[1], y = Q[2], z = Q[3];
@@ -446,12 +504,109 @@ int orc_lsq_w(int n, const double* src, const double* dst, const double* wt, dou
   return lsq_core(n, src, dst, wt, eps, a, NULL);
 }
 
+/* The six-degree-of-freedom fit (the refinement closing Sec. III-C, rotations
+ * about the other two axes as well), in 3-D: the small rigid motion, a
+ * displacement a and a rotation vector th about the origin of the
+ * coordinates, that best carries the set's points at t (src [n][3]) onto
+ * their points at t+1 (dst [n][3]), minimizing
+ *   sum_i w_i |dst_i - (src_i + a + th x src_i)|^2
+ * (th x src is the first-order term of the rotation, as a3 is of the yaw in
+ * eq. 2). The residual of pair i is linear in x = (a, th): its component c
+ * has the gradient (e_c, e_0 x src_i . e_c, e_1 x src_i . e_c, e_2 x src_i .
+ * e_c), and the fit solves the 6 x 6 normal equations sum_i w_i G_i^T G_i x =
+ * sum_i w_i G_i^T (dst_i - src_i). It is solved when the spread tensor of the
+ * set about its centroid, S = sum_i w_i (|e_i|^2 1 - e_i e_i^T), e_i = src_i -
+ * centroid, has its smallest eigenvalue above W eps^2 (the rotation is then
+ * determined about every axis: three or more points, not on one line); else
+ * the ground-plane fit of eqs. (4)-(6) on the x, y components (yaw and
+ * horizontal displacement, or displacement only, by its own spread test) with
+ * the weighted mean vertical slip as the vertical displacement and no roll or
+ * pitch. Writes a[0..2] the displacement and a[3..5] the rotation; returns 6,
+ * 3 (yaw only), 2 (displacement only) or 0 (no pair, or all weights zero). */
+static int lsq6_core(int n, const double* src, const double* dst, const double* wt, double eps,
+                     double* a, double* s2d, double* d2d, fragile_ctx* fc) {
+  for (int i = 0; i < 6; ++i) a[i] = 0.0;
+  if (n <= 0) return 0;
+  double Nm[36] = {0}, rhs[6] = {0}, W = 0.0, cen[3] = {0, 0, 0}, s2 = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double wi = wt ? wt[i] : 1.0;
+    const double* x = src + 3 * i;
+    double d[3];
+    for (int c = 0; c < 3; ++c) d[c] = dst[3 * i + c] - x[c];
+    double G[3][6];
+    for (int c = 0; c < 3; ++c) {
+      for (int k = 0; k < 3; ++k) G[c][k] = c == k ? 1.0 : 0.0;
+      for (int k = 0; k < 3; ++k) {
+        double e[3] = {0, 0, 0}, ex[3];
+        e[k] = 1.0;
+        cross3(e, x, ex);
+        G[c][3 + k] = ex[c];
+      }
+    }
+    for (int u = 0; u < 6; ++u) {
+      for (int v = 0; v < 6; ++v)
+        for (int c = 0; c < 3; ++c) Nm[6 * u + v] += wi * G[c][u] * G[c][v];
+      for (int c = 0; c < 3; ++c) rhs[u] += wi * G[c][u] * d[c];
+    }
+    W += wi;
+    for (int c = 0; c < 3; ++c) cen[c] += wi * x[c];
+    s2 += wi * (x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+  }
+  if (!(W > 0.0)) return 0;
+  for (int c = 0; c < 3; ++c) cen[c] /= W;
+  double S[9] = {0};
+  for (int i = 0; i < n; ++i) {
+    const double wi = wt ? wt[i] : 1.0;
+    const double e[3] = {src[3 * i] - cen[0], src[3 * i + 1] - cen[1], src[3 * i + 2] - cen[2]};
+    const double ee = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) S[3 * r + c] += wi * ((r == c ? ee : 0.0) - e[r] * e[c]);
+  }
+  const double lmin = sym3_min_eig(S);
+  int full = n >= 3 && lmin > W * eps * eps;
+  if (fc && n >= 3) {
+    const double gap = fabs(lmin - W * eps * eps), scale = W * eps * eps + s2;
+    if (gap < fc->margin_spread * scale)
+      note_fragile(fc, ORC_FR_FIT, -2, ORC_FK_SPREAD, gap / scale);
+    if (is_flipped(fc, ORC_FR_FIT, -2, ORC_FK_SPREAD)) full = !full;
+  }
+  if (full && solve_n(6, Nm, rhs, a)) return 6;
+  /* the ground-plane fit, and the mean vertical slip */
+  double dz = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double wi = wt ? wt[i] : 1.0;
+    s2d[2 * i] = src[3 * i];
+    s2d[2 * i + 1] = src[3 * i + 1];
+    d2d[2 * i] = dst[3 * i];
+    d2d[2 * i + 1] = dst[3 * i + 1];
+    dz += wi * (dst[3 * i + 2] - src[3 * i + 2]);
+  }
+  double a3[3];
+  int r = lsq_core(n, s2d, d2d, wt, eps, a3, fc);
+  for (int i = 0; i < 6; ++i) a[i] = 0.0;
+  a[0] = a3[0];
+  a[1] = a3[1];
+  a[2] = dz / W;
+  a[5] = a3[2];
+  return r;
+}
+
+int orc_lsq6_w(int n, const double* src, const double* dst, const double* wt, double eps,
+               double* a) {
+  double* s2d = (double*)malloc(sizeof(double) * 2 * (n > 0 ? n : 1));
+  double* d2d = (double*)malloc(sizeof(double) * 2 * (n > 0 ? n : 1));
+  int r = (s2d && d2d) ? lsq6_core(n, src, dst, wt, eps, a, s2d, d2d, NULL) : -1;
+  free(s2d);
+  free(d2d);
+  return r;
+}
+
 /* ------------------------------------------------------------------------- */
 /* the step                                                                   */
 /* ------------------------------------------------------------------------- */
 
 typedef struct {
-  double *y, *r, *P, *Ps, *src, *dst, *f, *wt, *d;
+  double *y, *r, *P, *Ps, *src, *dst, *src3, *dst3, *f, *wt, *d;
   int* kap;
 } work_t;
 
@@ -462,15 +617,19 @@ static int work_alloc(work_t* w, int N) {
   w->Ps = (double*)malloc(sizeof(double) * 3 * N);
   w->src = (double*)malloc(sizeof(double) * 2 * N);
   w->dst = (double*)malloc(sizeof(double) * 2 * N);
+  w->src3 = (double*)malloc(sizeof(double) * 3 * N);
+  w->dst3 = (double*)malloc(sizeof(double) * 3 * N);
   w->kap = (int*)malloc(sizeof(int) * N);
   w->f = (double*)malloc(sizeof(double) * N);
   w->wt = (double*)malloc(sizeof(double) * N);
   w->d = (double*)malloc(sizeof(double) * N);
-  return w->y && w->r && w->P && w->Ps && w->src && w->dst && w->kap && w->f && w->wt && w->d;
+  return w->y && w->r && w->P && w->Ps && w->src && w->dst && w->src3 && w->dst3 && w->kap &&
+         w->f && w->wt && w->d;
 }
 
 static void work_free(work_t* w) {
   free(w->y); free(w->r); free(w->P); free(w->Ps); free(w->src); free(w->dst); free(w->kap);
+  free(w->src3); free(w->dst3);
   free(w->f); free(w->wt); free(w->d);
 }
 
@@ -638,15 +797,28 @@ static int step_ws(const orc_morph* m, const orc_params* p, const float* ctrl, d
       w->src[2 * nS + 1] = w->P[3 * k + 1] - c1[1];
       w->dst[2 * nS] = w->Ps[3 * k] - c1[0];
       w->dst[2 * nS + 1] = w->Ps[3 * k + 1] - c1[1];
+      for (int i = 0; i < 3; ++i) {  /* the same in 3-D, for the six-degree fit */
+        w->src3[3 * nS + i] = w->P[3 * k + i] - c1[i];
+        w->dst3[3 * nS + i] = w->Ps[3 * k + i] - c1[i];
+      }
       w->wt[nS] = w->f[k];  /* the force pressing the point at P^n */
       ++nS;
     }
   }
 
   /* S6: least-squares displacement and rotation of the contact points */
-  double a[3];
+  double a[3], a6[6] = {0, 0, 0, 0, 0, 0};
   const double* wt = p->weighted ? w->wt : NULL;
-  int fit = lsq_core(nS, w->src, w->dst, wt, p->eps, a, fc);
+  int fit;
+  if (p->six_dof) {
+    /* the src/dst arrays serve as the ground-plane fallback's scratch */
+    fit = lsq6_core(nS, w->src3, w->dst3, wt, p->eps, a6, w->src, w->dst, fc);
+    a[0] = a6[0];
+    a[1] = a6[1];
+    a[2] = a6[5];
+  } else {
+    fit = lsq_core(nS, w->src, w->dst, wt, p->eps, a, fc);
+  }
 
   /* S7: cap by the maximum static friction mu F_N (the mean slip is weighted
    * like the fit) */
@@ -655,8 +827,8 @@ static int step_ws(const orc_morph* m, const orc_params* p, const float* ctrl, d
     double sbx = 0.0, sby = 0.0, W = 0.0;
     for (int i = 0; i < nS; ++i) {
       double wi = wt ? wt[i] : 1.0;
-      sbx += wi * (w->dst[2 * i] - w->src[2 * i]);
-      sby += wi * (w->dst[2 * i + 1] - w->src[2 * i + 1]);
+      sbx += wi * (w->dst3[3 * i] - w->src3[3 * i]);
+      sby += wi * (w->dst3[3 * i + 1] - w->src3[3 * i + 1]);
       W += wi;
     }
     sbx /= W;
@@ -675,26 +847,46 @@ static int step_ws(const orc_morph* m, const orc_params* p, const float* ctrl, d
     if (is_flipped(fc, ORC_FR_FIT, -1, ORC_FK_CAP)) slipping = !slipping;
   }
 
-  /* S8: move back by the capped fitted motion (translation, then yaw about the
-   * CoG) and remove the matching velocity */
-  double a3 = a[2] < -1.0 ? -1.0 : (a[2] > 1.0 ? 1.0 : a[2]);
-  double alpha = asin(a3);
-  double Q2[4];
-  {
-    double half = -0.5 * lam * alpha;
-    double qz[4] = {cos(half), 0.0, 0.0, sin(half)};
-    quat_mul(qz, Q1, Q2);
+  /* S8: move back by the capped fitted motion (translation, then the rotation
+   * about the CoG) and remove the matching velocity */
+  if (p->six_dof) {
+    /* the rotation vector's length is the sine of the angle (as a3 is of the
+     * yaw in eq. 5): angle asin(|th|) about th / |th| */
+    const double* th = a6 + 3;
+    const double s = sqrt(th[0] * th[0] + th[1] * th[1] + th[2] * th[2]);
+    const double ang = asin(s > 1.0 ? 1.0 : s);
+    double phi[3] = {0.0, 0.0, 0.0}, back[3], qb[4], Q2[4];
+    if (s > 0.0)
+      for (int i = 0; i < 3; ++i) phi[i] = ang * th[i] / s;
+    for (int i = 0; i < 3; ++i) back[i] = -lam * phi[i];
+    quat_exp(back, qb);
+    quat_mul(qb, Q1, Q2);
+    for (int i = 0; i < 3; ++i) {
+      c[i] = c1[i] - lam * a6[i];
+      v[i] = v1[i] - lam * a6[i] / dt;
+      om[i] = om1[i] - lam * phi[i] / dt;
+    }
+    for (int i = 0; i < 4; ++i) Q[i] = Q2[i];
+  } else {
+    double a3 = a[2] < -1.0 ? -1.0 : (a[2] > 1.0 ? 1.0 : a[2]);
+    double alpha = asin(a3);
+    double Q2[4];
+    {
+      double half = -0.5 * lam * alpha;
+      double qz[4] = {cos(half), 0.0, 0.0, sin(half)};
+      quat_mul(qz, Q1, Q2);
+    }
+    c[0] = c1[0] - lam * a[0];
+    c[1] = c1[1] - lam * a[1];
+    c[2] = c1[2];
+    for (int i = 0; i < 4; ++i) Q[i] = Q2[i];
+    v[0] = v1[0] - lam * a[0] / dt;
+    v[1] = v1[1] - lam * a[1] / dt;
+    v[2] = v1[2];
+    om[0] = om1[0];
+    om[1] = om1[1];
+    om[2] = om1[2] - lam * alpha / dt;
   }
-  c[0] = c1[0] - lam * a[0];
-  c[1] = c1[1] - lam * a[1];
-  c[2] = c1[2];
-  for (int i = 0; i < 4; ++i) Q[i] = Q2[i];
-  v[0] = v1[0] - lam * a[0] / dt;
-  v[1] = v1[1] - lam * a[1] / dt;
-  v[2] = v1[2];
-  om[0] = om1[0];
-  om[1] = om1[1];
-  om[2] = om1[2] - lam * alpha / dt;
 
   /* S9: telemetry and health */
   st[ORC_TELE + 0] += torso_height(p, st, g_b, fc);
@@ -715,6 +907,7 @@ static int step_ws(const orc_morph* m, const orc_params* p, const float* ctrl, d
     diag[ORC_D_NC] = n_contact;
     diag[ORC_D_NS] = nS;
     for (int i = 0; i < 3; ++i) diag[ORC_D_A + i] = a[i];
+    for (int i = 0; i < 6; ++i) diag[ORC_D_A6 + i] = a6[i];
     diag[ORC_D_LAMBDA] = lam;
     diag[ORC_D_FF] = Ff;
   }

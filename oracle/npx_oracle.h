@@ -52,6 +52,10 @@ typedef struct {
   double max_rate; /* > 0: a joint turns at most max_rate rad/s, so one joint
                       update moves it by at most max_rate K dt towards its
                       command (the motors' speed, Sec. III-B); 0 or +inf: no limit */
+  int six_dof;     /* 1: the friction fit takes the full rigid motion in 3-D
+                      (rotations about the other two axes as well, the
+                      refinement closing Sec. III-C; see orc_lsq6_w) and the
+                      correction moves the robot back by all of it */
 } orc_params;
 
 /* Per-instance state vector (double), fixed offsets; q and q_prev follow. */
@@ -76,7 +80,8 @@ enum {
   ORC_D_A = 6,       /* a1, a2, a3 (3) */
   ORC_D_LAMBDA = 9,  /* static-friction cap factor */
   ORC_D_FF = 10,     /* friction force estimate */
-  ORC_D_LEN = 11
+  ORC_D_A6 = 11,     /* six-degree fit: displacement (3), rotation vector (3) */
+  ORC_D_LEN = 17
 };
 
 /* Flag bits. */
@@ -141,6 +146,18 @@ int orc_lsq(int n, const double* src, const double* dst, double eps, double* a);
  * or all weights zero: no motion). */
 int orc_lsq_w(int n, const double* src, const double* dst, const double* wt, double eps,
               double* a);
+/* The six-degree-of-freedom friction fit on n point pairs in 3-D (src [n][3]
+ * at t, dst [n][3] at t+1, about the origin of the coordinates), pair i
+ * weighted by wt[i] (NULL: 1): a[0..2] the displacement, a[3..5] the
+ * rotation vector of the least-squares small rigid motion, when the set's
+ * spread tensor about its centroid has its smallest eigenvalue above W eps^2;
+ * else the ground-plane fit of orc_lsq_w on the x, y components (in a[0],
+ * a[1], a[5]) with the mean vertical slip in a[2]. Returns 6, 3, 2, 0, or -1
+ * when out of memory. */
+int orc_lsq6_w(int n, const double* src, const double* dst, const double* wt, double eps,
+               double* a);
+/* Smallest eigenvalue of a symmetric 3x3 matrix (row-major). */
+double orc_sym3_min_eig(const double* A);
 
 /* State from a start pose [7] = torso origin xyz + quaternion, at rest. */
 int orc_init_state(const orc_morph* m, const orc_params* p, const float* ctrl,

@@ -18,7 +18,7 @@ SRC = os.path.join(HERE, "npx_oracle.c")
 
 # state-vector offsets (mirror of the enum in npx_oracle.h)
 C_, Q_, V_, W_, STEP, FLAGS, TELE, HDR = 0, 3, 7, 10, 13, 14, 15, 19
-D_FN, D_TAU, D_NC, D_NS, D_A, D_LAMBDA, D_FF, D_LEN = 0, 1, 4, 5, 6, 9, 10, 11
+D_FN, D_TAU, D_NC, D_NS, D_A, D_LAMBDA, D_FF, D_A6, D_LEN = 0, 1, 4, 5, 6, 9, 10, 11, 17
 # fragile decisions (mirror of the enums in npx_oracle.h)
 FR_S1, FR_S5, FR_FIT, FR_S9 = 0, 1, 2, 3
 FK_EDGE_X, FK_EDGE_Y, FK_CONTACT, FK_SPREAD, FK_CAP = 0, 1, 2, 3, 4
@@ -55,7 +55,7 @@ class _Params(C.Structure):
                 ("k_n", C.c_double), ("zeta", C.c_double), ("eps", C.c_double),
                 ("weighted", C.c_int), ("hf_bilinear", C.c_int), ("hf_nx", C.c_int), ("hf_ny", C.c_int), ("hf_s", C.c_double),
                 ("hf_x0", C.c_double), ("hf_y0", C.c_double), ("hf", C.POINTER(C.c_float)),
-                ("max_rate", C.c_double)]
+                ("max_rate", C.c_double), ("six_dof", C.c_int)]
 
 
 _lib = None
@@ -78,6 +78,9 @@ def lib():
         L.orc_ray_range.restype = C.c_double
         L.orc_lsq.argtypes = [C.c_int, dp, dp, C.c_double, dp]
         L.orc_lsq_w.argtypes = [C.c_int, dp, dp, dp, C.c_double, dp]
+        L.orc_lsq6_w.argtypes = [C.c_int, dp, dp, dp, C.c_double, dp]
+        L.orc_sym3_min_eig.argtypes = [dp]
+        L.orc_sym3_min_eig.restype = C.c_double
         L.orc_init_state.argtypes = [C.POINTER(_Morph), C.POINTER(_Params), fp, fp, dp]
         L.orc_points.argtypes = [C.POINTER(_Morph), dp, dp]
         L.orc_step.argtypes = [C.POINTER(_Morph), C.POINTER(_Params), fp, dp, dp]
@@ -135,7 +138,8 @@ class OracleParams:
                          int(getattr(params, "friction_weighting", False)),
                          int(getattr(params, "hf_bilinear", False)), int(hf.nx), int(hf.ny),
                          float(hf.s), float(hf.x0), float(hf.y0), _fptr(self.H),
-                         float(getattr(params, "max_joint_rate", 0.0)))
+                         float(getattr(params, "max_joint_rate", 0.0)),
+                         int(getattr(params, "friction_6dof", False)))
 
     def cell(self, x, y):
         i, j = C.c_int(), C.c_int()
@@ -167,6 +171,29 @@ def lsq(src, dst, eps=1e-4, weights=None):
         k = lib().orc_lsq_w(int(src.shape[0]), _dptr(src), _dptr(dst), _dptr(w), float(eps),
                             _dptr(a))
     return a, k
+
+
+def lsq6(src, dst, eps=1e-4, weights=None):
+    """Six-degree-of-freedom friction fit of the 3-D pairs src -> dst (about
+    the coordinates' origin): (displacement (3), rotation vector (3)) and the
+    branch taken (6 full, 3 yaw only, 2 displacement only, 0 none)."""
+    src = np.ascontiguousarray(src, dtype=np.float64).reshape(-1, 3)
+    dst = np.ascontiguousarray(dst, dtype=np.float64).reshape(-1, 3)
+    a = np.zeros(6)
+    w = None
+    if weights is not None:
+        w = np.ascontiguousarray(weights, dtype=np.float64).reshape(-1)
+        assert w.shape[0] == src.shape[0]
+    k = lib().orc_lsq6_w(int(src.shape[0]), _dptr(src), _dptr(dst),
+                         _dptr(w) if w is not None else None, float(eps), _dptr(a))
+    assert k >= 0
+    return a, k
+
+
+def sym3_min_eig(A):
+    """Smallest eigenvalue of a symmetric 3x3 matrix (the oracle's closed form)."""
+    A = np.ascontiguousarray(A, dtype=np.float64).reshape(9)
+    return lib().orc_sym3_min_eig(_dptr(A))
 
 
 class OracleWorld:

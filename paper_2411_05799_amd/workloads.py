@@ -83,6 +83,7 @@ class Params:
     friction_weighting: bool = False  # friction fit weighted by each point's normal force
     hf_bilinear: bool = False   # height map read bilinearly between cell centres
     max_joint_rate: float = 0.0  # rad/s a joint may turn (0: no limit)
+    friction_6dof: bool = False  # friction fit over the full rigid motion in 3-D
 
 
 @dataclass
