@@ -169,6 +169,22 @@ typedef struct {
                                       from its angle towards its command by at most
                                       max_joint_rate K dt; 0 or +inf: no limit;
                                       negative or NaN: rejected */
+  int32_t friction_6dof;           /* 0: the friction fit in the ground plane
+                                      (eqs. (4)-(6): displacement and yaw);
+                                      1: the fit over the full rigid motion in
+                                      3-D (rotations about the other two axes
+                                      as well, the refinement closing Sec.
+                                      III-C): displacement and rotation vector
+                                      of the contact points from P^n to P*, the
+                                      ground-plane fit with the mean vertical
+                                      slip when the set's spread is too small to
+                                      fix a 3-D rotation; the robot is moved
+                                      back by the whole fitted motion under the
+                                      same static-friction cap; other values,
+                                      and 1 together with friction_weighting
+                                      (when the force sits on points along one
+                                      line, a point of near-zero force would
+                                      decide the roll about it), are rejected */
 } npx_world_desc;
 
 typedef struct npx_world npx_world;

@@ -516,8 +516,11 @@ int orc_lsq_w(int n, const double* src, const double* dst, const double* wt, dou
  * e_c), and the fit solves the 6 x 6 normal equations sum_i w_i G_i^T G_i x =
  * sum_i w_i G_i^T (dst_i - src_i). It is solved when the spread tensor of the
  * set about its centroid, S = sum_i w_i (|e_i|^2 1 - e_i e_i^T), e_i = src_i -
- * centroid, has its smallest eigenvalue above W eps^2 (the rotation is then
- * determined about every axis: three or more points, not on one line); else
+ * centroid, has its smallest eigenvalue above both W eps^2 and
+ * ORC_SIX_DOF_COND tr S (three or more points, not on one line, and not so
+ * close to a line that the rotation about it would be set by slips of
+ * 1e-8 m: a bound of 1e3 on the ratio of the largest to the smallest
+ * eigenvalue, within a factor of 3); else
  * the ground-plane fit of eqs. (4)-(6) on the x, y components (yaw and
  * horizontal displacement, or displacement only, by its own spread test) with
  * the weighted mean vertical slip as the vertical displacement and no roll or
@@ -563,9 +566,10 @@ static int lsq6_core(int n, const double* src, const double* dst, const double* 
       for (int c = 0; c < 3; ++c) S[3 * r + c] += wi * ((r == c ? ee : 0.0) - e[r] * e[c]);
   }
   const double lmin = sym3_min_eig(S);
-  int full = n >= 3 && lmin > W * eps * eps;
+  const double thr = fmax(W * eps * eps, ORC_SIX_DOF_COND * (S[0] + S[4] + S[8]));
+  int full = n >= 3 && lmin > thr;
   if (fc && n >= 3) {
-    const double gap = fabs(lmin - W * eps * eps), scale = W * eps * eps + s2;
+    const double gap = fabs(lmin - thr), scale = thr + s2;
     if (gap < fc->margin_spread * scale)
       note_fragile(fc, ORC_FR_FIT, -2, ORC_FK_SPREAD, gap / scale);
     if (is_flipped(fc, ORC_FR_FIT, -2, ORC_FK_SPREAD)) full = !full;
@@ -631,6 +635,13 @@ static void work_free(work_t* w) {
   free(w->y); free(w->r); free(w->P); free(w->Ps); free(w->src); free(w->dst); free(w->kap);
   free(w->src3); free(w->dst3);
   free(w->f); free(w->wt); free(w->d);
+}
+
+/* Step parameters the oracle takes: the six-degree fit is not combined with
+ * the force weighting (with the force on points along one line, a point of
+ * near-zero force would decide the roll about it). */
+static int params_ok(const orc_params* p) {
+  return p->K >= 1 && p->dt > 0.0 && !(p->six_dof && p->weighted);
 }
 
 static int morph_ok(const orc_morph* m) {
@@ -955,7 +966,7 @@ void orc_points(const orc_morph* m, const double* st, double* P) {
 
 int orc_step(const orc_morph* m, const orc_params* p, const float* ctrl, double* st,
              double* diag) {
-  if (!morph_ok(m) || p->K < 1 || p->dt <= 0.0) return -1;
+  if (!morph_ok(m) || !params_ok(p)) return -1;
   work_t w;
   if (!work_alloc(&w, m->n_points)) {
     work_free(&w);
@@ -969,7 +980,7 @@ int orc_step(const orc_morph* m, const orc_params* p, const float* ctrl, double*
 int orc_step_ex(const orc_morph* m, const orc_params* p, const float* ctrl, double* st,
                 double* diag, const double* margins, orc_fragile* log, int log_cap,
                 int* n_log, const orc_fragile* flips, int n_flips) {
-  if (!morph_ok(m) || p->K < 1 || p->dt <= 0.0 || log_cap < 0 || n_flips < 0) return -1;
+  if (!morph_ok(m) || !params_ok(p) || log_cap < 0 || n_flips < 0) return -1;
   work_t w;
   if (!work_alloc(&w, m->n_points)) {
     work_free(&w);
@@ -986,7 +997,7 @@ int orc_step_ex(const orc_morph* m, const orc_params* p, const float* ctrl, doub
 
 int orc_run(const orc_morph* m, const orc_params* p, const float* ctrl, double* st,
             long n_steps) {
-  if (!morph_ok(m) || p->K < 1 || p->dt <= 0.0 || n_steps < 0) return -1;
+  if (!morph_ok(m) || !params_ok(p) || n_steps < 0) return -1;
   work_t w;
   if (!work_alloc(&w, m->n_points)) {
     work_free(&w);
@@ -1000,6 +1011,7 @@ int orc_run(const orc_morph* m, const orc_params* p, const float* ctrl, double* 
 int orc_run_batch(int n_inst, const orc_morph* morphs, const int* inst_morph,
                   const orc_params* p, const float* const* ctrl, double* const* states,
                   long n_steps, int n_threads) {
+  if (!params_ok(p)) return -1;
   int used = 1;
 #ifdef _OPENMP
   if (n_threads <= 0) n_threads = omp_get_max_threads();

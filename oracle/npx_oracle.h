@@ -55,8 +55,14 @@ typedef struct {
   int six_dof;     /* 1: the friction fit takes the full rigid motion in 3-D
                       (rotations about the other two axes as well, the
                       refinement closing Sec. III-C; see orc_lsq6_w) and the
-                      correction moves the robot back by all of it */
+                      correction moves the robot back by all of it; not with
+                      weighted (the step functions return -1) */
 } orc_params;
+
+/* The six-degree fit takes a 3-D rotation only when the smallest eigenvalue
+ * of the contact set's spread tensor is at least this fraction of its trace
+ * (see orc_lsq6_w). */
+#define ORC_SIX_DOF_COND 1e-3
 
 /* Per-instance state vector (double), fixed offsets; q and q_prev follow. */
 enum {
@@ -150,7 +156,8 @@ int orc_lsq_w(int n, const double* src, const double* dst, const double* wt, dou
  * at t, dst [n][3] at t+1, about the origin of the coordinates), pair i
  * weighted by wt[i] (NULL: 1): a[0..2] the displacement, a[3..5] the
  * rotation vector of the least-squares small rigid motion, when the set's
- * spread tensor about its centroid has its smallest eigenvalue above W eps^2;
+ * spread tensor about its centroid has its smallest eigenvalue above W eps^2
+ * and ORC_SIX_DOF_COND times its trace;
  * else the ground-plane fit of orc_lsq_w on the x, y components (in a[0],
  * a[1], a[5]) with the mean vertical slip in a[2]. Returns 6, 3, 2, 0, or -1
  * when out of memory. */
@@ -188,7 +195,8 @@ int orc_run(const orc_morph* m, const orc_params* p, const float* ctrl, double* 
             long n_steps);
 
 /* n_steps steps of n_inst independent instances on up to n_threads threads
- * (n_threads <= 0: all). Returns the thread count used. */
+ * (n_threads <= 0: all). Returns the thread count used, or -1 for parameters
+ * the step does not take. */
 int orc_run_batch(int n_inst, const orc_morph* morphs, const int* inst_morph,
                   const orc_params* p, const float* const* ctrl, double* const* states,
                   long n_steps, int n_threads);

@@ -271,8 +271,10 @@ class OracleWorld:
         dp = C.POINTER(C.c_double)
         cptr = (fp * n)(*[_fptr(self.ctrl[int(i)]) for i in idx])
         sptr = (dp * n)(*[_dptr(s) for s in states])
-        return lib().orc_run_batch(n, self._cmorphs, _iptr(im), C.byref(self.params.c), cptr, sptr,
-                                   int(n_steps), int(threads))
+        used = lib().orc_run_batch(n, self._cmorphs, _iptr(im), C.byref(self.params.c), cptr,
+                                   sptr, int(n_steps), int(threads))
+        assert used > 0, "parameters the step does not take"
+        return used
 
     def ray_ends(self, i, st, rays, ray_link):
         """World start and end [n, 3] of rays riding on instance i's links at

@@ -52,6 +52,7 @@ struct StepArgs {
   int mu_inf;
   float kn, zeta, eps;
   int fric_w;             // friction fit weighted by each point's normal force
+  int fric6;              // six-degree friction fit (rotation in 3-D, vertical displacement)
   const float* hf;
   int hf_nx, hf_ny;
   float hf_s, hf_x0, hf_y0;

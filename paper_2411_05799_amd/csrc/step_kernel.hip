@@ -91,6 +91,55 @@ __device__ __forceinline__ void seg_sum_n(float (&x)[N]) {
   }
 }
 
+// The same sums for doubles: each exchange moves the two 32-bit halves.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  const unsigned long long v = __builtin_bit_cast(unsigned long long, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double xor16_d(double x) {
+  const unsigned long long v = __builtin_bit_cast(unsigned long long, x);
+  const int lo = __builtin_amdgcn_ds_swizzle((int)(unsigned)v, 0x401F);
+  const int hi = __builtin_amdgcn_ds_swizzle((int)(unsigned)(v >> 32), 0x401F);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double swap_sum32_d(double x) {
+  const unsigned long long v = __builtin_bit_cast(unsigned long long, x);
+  auto lo = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+  auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(v >> 32), (unsigned)(v >> 32), false, false);
+  const double a = __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi[0] << 32) | (unsigned)lo[0]);
+  const double b = __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi[1] << 32) | (unsigned)lo[1]);
+  return a + b;
+}
+
+template <int G, int N>
+__device__ __forceinline__ void seg_sum_nd(double (&x)[N]) {
+  static_assert(G == 16 || G == 32 || G == 64, "segment of 16, 32 or 64 lanes");
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] += dpp_d<0xB1>(x[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] += dpp_d<0x4E>(x[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] += dpp_d<0x141>(x[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] += dpp_d<0x140>(x[i]);
+  if constexpr (G >= 32) {
+    double o[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) o[i] = xor16_d(x[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] += o[i];
+  }
+  if constexpr (G >= 64) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = swap_sum32_d(x[i]);
+  }
+}
+
 template <int G>
 __device__ __forceinline__ float seg_sum(float x) {
   float v[1] = {x};
@@ -130,6 +179,10 @@ __device__ __forceinline__ unsigned long long seg_bits(unsigned long long m, int
 
 enum Mode { kStep = 0, kPlace = 1, kPoints = 2 };
 
+// The six-degree friction fit takes a 3-D rotation only when the contact set's
+// thinnest spread is at least this fraction of the trace of its spread tensor.
+constexpr float kSixDofCond = 1e-3f;
+
 // LDS rows of one link: [R row 0 | t0], [R row 1 | t1], [R row 2 | t2].
 using LinkT = float4[3];
 
@@ -145,7 +198,7 @@ struct LinkConst {
   double ph;
 };
 
-template <int G, int PPL, int LPL, int MODE, bool BIL>
+template <int G, int PPL, int LPL, int MODE, bool BIL, bool SIX>
 __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT, int* cand,
                                           int* touch, LinkConst* LK, int tb, int seg,
                                           int sl) {
@@ -553,14 +606,21 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
       // as c1 - c: c1 is rounded to float32 (half an ulp, 1.2e-7 m at |c| ~ 2 m),
       // and a fit that took that rounding for slip would return it as a
       // velocity change of 1.2e-7 m / dt.
-      const float dcx = dt * v1[0], dcy = dt * v1[1];
+      const float dcx = dt * v1[0], dcy = dt * v1[1], dcz = dt * v1[2];
       float mn = 0.f, Sx = 0.f, Sy = 0.f, S2 = 0.f, Dx = 0.f, Dy = 0.f, Cd = 0.f, Wt = 0.f;
-      float ox_ = 0.f, oy_ = 0.f;  // origin of the moments (about c), see above
+      // the six-degree fit's moments, in double (the moments about a set member
+      // lose digits to the centroid's removal when the set is wide and its
+      // slips large): Sx Sy Sz, Dx Dy Dz, sum s s^T (xx yy zz xy xz yz) and
+      // sum s x delta (3)
+      double dm[15];
+#pragma unroll
+      for (int i = 0; i < 15; ++i) dm[i] = 0.0;
+      float ox_ = 0.f, oy_ = 0.f, oz_ = 0.f;  // origin of the moments (about c), see above
       bool have_o = false;
       for (int e0 = 0; __any(e0 < n_cand); e0 += G) {
         const int e = e0 + sl;
         bool inS = false;
-        float Ux = 0.f, Uy = 0.f, dx = 0.f, dy = 0.f, wk = 1.f;
+        float Ux = 0.f, Uy = 0.f, Uz = 0.f, dx = 0.f, dy = 0.f, dz = 0.f, wk = 1.f;
         if (e < n_cand) {
           const int kk = pt_off + cand[e];
           const float4 rho = a.pts[kk];
@@ -586,12 +646,15 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
             const float qx = rx - drx, qy = ry - dry, qz = rz - drz;  // r_old
             Ux = R[0] * qx + R[1] * qy + R[2] * qz;
             Uy = R[3] * qx + R[4] * qy + R[5] * qz;
-            const float Uz = R[6] * qx + R[7] * qy + R[8] * qz;
+            Uz = R[6] * qx + R[7] * qy + R[8] * qz;
             dx = (Eb[0] * Ux + Eb[1] * Uy + Eb[2] * Uz) + (R1[0] * drx + R1[1] * dry + R1[2] * drz) +
                  dcx;
             dy = (Eb[3] * Ux + Eb[4] * Uy + Eb[5] * Uz) + (R1[3] * drx + R1[4] * dry + R1[5] * drz) +
                  dcy;
-            if (a.fric_w) {
+            if constexpr (SIX)
+              dz = (Eb[6] * Ux + Eb[7] * Uy + Eb[8] * Uz) +
+                   (R1[6] * drx + R1[7] * dry + R1[8] * drz) + dcz;
+            if (!SIX && a.fric_w) {  // the six-degree fit is not force-weighted
               // weighted by the force pressing the point at P^n, the normal
               // force of detection recomputed from the point before this
               // frame's joint update (the position P^n = c + U)
@@ -605,9 +668,11 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
         const unsigned long long m = seg_bits<G>(__ballot(inS), seg);
         const int src = seg * G + (m ? (int)__builtin_ctzll(m) : sl);
         const float bx = __shfl(Ux, src), by = __shfl(Uy, src);
+        const float bz = SIX ? __shfl(Uz, src) : 0.f;
         if (!have_o && m != 0ull) {
           ox_ = bx;
           oy_ = by;
+          oz_ = bz;
           have_o = true;
         }
         if (inS) {
@@ -620,8 +685,28 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
           Dx += wk * dx;
           Dy += wk * dy;
           Cd += wk * (sx * dy - sy * dx);
+          if constexpr (SIX) {
+            const double ex = sx, ey = sy, ez = (double)Uz - (double)oz_;
+            const double fx = dx, fy = dy, fz = dz;
+            dm[0] += ex;
+            dm[1] += ey;
+            dm[2] += ez;
+            dm[3] += fx;
+            dm[4] += fy;
+            dm[5] += fz;
+            dm[6] += ex * ex;
+            dm[7] += ey * ey;
+            dm[8] += ez * ez;
+            dm[9] += ex * ey;
+            dm[10] += ex * ez;
+            dm[11] += ey * ez;
+            dm[12] += ey * fz - ez * fy;
+            dm[13] += ez * fx - ex * fz;
+            dm[14] += ex * fy - ey * fx;
+          }
         }
       }
+      if constexpr (SIX) seg_sum_nd<G>(dm);
       {
         float m7[7] = {mn, Sx, Sy, S2, Dx, Dy, Cd};
         seg_sum_n<G>(m7);
@@ -634,44 +719,135 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
       // a = (D + a3 J^T S)/n, the mean slip is D/n. With the force weighting
       // every sum carries the point's weight and n becomes the total weight.
       float a1 = 0.f, a2 = 0.f, a3 = 0.f, lam = 0.f;
+      float az = 0.f, th6[3] = {0.f, 0.f, 0.f};  // six-degree fit: a_z and the rotation
       if (mn > 0.f && Wn > 0.f) {
         const float inv_n = rcp(Wn);
         const float D = S2 - (Sx * Sx + Sy * Sy) * inv_n;
         if (mn >= 2.f && D > Wn * a.eps * a.eps) a3 = (Cd - (Sx * Dy - Sy * Dx) * inv_n) * rcp(D);
         a1 = (Dx + Sy * a3) * inv_n + a3 * (oy_ - dcy);
         a2 = (Dy - Sx * a3) * inv_n - a3 * (ox_ - dcx);
+        if constexpr (SIX) {
+          // The six-degree fit (the refinement closing Sec. III-C, in 3-D), in
+          // double: the rotation th = J^-1 b with J = sum (|e|^2 1 - e e^T) the
+          // set's spread tensor about its centroid and b = sum e x delta the
+          // slips' moment there, when J - t 1 is positive definite (its leading
+          // minors, Sylvester) for t = max(n eps^2, 1e-3 tr J): a set thinner
+          // than that about some axis (a leg lying on the ground) would have
+          // the rotation about it set by the rounding of the slips; else the
+          // ground-plane fit (yaw, or none) with the mean vertical slip. The
+          // displacement at the predicted CoG: a = D/n - th x (S/n + o - dt v1).
+          const double n6 = mn, in6 = 1.0 / n6;
+          const double Sx6 = dm[0], Sy6 = dm[1], Sz6 = dm[2];
+          const double Dx6 = dm[3], Dy6 = dm[4], Dz6 = dm[5];
+          const double Qxx = dm[6] - Sx6 * Sx6 * in6, Qyy = dm[7] - Sy6 * Sy6 * in6;
+          const double Qzz = dm[8] - Sz6 * Sz6 * in6, Qxy = dm[9] - Sx6 * Sy6 * in6;
+          const double Qxz = dm[10] - Sx6 * Sz6 * in6, Qyz = dm[11] - Sy6 * Sz6 * in6;
+          const double J00 = Qyy + Qzz, J11 = Qxx + Qzz, J22 = Qxx + Qyy;
+          const double J01 = -Qxy, J02 = -Qxz, J12 = -Qyz;
+          const double bx6 = dm[12] - (Sy6 * Dz6 - Sz6 * Dy6) * in6;
+          const double by6 = dm[13] - (Sz6 * Dx6 - Sx6 * Dz6) * in6;
+          const double bz6 = dm[14] - (Sx6 * Dy6 - Sy6 * Dx6) * in6;
+          const double e2 = (double)a.eps * (double)a.eps;
+          const double t = fmax(n6 * e2, (double)kSixDofCond * (J00 + J11 + J22));
+          const double k00 = J00 - t, k11 = J11 - t, k22 = J22 - t;
+          const double m2 = k00 * k11 - J01 * J01;
+          const double m3 = k00 * (k11 * k22 - J12 * J12) - J01 * (J01 * k22 - J12 * J02) +
+                            J02 * (J01 * J12 - k11 * J02);
+          double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+          if (mn >= 3.f && k00 > 0.0 && m2 > 0.0 && m3 > 0.0) {
+            const double c00 = J11 * J22 - J12 * J12, c11 = J00 * J22 - J02 * J02;
+            const double c22 = J00 * J11 - J01 * J01, c01 = J02 * J12 - J01 * J22;
+            const double c02 = J01 * J12 - J02 * J11, c12 = J01 * J02 - J00 * J12;
+            const double id = 1.0 / (J00 * c00 + J01 * c01 + J02 * c02);
+            t0 = (c00 * bx6 + c01 * by6 + c02 * bz6) * id;
+            t1 = (c01 * bx6 + c11 * by6 + c12 * bz6) * id;
+            t2 = (c02 * bx6 + c12 * by6 + c22 * bz6) * id;
+          } else if (mn >= 2.f && J22 > n6 * e2) {
+            t2 = bz6 / J22;
+          }
+          const double gx = Sx6 * in6 + (double)ox_ - (double)dcx;
+          const double gy = Sy6 * in6 + (double)oy_ - (double)dcy;
+          const double gz = Sz6 * in6 + (double)oz_ - (double)dcz;
+          th6[0] = (float)t0;
+          th6[1] = (float)t1;
+          th6[2] = (float)t2;
+          a1 = (float)(Dx6 * in6 - (t1 * gz - t2 * gy));
+          a2 = (float)(Dy6 * in6 - (t2 * gx - t0 * gz));
+          az = (float)(Dz6 * in6 - (t0 * gy - t1 * gx));
+          Dx = (float)Dx6;
+          Dy = (float)Dy6;
+        }
         const float sbx = Dx * inv_n, sby = Dy * inv_n;
         const float Ff = M * __builtin_amdgcn_sqrtf(sbx * sbx + sby * sby) * (inv_dt * inv_dt);
         lam = (a.mu_inf || Ff <= a.mu * F) ? 1.f : a.mu * F * rcp(Ff);
       }
 
       // S8 correction and commit
-      float alpha, sh, ch;
-      if (!__any(!(fabsf(a3) < 0.1f))) {
-        // |a3| < 0.1: asin from its series to float32 precision (the next term
-        // is below 3e-10 relative), and the half-angle rotation |beta| < 0.06
-        // from the sine and cosine series
-        const float x2 = a3 * a3;
-        alpha = a3 * (1.f + x2 * ((1.f / 6.f) + x2 * ((3.f / 40.f) + x2 * (5.f / 112.f))));
-        const float be = -0.5f * lam * alpha, b2 = be * be;
-        sh = be * (1.f - b2 * (1.f / 6.f) * (1.f - b2 * (1.f / 20.f)));
-        ch = 1.f - 0.5f * b2 * (1.f - b2 * (1.f / 12.f) * (1.f - b2 * (1.f / 30.f)));
-      } else {
-        alpha = asinf(fminf(fmaxf(a3, -1.f), 1.f));
-        sin_cos(-0.5f * lam * alpha, &sh, &ch);
-      }
-      float Q2[4];
-      {
+      float c2[3], v2[3], w2[3], Q2[4];
+      if constexpr (!SIX) {
+        float alpha, sh, ch;
+        if (!__any(!(fabsf(a3) < 0.1f))) {
+          // |a3| < 0.1: asin from its series to float32 precision (the next term
+          // is below 3e-10 relative), and the half-angle rotation |beta| < 0.06
+          // from the sine and cosine series
+          const float x2 = a3 * a3;
+          alpha = a3 * (1.f + x2 * ((1.f / 6.f) + x2 * ((3.f / 40.f) + x2 * (5.f / 112.f))));
+          const float be = -0.5f * lam * alpha, b2 = be * be;
+          sh = be * (1.f - b2 * (1.f / 6.f) * (1.f - b2 * (1.f / 20.f)));
+          ch = 1.f - 0.5f * b2 * (1.f - b2 * (1.f / 12.f) * (1.f - b2 * (1.f / 30.f)));
+        } else {
+          alpha = asinf(fminf(fmaxf(a3, -1.f), 1.f));
+          sin_cos(-0.5f * lam * alpha, &sh, &ch);
+        }
         Q2[0] = ch * Q1[0] - sh * Q1[3];
         Q2[1] = ch * Q1[1] - sh * Q1[2];
         Q2[2] = ch * Q1[2] + sh * Q1[1];
         Q2[3] = ch * Q1[3] + sh * Q1[0];
+        // c'' = c + (dt v1 - lam a): the small trial step and correction first,
+        // one rounding onto the position
+        c2[0] = c[0] + (dcx - lam * a1);
+        c2[1] = c[1] + (dcy - lam * a2);
+        c2[2] = c1[2];
+        v2[0] = v1[0] - lam * a1 * inv_dt;
+        v2[1] = v1[1] - lam * a2 * inv_dt;
+        v2[2] = v1[2];
+        w2[0] = w1[0];
+        w2[1] = w1[1];
+        w2[2] = w1[2] - lam * alpha * inv_dt;
+      } else {
+        // back by the capped six-degree motion: displacement lam a, rotation
+        // by lam asin|th| about th/|th| (|th| is the sine of the angle, as a3
+        // of the yaw)
+        const float s2 = th6[0] * th6[0] + th6[1] * th6[1] + th6[2] * th6[2];
+        const float sn = __builtin_amdgcn_sqrtf(s2);
+        const float in = sn > 0.f ? rcp(sn) : 0.f;
+        float alpha, sh, ch;
+        if (!__any(!(sn < 0.1f))) {
+          alpha = sn * (1.f + s2 * ((1.f / 6.f) + s2 * ((3.f / 40.f) + s2 * (5.f / 112.f))));
+          const float be = -0.5f * lam * alpha, b2 = be * be;
+          sh = be * (1.f - b2 * (1.f / 6.f) * (1.f - b2 * (1.f / 20.f)));
+          ch = 1.f - 0.5f * b2 * (1.f - b2 * (1.f / 12.f) * (1.f - b2 * (1.f / 30.f)));
+        } else {
+          alpha = asinf(fminf(sn, 1.f));
+          sin_cos(-0.5f * lam * alpha, &sh, &ch);
+        }
+        const float nx = th6[0] * in, ny = th6[1] * in, nz = th6[2] * in;
+        const float qx = sh * nx, qy = sh * ny, qz = sh * nz;
+        Q2[0] = ch * Q1[0] - qx * Q1[1] - qy * Q1[2] - qz * Q1[3];
+        Q2[1] = ch * Q1[1] + qx * Q1[0] + qy * Q1[3] - qz * Q1[2];
+        Q2[2] = ch * Q1[2] - qx * Q1[3] + qy * Q1[0] + qz * Q1[1];
+        Q2[3] = ch * Q1[3] + qx * Q1[2] - qy * Q1[1] + qz * Q1[0];
+        c2[0] = c[0] + (dcx - lam * a1);
+        c2[1] = c[1] + (dcy - lam * a2);
+        c2[2] = c[2] + (dcz - lam * az);
+        v2[0] = v1[0] - lam * a1 * inv_dt;
+        v2[1] = v1[1] - lam * a2 * inv_dt;
+        v2[2] = v1[2] - lam * az * inv_dt;
+        const float ra = lam * alpha * inv_dt;
+        w2[0] = w1[0] - ra * nx;
+        w2[1] = w1[1] - ra * ny;
+        w2[2] = w1[2] - ra * nz;
       }
-      // c'' = c + (dt v1 - lam a): the small trial step and correction first,
-      // one rounding onto the position
-      const float c2[3] = {c[0] + (dcx - lam * a1), c[1] + (dcy - lam * a2), c1[2]};
-      const float v2[3] = {v1[0] - lam * a1 * inv_dt, v1[1] - lam * a2 * inv_dt, v1[2]};
-      const float w2[3] = {w1[0], w1[1], w1[2] - lam * alpha * inv_dt};
 
       // S9 telemetry and health
       float R2[9];
@@ -859,7 +1035,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
 template <int G, int PPL, int LPL>
 constexpr int kMinWavesPerEU = ((G == 64 && PPL <= 6) || (G == 32 && PPL <= 12 && LPL == 1)) ? 2 : 1;
 
-template <int G, int PPL, int LPL, int MODE, bool BIL = false>
+template <int G, int PPL, int LPL, int MODE, bool BIL = false, bool SIX = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWavesPerEU<G, PPL, LPL>, 8)))
 void step_kernel(const StepArgs a) {
   constexpr int IPW = 64 / G;
@@ -883,7 +1059,7 @@ void step_kernel(const StepArgs a) {
       tb = blockIdx.x;
     }
     if (tb >= a.n_blocks) break;
-    run_block<G, PPL, LPL, MODE, BIL>(a, T[seg], dT[seg], cand[seg], touch[seg], LK[seg], tb,
+    run_block<G, PPL, LPL, MODE, BIL, SIX>(a, T[seg], dT[seg], cand[seg], touch[seg], LK[seg], tb,
                                       seg, sl);
     __syncthreads();
   }
@@ -928,6 +1104,12 @@ hipError_t launch_step(const StepArgs& a, const Shape& s, int grid, hipStream_t 
     else if (a.points_out)                                                             \
       hipLaunchKernelGGL((step_kernel<g, ppl, lpl, kPoints>), dim3(grid), dim3(64), 0,  \
                          stream, a);                                                   \
+    else if (a.hf_bilinear && a.fric6)                                                 \
+      hipLaunchKernelGGL((step_kernel<g, ppl, lpl, kStep, true, true>), dim3(grid),     \
+                         dim3(64), 0, stream, a);                                      \
+    else if (a.fric6)                                                                  \
+      hipLaunchKernelGGL((step_kernel<g, ppl, lpl, kStep, false, true>), dim3(grid),    \
+                         dim3(64), 0, stream, a);                                      \
     else if (a.hf_bilinear)                                                            \
       hipLaunchKernelGGL((step_kernel<g, ppl, lpl, kStep, true>), dim3(grid), dim3(64), 0, \
                          stream, a);                                                   \

@@ -351,6 +351,12 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
     return fail(NPX_EINVAL, "friction_weighting must be 0 or 1");
   if (d->hf_bilinear != 0 && d->hf_bilinear != 1)
     return fail(NPX_EINVAL, "hf_bilinear must be 0 or 1");
+  if (d->friction_6dof != 0 && d->friction_6dof != 1)
+    return fail(NPX_EINVAL, "friction_6dof must be 0 or 1");
+  if (d->friction_6dof && d->friction_weighting)
+    return fail(NPX_EINVAL, "friction_6dof with friction_weighting is not supported: with the "
+                "weight on a set along one line, a point of near-zero force decides the roll "
+                "about that line");
   for (int i = 0; i < d->n_morphs; ++i) {
     npx_status s = check_tables(d->morphs[i], i);
     if (s != NPX_OK) return s;
@@ -600,6 +606,7 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   a.zeta = (float)d->zeta;
   a.eps = (float)d->eps_lsq;
   a.fric_w = d->friction_weighting;
+  a.fric6 = d->friction_6dof;
   a.hf_bilinear = d->hf_bilinear;
   a.hf = w->hf;
   a.hf_nx = d->hf_nx;

@@ -43,7 +43,8 @@ class _WorldDesc(C.Structure):
                 ("n_morphs", C.c_int32), ("morphs", C.POINTER(_MorphTables)),
                 ("instance_morph", C.POINTER(C.c_int32)), ("init_pose", C.POINTER(C.c_float)),
                 ("ctrl", C.POINTER(C.c_float)), ("friction_weighting", C.c_int32),
-                ("hf_bilinear", C.c_int32), ("max_joint_rate", C.c_double)]
+                ("hf_bilinear", C.c_int32), ("max_joint_rate", C.c_double),
+                ("friction_6dof", C.c_int32)]
 
 
 class Launch(C.Structure):
@@ -235,7 +236,8 @@ class World:
                           ctrl.ctypes.data_as(C.POINTER(C.c_float)),
                           int(getattr(p, "friction_weighting", 0)),
                           int(getattr(p, "hf_bilinear", 0)),
-                          float(getattr(p, "max_joint_rate", 0.0)))
+                          float(getattr(p, "max_joint_rate", 0.0)),
+                          int(getattr(p, "friction_6dof", 0)))
         h = C.c_void_p()
         check(lib().npx_create_world(C.byref(desc), C.byref(h)))
         self.h = h

@@ -64,6 +64,14 @@ def test_bad_tables_rejected_before_device_use():
                     inst_morph=w.inst_morph, ctrl=w.ctrl, pose=w.pose)
     with pytest.raises(N.NpxError, match="hf_bilinear"):
         N.World(w6)
+    w6b = W.Workload(params=W.Params(friction_6dof=2), hf=w.hf, morphs=w.morphs,
+                     inst_morph=w.inst_morph, ctrl=w.ctrl, pose=w.pose)
+    with pytest.raises(N.NpxError, match="friction_6dof"):
+        N.World(w6b)
+    w6c = W.Workload(params=W.Params(friction_6dof=True, friction_weighting=True), hf=w.hf,
+                     morphs=w.morphs, inst_morph=w.inst_morph, ctrl=w.ctrl, pose=w.pose)
+    with pytest.raises(N.NpxError, match="friction_6dof with friction_weighting"):
+        N.World(w6c)
     for rate in (-1.0, float("nan")):
         w7 = W.Workload(params=W.Params(max_joint_rate=rate), hf=w.hf, morphs=w.morphs,
                         inst_morph=w.inst_morph, ctrl=w.ctrl, pose=w.pose)

@@ -392,11 +392,14 @@ def _body(gw):
                            gw.read_state(N.F_STEP).astype(np.float32).ravel()])
 
 
-def test_bitwise_chunking_graphs_and_persistence():
+@pytest.mark.parametrize("six", [False, True])
+def test_bitwise_chunking_graphs_and_persistence(six):
     """A trajectory does not depend on chunk length, hipGraph replay or the
-    persistent queue (same lanes per robot): bit-identical states."""
-    say("case: bitwise chunking / graphs / persistent")
+    persistent queue (same lanes per robot): bit-identical states, with the
+    ground-plane and the six-degree friction fit."""
+    say(f"case: bitwise chunking / graphs / persistent, six-degree friction {six}")
     w = W.hexapod_batch(40, seed=11)
+    w.params.friction_6dof = six
     out = []
     for chunk, graph, pers in ((100, 1, 0), (7, 0, 0), (33, 1, 1), (300, 0, 1)):
         with N.World(w) as gw:
@@ -537,6 +540,42 @@ def test_force_weighted_friction_windows():
         gw_u.step_n(600)
         d = np.abs(gw_w.read_state(N.F_COG)[:2] - gw_u.read_state(N.F_COG)[:2]).max()
     assert d > 1e-4, d
+
+
+def test_six_dof_friction_windows():
+    """The friction fit over the full rigid motion in 3-D (rotations about the
+    other two axes as well, the refinement closing Sec. III-C): 32 hexapods on
+    the terrain, 3 windows of 200 frames each against the oracle's six-degree
+    fit, and the option changes the trajectories."""
+    say("case: six-degree friction, 32 hexapods x 3 windows")
+    w = W.hexapod_batch(32, seed=71, hf=W.octave_terrain(7), n_steps=600)
+    w.params.friction_6dof = True
+    ow = O.OracleWorld(w)
+    with N.World(w) as gw:
+        res = run_windows(ow, gw, list(range(32)), starts=[0, 200, 400])
+    assert_windows(res, "six-degree friction", ow)
+    w0 = W.hexapod_batch(32, seed=71, hf=W.octave_terrain(7), n_steps=600)
+    with N.World(w) as gw_6, N.World(w0) as gw_3:
+        gw_6.step_n(600)
+        gw_3.step_n(600)
+        d = np.abs(gw_6.read_state(N.F_COG) - gw_3.read_state(N.F_COG)).max()
+    assert d > 1e-4, d
+
+
+def test_six_dof_uneven_bilinear_windows():
+    """The six-degree fit on uneven random legged robots (legs that lie on the
+    ground give contact sets close to a line) over the bilinear ground, at 32
+    lanes per robot (two links per lane): 24 robots, 2 windows of 200 frames
+    against the oracle."""
+    say("case: six-degree + bilinear, 24 uneven robots x 2 windows")
+    w = W.config3(seed=72, n_inst=24, n_steps=400)
+    w.params.friction_6dof = True
+    w.params.hf_bilinear = True
+    ow = O.OracleWorld(w)
+    with N.World(w) as gw:
+        gw.set_launch(lanes_per_instance=32)
+        res = run_windows(ow, gw, list(range(24)), starts=[0, 200])
+    assert_windows(res, "six-degree uneven bilinear", ow)
 
 
 def test_bilinear_ground_windows():

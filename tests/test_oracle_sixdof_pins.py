@@ -146,8 +146,10 @@ def test_fit_is_covariant_in_its_origin():
 
 
 def test_degenerate_sets_fall_back_to_the_ground_plane_fit():
-    """A set on one line (rotation about it undetermined) and a single point:
-    the ground-plane fit on x, y with the mean vertical slip; no roll, pitch."""
+    """A set on one line (rotation about it undetermined), one within 1 mm of a
+    line over 20 cm (spread ratio under 1e-3) and a single point: the
+    ground-plane fit on x, y with the mean vertical slip; no roll, pitch. 1 cm
+    off the line the rotation is fitted in 3-D."""
     rng = np.random.default_rng(13)
     u = np.array([0.6, 0.8, 0.0])
     s = np.linspace(-0.1, 0.1, 5)
@@ -159,6 +161,15 @@ def test_degenerate_sets_fall_back_to_the_ground_plane_fit():
     np.testing.assert_allclose(a[[0, 1, 5]], a3, rtol=1e-12, atol=1e-18)
     assert abs(a[2] - (dst - src)[:, 2].mean()) < 1e-18
     assert a[3] == 0.0 and a[4] == 0.0
+    # nearly on a line: 1 mm off it over 20 cm, spread ratio below 1e-3
+    near = src + np.outer(np.array([1, -1, 1, -1, 1]) * 1e-3, [0.0, 0.0, 1.0])
+    S = sum(np.dot(e, e) * np.eye(3) - np.outer(e, e) for e in near - near.mean(0))
+    assert O.sym3_min_eig(S) < 1e-3 * np.trace(S) and O.sym3_min_eig(S) > 5 * 1e-8
+    a, k = O.lsq6(near, near + (dst - src))
+    assert k == 3 and a[3] == 0.0 and a[4] == 0.0
+    wide = src + np.outer(np.array([1, -1, 1, -1, 1]) * 1e-2, [0.0, 0.0, 1.0])
+    a, k = O.lsq6(wide, wide + (dst - src))
+    assert k == 6
     one = np.array([[0.1, 0.2, -0.1]])
     a, k = O.lsq6(one, one + [1e-4, -2e-4, 3e-4])
     assert k == 2
@@ -173,6 +184,18 @@ def test_degenerate_sets_fall_back_to_the_ground_plane_fit():
 
 def p6(**kw):
     return W.Params(friction_6dof=True, **kw)
+
+
+def test_six_dof_with_force_weighting_is_refused():
+    """The two refinements are not combined: with the force on points along one
+    line, a point of near-zero force would decide the roll about that line."""
+    ow = scene(box_morph(), [0.0, 0.0, 0.0, 1, 0, 0, 0],
+               params=W.Params(friction_6dof=True, friction_weighting=True))
+    st = ow.init_state(0)
+    with pytest.raises(AssertionError):
+        ow.step(0, st)
+    with pytest.raises(AssertionError):
+        ow.run_batch([st], 3)
 
 
 def test_free_flight_is_the_plain_step():
@@ -277,13 +300,14 @@ def test_rolling_box_is_stopped_only_with_six_dof():
 
 
 def test_six_dof_conditioning_test_logged_and_flipped():
-    """Four resting points at (+-5 cm, +-1e-4 m): the spread tensor's smallest
-    eigenvalue is 4 (1e-4)^2 = W eps^2, on the threshold, so the test is
-    logged as the fit's fragile decision at point -2; with a roll rate about
-    x the full fit stops the roll and the ground-plane branch leaves it."""
+    """Four resting points at (+-5 cm, +-e) with e chosen so that the spread
+    tensor's smallest eigenvalue 4 e^2 is 1e-3 of its trace 8 (0.05^2 + e^2)
+    (the conditioning bound, above W eps^2): the test is logged as the fit's
+    fragile decision at point -2; with a roll rate about x the full fit stops
+    the roll and the ground-plane branch leaves it."""
     from test_oracle_fragile_pins import one_body
     p = p6()
-    e = 1e-4
+    e = math.sqrt(2e-3 * 0.05 ** 2 / (1 - 2e-3))
     pts = [[sx * 0.05, sy * e, 0.0, 0.25] for sx in (-1, 1) for sy in (-1, 1)]
     ow = one_body(pts, [0.0, 0.0, 0.0, 1, 0, 0, 0], params=p)
     st = ow.init_state(0)
