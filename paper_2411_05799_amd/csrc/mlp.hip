@@ -107,13 +107,14 @@ struct GemmArgs {
   int M, N, K;       // multiples of 64, 64, 32
   int k_split;       // K per grid.y slice (multiple of 32)
   const float* bias; // EPI_HID, EPI_OUT: [N]
-  float* C;          // EPI_HID: pre-activations Z; EPI_OUT: output; EPI_DW: partial dW slices
+  float* C;          // EPI_OUT: output; EPI_DW: partial dW slices
+  T* Zt;             // EPI_HID: pre-activations Z, in the operand type (may be null)
   int64_t ldc;
   T* H;              // EPI_HID: activations; EPI_DX: dZ of the layer below
   int64_t ldh;
   T* HT;             // transposed copy of H (may be null)
   int64_t ldht;
-  const float* Zin;  // EPI_DX: pre-activations of the layer below
+  const T* Zin;      // EPI_DX: pre-activations of the layer below
   int64_t ldz;
   float* colsum;     // EPI_DX: per-64-row-tile column sums of dZ, [M/64][N]
   const float* scale;  // EPI_OUT: optional de-normalisation y*scale + shift
@@ -126,10 +127,17 @@ struct GemmArgs {
 // (w/2, w%2) as 2x2 MFMA blocks.  Blocks are renumbered so that the blocks one
 // XCD receives (hardware deals them round-robin over 8 XCDs) are consecutive
 // tiles, which share the A rows in that XCD's L2.
+// LDS of one block: the two staged 64-wide chunks of A and B (BF16), reused
+// after the products as the 64 x 64 FP32 output tile of the epilogue.
+constexpr int GEMM_LDR = 64 + 8;                                  // staged row, elements
+constexpr int GEMM_CT = TILE + 1;  // output tile row, floats (odd: rows and columns conflict-free)
+constexpr int GEMM_SMEM = 2 * 2 * TILE * GEMM_LDR * 2;            // bytes
+static_assert(TILE * GEMM_CT * 4 <= GEMM_SMEM, "output tile fits the staging buffers");
+
 template <class T, int EPI>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<T> g) {
   using M = Mfma<T>;
-  __shared__ float red[64];
+  __shared__ __align__(16) unsigned char smem[GEMM_SMEM];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tiles_n = g.N / TILE;
   int tile = blockIdx.x;
@@ -163,9 +171,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<T> g) {
     // padded to 72 elements (eight lanes reading eight rows touch 32 banks).
     if (kb < ke && (ke - kb) % 64 == 0) {
       staged = true;
-      constexpr int KC = 64, LDR = KC + 8;
-      __shared__ __bf16 As[2][TILE][LDR];
-      __shared__ __bf16 Bs[2][TILE][LDR];
+      constexpr int KC = 64, LDR = GEMM_LDR;
+      auto As = reinterpret_cast<__bf16(*)[TILE][LDR]>(smem);
+      auto Bs = As + 2;
       const int t = threadIdx.x;
       const int mb = mt * TILE, nbase = (tile % tiles_n) * TILE;
       bf16x8 ga[2], gb[2];
@@ -230,67 +238,101 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<T> g) {
   }
 
   // ---- epilogue: acc[i][j][e] is C[m0 + 16i + 4 grp + e][n0 + 16j + r16]
-  float csum[2] = {0.f, 0.f};
-  for (int i = 0; i < 2; ++i) {
-    for (int j = 0; j < 2; ++j) {
-      const int col = n0 + 16 * j + r16;
-      const int row = m0 + 16 * i + 4 * grp;
-      float v[4];
-      for (int e = 0; e < 4; ++e) v[e] = acc[i][j][e];
-      if constexpr (EPI == EPI_DW) {
-        float* c = g.C + (int64_t)blockIdx.y * g.M * g.ldc;
-        for (int e = 0; e < 4; ++e) c[(int64_t)(row + e) * g.ldc + col] = v[e];
-      } else if constexpr (EPI == EPI_OUT) {
-        if (col < g.n_valid) {
-          const float b = g.bias[col];
-          float sc = 1.f, sh = 0.f;
-          if (g.scale) {
-            sc = g.scale[col];
-            sh = g.shift[col];
-          }
-          for (int e = 0; e < 4; ++e)
-            if (row + e < g.m_valid) g.C[(int64_t)(row + e) * g.ldc + col] = (v[e] + b) * sc + sh;
-        }
-      } else {
-        T out[4];
-        if constexpr (EPI == EPI_HID) {
-          const float b = g.bias[col];
-          for (int e = 0; e < 4; ++e) {
-            const float z = v[e] + b;
-            if (g.C) g.C[(int64_t)(row + e) * g.ldc + col] = z;
-            out[e] = to_t<T>(z * sigmoid(z));
-          }
-        } else {  // EPI_DX: dz = dh * silu'(z) with silu'(z) = s (1 + z (1 - s))
-          for (int e = 0; e < 4; ++e) {
-            const float z = g.Zin[(int64_t)(row + e) * g.ldz + col];
-            const float s = sigmoid(z);
-            const float dz = v[e] * (s * (1.f + z * (1.f - s)));
-            csum[j] += dz;
-            out[e] = to_t<T>(dz);
-          }
-        }
-        for (int e = 0; e < 4; ++e) g.H[(int64_t)(row + e) * g.ldh + col] = out[e];
-        if (g.HT) {
-          T* ht = g.HT + (int64_t)col * g.ldht + row;
-          for (int e = 0; e < 4; ++e) ht[e] = out[e];
-        }
-      }
-    }
-  }
-  if constexpr (EPI == EPI_DX) {
-    // column sums over the 64-row tile: 4 rows per lane, 4 lane groups, 2 waves
-    for (int j = 0; j < 2; ++j) {
-      csum[j] += __shfl_xor(csum[j], 16);
-      csum[j] += __shfl_xor(csum[j], 32);
-    }
-    if ((wave >> 1) == 1 && grp == 0)
-      for (int j = 0; j < 2; ++j) red[(wave & 1) * 32 + 16 * j + r16] = csum[j];
-    __syncthreads();
-    if ((wave >> 1) == 0 && grp == 0)
+  if constexpr (EPI == EPI_DW || EPI == EPI_OUT) {
+    for (int i = 0; i < 2; ++i) {
       for (int j = 0; j < 2; ++j) {
         const int col = n0 + 16 * j + r16;
-        g.colsum[(int64_t)mt * g.N + col] = csum[j] + red[(wave & 1) * 32 + 16 * j + r16];
+        const int row = m0 + 16 * i + 4 * grp;
+        float v[4];
+        for (int e = 0; e < 4; ++e) v[e] = acc[i][j][e];
+        if constexpr (EPI == EPI_DW) {
+          float* c = g.C + (int64_t)blockIdx.y * g.M * g.ldc;
+          for (int e = 0; e < 4; ++e) c[(int64_t)(row + e) * g.ldc + col] = v[e];
+        } else {
+          if (col < g.n_valid) {
+            const float b = g.bias[col];
+            float sc = 1.f, sh = 0.f;
+            if (g.scale) {
+              sc = g.scale[col];
+              sh = g.shift[col];
+            }
+            for (int e = 0; e < 4; ++e)
+              if (row + e < g.m_valid) g.C[(int64_t)(row + e) * g.ldc + col] = (v[e] + b) * sc + sh;
+          }
+        }
       }
+    }
+  } else {
+    // Hidden-layer and input-gradient epilogues through LDS: the block's
+    // 64 x 64 result goes to an FP32 tile, then every output (Z, the layer's
+    // values H and their transpose HT) leaves as whole rows of 16-byte stores.
+    // EPI_HID: z = acc + b, H = SiLU(z). EPI_DX: dz = acc silu'(z) with z read
+    // from Zin row by row, then dz's column sums over the tile.
+    auto Ct = reinterpret_cast<float(*)[GEMM_CT]>(smem);
+    __syncthreads();  // the staged chunks are no longer read
+    const int tr = (wave >> 1) * 32, tc = (wave & 1) * 32;  // this wave's quadrant
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
+        for (int e = 0; e < 4; ++e) {
+          float v = acc[i][j][e];
+          if constexpr (EPI == EPI_HID) v += g.bias[n0 + 16 * j + r16];
+          Ct[tr + 16 * i + 4 * grp + e][tc + 16 * j + r16] = v;
+        }
+    __syncthreads();
+    const int t = threadIdx.x;
+    const int mb = mt * TILE, nb = (tile % tiles_n) * TILE;
+    constexpr int VEC = 16 / (int)sizeof(T);
+    constexpr int PER = TILE * TILE / VEC / 256;  // 16-byte pieces per thread
+    typedef T vec_t __attribute__((ext_vector_type(VEC)));
+    if constexpr (EPI == EPI_HID) {
+      if (g.Zt) {  // Z in the operand type, row by row
+        for (int k = 0; k < PER; ++k) {
+          const int piece = t + 256 * k;
+          const int r = piece / (TILE / VEC), cv = (piece % (TILE / VEC)) * VEC;
+          vec_t o;
+          for (int q = 0; q < VEC; ++q) o[q] = to_t<T>(Ct[r][cv + q]);
+          *reinterpret_cast<vec_t*>(g.Zt + (int64_t)(mb + r) * g.ldz + nb + cv) = o;
+        }
+      }
+    } else {
+      // dz in place: Zin read row by row, then its column sums
+      for (int k = 0; k < PER; ++k) {
+        const int piece = t + 256 * k;
+        const int r = piece / (TILE / VEC), cv = (piece % (TILE / VEC)) * VEC;
+        const vec_t z8 = *reinterpret_cast<const vec_t*>(g.Zin + (int64_t)(mb + r) * g.ldz + nb + cv);
+        for (int q = 0; q < VEC; ++q) {
+          const float z = (float)z8[q], sg = sigmoid(z);
+          Ct[r][cv + q] *= sg * (1.f + z * (1.f - sg));
+        }
+      }
+      __syncthreads();
+      if (t < TILE) {
+        float cs = 0.f;
+        for (int r = 0; r < TILE; ++r) cs += Ct[r][t];
+        g.colsum[(int64_t)mt * g.N + nb + t] = cs;
+      }
+    }
+    // H row by row and HT column by column, VEC elements per 16-byte store
+    auto out_val = [&](float v) __attribute__((always_inline)) {
+      if constexpr (EPI == EPI_HID) return v * sigmoid(v);
+      else return v;
+    };
+    for (int k = 0; k < PER; ++k) {
+      const int piece = t + 256 * k;
+      const int r = piece / (TILE / VEC), cv = (piece % (TILE / VEC)) * VEC;
+      vec_t o;
+      for (int q = 0; q < VEC; ++q) o[q] = to_t<T>(out_val(Ct[r][cv + q]));
+      *reinterpret_cast<vec_t*>(g.H + (int64_t)(mb + r) * g.ldh + nb + cv) = o;
+    }
+    if (g.HT) {
+      for (int k = 0; k < PER; ++k) {
+        const int piece = t + 256 * k;
+        const int c = piece / (TILE / VEC), rv = (piece % (TILE / VEC)) * VEC;
+        vec_t o;
+        for (int q = 0; q < VEC; ++q) o[q] = to_t<T>(out_val(Ct[rv + q][c]));
+        *reinterpret_cast<vec_t*>(g.HT + (int64_t)(nb + c) * g.ldht + mb + rv) = o;
+      }
+    }
   }
 }
 
@@ -395,7 +437,7 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(GemmArgs<__bf16> g) {
           __bf16 out[4];
           for (int e = 0; e < 4; ++e) {
             const float z = acc[i][j][4 * q + e] + b;
-            if (g.C) g.C[(int64_t)(row + e) * g.ldc + col] = z;
+            if (g.Zt) g.Zt[(int64_t)(row + e) * g.ldz + col] = (__bf16)z;
             out[e] = (__bf16)(z * sigmoid(z));
           }
           for (int e = 0; e < 4; ++e) g.H[(int64_t)(row + e) * g.ldh + col] = out[e];
@@ -757,6 +799,42 @@ __global__ void adam_kernel(LayerTable t, int update, float* P, const float* G, 
   }
 }
 
+// One training step's parameter update in one pass: the gradient of p as
+// grad_reduce_kernel sums it (same order, so the same bits), kept in G, then
+// Adam as adam_kernel takes it (c1 = 1 - b1^t, c2 = 1 - b2^t), then the
+// operand copies.
+template <class T>
+__global__ void reduce_adam_kernel(LayerTable t, float* G, float* P, float* Mom, float* Vel,
+                                   float lr, float b1, float b2, float eps, float c1, float c2,
+                                   T* Wc, T* WTc) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= t.off[t.n_layers]) return;
+  const int l = layer_of(t, p);
+  const int64_t q = p - t.off[l];
+  const int64_t nw = (int64_t)t.out_p[l] * t.in_p[l];
+  float gr = 0.f;
+  if (q < nw) {
+#pragma unroll 8
+    for (int k = 0; k < t.dw_slices[l]; ++k) gr += t.dwp[l][(int64_t)k * nw + q];
+  } else {
+    const int o = (int)(q - nw);
+#pragma unroll 8
+    for (int k = 0; k < t.db_tiles; ++k) gr += t.dbp[l][(int64_t)k * t.out_p[l] + o];
+  }
+  G[p] = gr;
+  const float m = b1 * Mom[p] + (1.f - b1) * gr;
+  const float v = b2 * Vel[p] + (1.f - b2) * gr * gr;
+  Mom[p] = m;
+  Vel[p] = v;
+  const float w = P[p] - lr * (m / c1) / (sqrtf(v / c2) + eps);
+  P[p] = w;
+  if (q < nw) {
+    const int o = (int)(q / t.in_p[l]), i = (int)(q % t.in_p[l]);
+    Wc[t.woff[l] + q] = to_t<T>(w);
+    WTc[t.woff[l] + (int64_t)i * t.out_p[l] + o] = to_t<T>(w);
+  }
+}
+
 // Between the padded vector and the unpadded flat order (per layer W [out][in]
 // row-major, then b [out]).  dir 0: padded -> flat, 1: flat -> padded.
 __global__ void repack_kernel(LayerTable t, int dir, float* padded, float* flat) {
@@ -835,7 +913,7 @@ struct npx_sur {
   void* X0 = nullptr;
   void* X0T = nullptr;
   std::vector<void*> H, HT;
-  std::vector<float*> Z;
+  std::vector<void*> Z;  // pre-activations, in the operand type
   float* Yhat = nullptr;
   void *dA = nullptr, *dAT = nullptr, *dB = nullptr, *dBT = nullptr;
   std::vector<float*> dwp, dbp;
@@ -992,8 +1070,8 @@ npx_status forward_packed_t(npx_sur* s, int batch, float* final_out, int64_t ld_
     GemmArgs<T> g = gemm_args<T>(prev, ld_prev, wc<T>(s, l), s->tab.in_p[l], Mp, s->hp,
                                  s->tab.in_p[l]);
     g.bias = bias(s, l);
-    g.C = train ? s->Z[l] : nullptr;
-    g.ldc = s->hp;
+    g.Zt = train ? static_cast<T*>(s->Z[l]) : nullptr;
+    g.ldz = s->hp;
     g.H = static_cast<T*>(s->H[l]);
     g.ldh = s->hp;
     g.HT = train ? static_cast<T*>(s->HT[l]) : nullptr;
@@ -1027,7 +1105,8 @@ npx_status forward_packed_t(npx_sur* s, int batch, float* final_out, int64_t ld_
 // batch and the n_out standardised outputs) to loss_out[0].
 template <class T>
 npx_status backward_t(npx_sur* s, const float* x, int64_t ldx, const float* y, int64_t ldy,
-                      const int* rows, int batch, float* loss_out, hipStream_t st) {
+                      const int* rows, int batch, float* loss_out, hipStream_t st,
+                      bool reduce = true) {
   npx_status r = forward_t<T>(s, x, ldx, rows, batch, nullptr, 0, st);
   if (r != NPX_OK) return r;
   const int Mp = round_up(batch, TILE);
@@ -1062,7 +1141,7 @@ npx_status backward_t(npx_sur* s, const float* x, int64_t ldx, const float* y, i
     if (l == 0) break;
     // dZ_{l-1} = (dZ_l * W_l) . silu'(Z_{l-1})
     GemmArgs<T> gx = gemm_args<T>(cur, out_p, wtc<T>(s, l), out_p, Mp, in_p, out_p);
-    gx.Zin = s->Z[l - 1];
+    gx.Zin = static_cast<const T*>(s->Z[l - 1]);
     gx.ldz = s->hp;
     gx.H = static_cast<T*>(nxt);
     gx.ldh = in_p;
@@ -1078,6 +1157,7 @@ npx_status backward_t(npx_sur* s, const float* x, int64_t ldx, const float* y, i
     s->tab.dwp[l] = s->dwp[l];
     s->tab.dbp[l] = s->dbp[l];
   }
+  if (!reduce) return NPX_OK;  // the training step reduces inside its update
   const int blocks = (int)((s->n_pad + 255) / 256);
   hipLaunchKernelGGL(grad_reduce_kernel, dim3(blocks), dim3(256), 0, st, s->tab, s->G);
   HIP_TRY(hipGetLastError());
@@ -1232,7 +1312,7 @@ npx_status npx_sur_create(const npx_sur_desc* d, npx_sur** out) {
     s->Z.assign(s->n_hl, nullptr);
     for (int l = 0; l < s->n_hl; ++l) {
       A(&s->HT[l], Mp * s->hp * s->esz);
-      A(&s->Z[l], Mp * s->hp * 4);
+      A(&s->Z[l], Mp * s->hp * s->esz);
     }
     A(&s->Yhat, Mp * s->out_p * 4);
     A(&s->dA, Mp * wmax * s->esz);
@@ -1387,10 +1467,30 @@ npx_status npx_sur_train_step(npx_sur* s, const float* x, int64_t ldx, const flo
                               int64_t ldy, const int32_t* rows, int64_t batch, double lr,
                               float* loss, void* stream) {
   if (!(lr >= 0)) return fail(NPX_EINVAL, "learning rate must be >= 0");
-  npx_status r = npx_sur_grad(s, x, ldx, y, ldy, rows, batch, loss, nullptr, stream);
+  npx_status r = check_io(s, x, ldx, batch);
+  if (r != NPX_OK) return r;
+  if (!s->training) return fail(NPX_ESTATE, "surrogate was created without training buffers");
+  if (batch < 1) return fail(NPX_EINVAL, "empty batch");
+  if (!y || ldy < s->n_out) return fail(NPX_EINVAL, "bad target buffer or stride");
+  hipStream_t st = (hipStream_t)stream;
+  r = s->precision == NPX_SUR_FP32
+          ? backward_t<float>(s, x, ldx, y, ldy, rows, (int)batch, loss, st, false)
+          : backward_t<__bf16>(s, x, ldx, y, ldy, rows, (int)batch, loss, st, false);
   if (r != NPX_OK) return r;
   s->step += 1;
-  HIP_TRY(refresh(s, 1, (float)lr, (hipStream_t)stream));
+  const float c1 = (float)(1.0 - std::pow(s->b1, s->step));
+  const float c2 = (float)(1.0 - std::pow(s->b2, s->step));
+  const int blocks = (int)((s->n_pad + 255) / 256);
+  if (s->precision == NPX_SUR_FP32)
+    hipLaunchKernelGGL((reduce_adam_kernel<float>), dim3(blocks), dim3(256), 0, st, s->tab, s->G,
+                       s->P, s->Mom, s->Vel, (float)lr, (float)s->b1, (float)s->b2, (float)s->eps,
+                       c1, c2, static_cast<float*>(s->Wc), static_cast<float*>(s->WTc));
+  else
+    hipLaunchKernelGGL((reduce_adam_kernel<__bf16>), dim3(blocks), dim3(256), 0, st, s->tab,
+                       s->G, s->P, s->Mom, s->Vel, (float)lr, (float)s->b1, (float)s->b2,
+                       (float)s->eps, c1, c2, static_cast<__bf16*>(s->Wc),
+                       static_cast<__bf16*>(s->WTc));
+  HIP_TRY(hipGetLastError());
   return NPX_OK;
 }
 
