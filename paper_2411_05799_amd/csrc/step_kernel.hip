@@ -999,27 +999,36 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
 
   // ---- write back
   if (valid && MODE != kPoints) {
+    // The addresses are formed here from fresh copies of the state pointers
+    // and the instance index: formed once in the prologue and kept, they
+    // would be held (spilled) through the whole launch.
     float* so = a.st;
+    int* sp = a.step;
+    int* fp = a.flags;
+    double* tp = a.tele;
+    int iw = inst;
+    asm volatile("" : "+s"(so), "+s"(sp), "+s"(fp), "+s"(tp));
+    asm volatile("" : "+v"(iw));
     if (sl == 0) {
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        so[(size_t)i * I + inst] = c[i];
-        so[(size_t)(7 + i) * I + inst] = v[i];
-        so[(size_t)(10 + i) * I + inst] = w[i];
+        so[(size_t)i * I + iw] = c[i];
+        so[(size_t)(7 + i) * I + iw] = v[i];
+        so[(size_t)(10 + i) * I + iw] = w[i];
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i) so[(size_t)(3 + i) * I + inst] = Q[i];
-      a.step[inst] = n;
-      a.flags[inst] = fl;
+      for (int i = 0; i < 4; ++i) so[(size_t)(3 + i) * I + iw] = Q[i];
+      sp[iw] = n;
+      fp[iw] = fl;
 #pragma unroll
-      for (int i = 0; i < TELE_N; ++i) a.tele[(size_t)i * I + inst] = tele[i];
+      for (int i = 0; i < TELE_N; ++i) tp[(size_t)i * I + iw] = tele[i];
     }
 #pragma unroll
     for (int l = 0; l < LPL; ++l) {
       const int li = sl + l * G;
       if (lj[l]) {
-        so[(size_t)(BODY_ROWS + li - 1) * I + inst] = q[l];
-        so[(size_t)(BODY_ROWS + a.j_max + li - 1) * I + inst] = qp[l];
+        so[(size_t)(BODY_ROWS + li - 1) * I + iw] = q[l];
+        so[(size_t)(BODY_ROWS + a.j_max + li - 1) * I + iw] = qp[l];
       }
     }
   }
