@@ -183,6 +183,9 @@ enum Mode { kStep = 0, kPlace = 1, kPoints = 2 };
 // thinnest spread is at least this fraction of the trace of its spread tensor.
 constexpr float kSixDofCond = 1e-3f;
 
+// XCDs of the MI355X (eight, 32 compute units each).
+constexpr unsigned kXcds = 8;
+
 // LDS rows of one link: [R row 0 | t0], [R row 1 | t1], [R row 2 | t2].
 using LinkT = float4[3];
 
@@ -1065,7 +1068,15 @@ void step_kernel(const StepArgs a) {
       tb = __builtin_amdgcn_readfirstlane(v);
     } else {
       if (it > 0) break;
-      tb = blockIdx.x;
+      // Workgroups go to the chip's XCDs in turn (workgroup b to XCD b mod 8),
+      // and each XCD has its own L2. Block b takes the (b / 8)-th task block of
+      // a contiguous share of its XCD, so the robots of one XCD are adjacent
+      // in the struct-of-arrays state: a cache line of a state row is read
+      // and written by one L2 instead of partly by each of eight. Any grid
+      // size maps one-to-one.
+      const int nb = (int)gridDim.x, x = (int)(blockIdx.x % kXcds);
+      const int q = nb / (int)kXcds, r = nb % (int)kXcds;
+      tb = x * q + (x < r ? x : r) + (int)(blockIdx.x / kXcds);
     }
     if (tb >= a.n_blocks) break;
     run_block<G, PPL, LPL, MODE, BIL, SIX>(a, T[seg], dT[seg], cand[seg], touch[seg], LK[seg], tb,
