@@ -97,7 +97,37 @@ __device__ __forceinline__ float sigmoid_fast(float z) {
   return __builtin_amdgcn_rcpf(1.0f + __expf(-z));
 }
 
-enum Epi { EPI_HID = 0, EPI_OUT = 1, EPI_DX = 2, EPI_DW = 3 };
+// Training noise (optional): noise[r][j] is added to input column c0 + j of
+// batch row r before standardisation (and subtracted from the same target
+// column by the loss).
+struct Noise {
+  const float* v;
+  int64_t ld;
+  int c0, n;
+};
+
+// EPI_LOSS: the output layer of a training pass with the loss in its epilogue.
+enum Epi { EPI_HID = 0, EPI_OUT = 1, EPI_DX = 2, EPI_DW = 3, EPI_LOSS = 4 };
+
+// The loss terms of EPI_LOSS (as the loss kernel takes them).
+template <class T>
+struct LossArgs {
+  const float* y;
+  int64_t ldy;
+  const int* rows;
+  int batch, n_out;
+  const float* y_mean;
+  const float* y_inv_std;
+  float grad_scale;
+  T* dY;
+  int64_t lddy;
+  T* dYT;
+  int64_t lddyt;
+  float* colsum;
+  int ncols;
+  double* partial;
+  Noise nz;
+};
 
 template <class T>
 struct GemmArgs {
@@ -121,6 +151,7 @@ struct GemmArgs {
   const float* shift;
   int n_valid;       // EPI_OUT: columns written
   int m_valid;       // EPI_OUT: rows written
+  LossArgs<T> loss;  // EPI_LOSS
 };
 
 // One block = 4 waves = one 64x64 output tile; wave w owns the 32x32 quadrant
@@ -132,21 +163,21 @@ struct GemmArgs {
 constexpr int GEMM_LDR = 64 + 8;                                  // staged row, elements
 constexpr int GEMM_CT = TILE + 1;  // output tile row, floats (odd: rows and columns conflict-free)
 constexpr int GEMM_SMEM = 2 * 2 * TILE * GEMM_LDR * 2;            // bytes
-static_assert(TILE * GEMM_CT * 4 <= GEMM_SMEM, "output tile fits the staging buffers");
+static_assert(TILE * GEMM_CT * 4 + 256 * 8 <= GEMM_SMEM,
+              "output tile (and the loss epilogue's partial sums) fit the staging buffers");
 
+// One 64 x 64 output tile `tile` of the product over K slice `slice`, with
+// the block's LDS `smem` (GEMM_SMEM bytes).
 template <class T, int EPI>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<T> g) {
+__device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int tile, int slice,
+                                          unsigned char* smem) {
   using M = Mfma<T>;
-  __shared__ __align__(16) unsigned char smem[GEMM_SMEM];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tiles_n = g.N / TILE;
-  int tile = blockIdx.x;
-  const int nb = gridDim.x;
-  if ((nb & 7) == 0) tile = (tile & 7) * (nb >> 3) + (tile >> 3);
   const int mt = tile / tiles_n;
   const int m0 = mt * TILE + (wave >> 1) * 32;
   const int n0 = (tile % tiles_n) * TILE + (wave & 1) * 32;
-  const int kb = blockIdx.y * g.k_split;
+  const int kb = slice * g.k_split;
   const int ke = min(g.K, kb + g.k_split);
   const int r16 = lane & 15, grp = lane >> 4;
 
@@ -238,7 +269,71 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<T> g) {
   }
 
   // ---- epilogue: acc[i][j][e] is C[m0 + 16i + 4 grp + e][n0 + 16j + r16]
-  if constexpr (EPI == EPI_DW || EPI == EPI_OUT) {
+  if constexpr (EPI == EPI_LOSS) {
+    // The block holds every output column of its 64 rows (64 padded outputs):
+    // yhat = acc + b goes through an LDS tile, then the same terms as the
+    // loss kernel: L = mean over valid rows and the n_out columns of
+    // (yhat - y_n)^2, y_n = (y - mean) / std; dL/dyhat row by row and its
+    // transpose, the tile's column sums of it and the block's partial loss.
+    const LossArgs<T>& q = g.loss;
+    auto Ct = reinterpret_cast<float(*)[GEMM_CT]>(smem);
+    double* lsum = reinterpret_cast<double*>(smem + TILE * GEMM_CT * 4);
+    __syncthreads();  // the staged chunks are no longer read
+    const int tr = (wave >> 1) * 32, tc = (wave & 1) * 32;
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
+        for (int e = 0; e < 4; ++e)
+          Ct[tr + 16 * i + 4 * grp + e][tc + 16 * j + r16] =
+              acc[i][j][e] + g.bias[n0 + 16 * j + r16];
+    __syncthreads();
+    const int t = threadIdx.x, c_t = t & 63, r_t = t >> 6;
+    const int r0 = mt * TILE, c0 = (tile % tiles_n) * TILE;
+    const int c = c0 + c_t;
+    const bool cok = c < q.n_out;
+    const bool noisy = q.nz.v && c >= q.nz.c0 && c < q.nz.c0 + q.nz.n;
+    constexpr int RPT = 16;
+    int64_t src[RPT];
+    float yr[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = r0 + r_t + 4 * i;
+      src[i] = r < q.batch ? (q.rows ? (int64_t)q.rows[r] : (int64_t)r) : -1;
+    }
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = r0 + r_t + 4 * i;
+      yr[i] = (src[i] >= 0 && cok) ? q.y[src[i] * q.ldy + c] : 0.f;
+      if (noisy && src[i] >= 0) yr[i] -= q.nz.v[(int64_t)r * q.nz.ld + (c - q.nz.c0)];
+    }
+    const float mu = cok ? q.y_mean[c] : 0.f, is = cok ? q.y_inv_std[c] : 0.f;
+    double l2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int rr = r_t + 4 * i;
+      float d = 0.f;
+      if (src[i] >= 0 && cok) {
+        const float e = Ct[rr][c_t] - (yr[i] - mu) * is;
+        l2 += (double)e * e;
+        d = q.grad_scale * e;
+      }
+      Ct[rr][c_t] = d;
+      q.dY[(int64_t)(r0 + rr) * q.lddy + c] = to_t<T>(d);
+    }
+    lsum[t] = l2;
+    __syncthreads();
+    for (int cc = r_t; cc < 64; cc += 4)
+      q.dYT[(int64_t)(c0 + cc) * q.lddyt + r0 + c_t] = to_t<T>(Ct[c_t][cc]);
+    if (t < 64) {
+      float sum = 0.f;
+      for (int rr = 0; rr < 64; ++rr) sum += Ct[rr][t];
+      q.colsum[(int64_t)mt * q.ncols + c0 + t] = sum;
+    }
+    for (int w = 128; w > 0; w >>= 1) {
+      if (t < w) lsum[t] += lsum[t + w];
+      __syncthreads();
+    }
+    if (t == 0) q.partial[(int64_t)(tile % tiles_n) * (g.M / TILE) + mt] = lsum[0];
+  } else if constexpr (EPI == EPI_DW || EPI == EPI_OUT) {
     for (int i = 0; i < 2; ++i) {
       for (int j = 0; j < 2; ++j) {
         const int col = n0 + 16 * j + r16;
@@ -246,7 +341,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<T> g) {
         float v[4];
         for (int e = 0; e < 4; ++e) v[e] = acc[i][j][e];
         if constexpr (EPI == EPI_DW) {
-          float* c = g.C + (int64_t)blockIdx.y * g.M * g.ldc;
+          float* c = g.C + (int64_t)slice * g.M * g.ldc;
           for (int e = 0; e < 4; ++e) c[(int64_t)(row + e) * g.ldc + col] = v[e];
         } else {
           if (col < g.n_valid) {
@@ -333,6 +428,37 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<T> g) {
         *reinterpret_cast<vec_t*>(g.HT + (int64_t)(nb + c) * g.ldht + mb + rv) = o;
       }
     }
+  }
+}
+
+// Blocks of one launch are renumbered so that the blocks one XCD receives
+// (the hardware deals them round-robin over 8 XCDs) are consecutive tiles,
+// which share the A rows in that XCD's L2 (when the count divides by 8).
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  return (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
+}
+
+template <class T, int EPI>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<T> g) {
+  __shared__ __align__(16) unsigned char smem[GEMM_SMEM];
+  gemm_tile<T, EPI>(g, xcd_tile(blockIdx.x, gridDim.x), blockIdx.y, smem);
+}
+
+// The two products of one backward layer in one launch: they read the same
+// dZ_l and are independent, so the input-gradient tiles (blocks [0, n_dx))
+// and the weight-gradient tiles and slices (the rest, tile-major within a
+// slice) run side by side instead of in two launches of a few hundred
+// latency-bound blocks each.
+template <class T>
+__global__ __launch_bounds__(256) void gemm_pair_kernel(GemmArgs<T> dx, GemmArgs<T> dw, int n_dx,
+                                                        int dw_tiles) {
+  __shared__ __align__(16) unsigned char smem[GEMM_SMEM];
+  const int b = blockIdx.x;
+  if (b < n_dx) {
+    gemm_tile<T, EPI_DX>(dx, xcd_tile(b, n_dx), 0, smem);
+  } else {
+    const int q = b - n_dx;
+    gemm_tile<T, EPI_DW>(dw, q % dw_tiles, q / dw_tiles, smem);
   }
 }
 
@@ -604,15 +730,6 @@ __global__ __launch_bounds__(512) void mlp_fused_kernel(FusedArgs f) {
 
 // ---- layer-0 input: gather rows, standardise, pad, write X and X^T ---------
 // Block: 64 rows x 64 columns through an LDS tile.
-// Training noise (optional): noise[r][j] is added to input column nc0 + j of
-// batch row r before standardisation (and subtracted from the same target
-// column by the loss kernel).
-struct Noise {
-  const float* v;
-  int64_t ld;
-  int c0, n;
-};
-
 template <class T>
 __global__ __launch_bounds__(256) void pack_input_kernel(
     const float* __restrict__ x, int64_t ldx, const int* __restrict__ rows, int batch, int n_in,
@@ -653,69 +770,7 @@ __global__ __launch_bounds__(256) void pack_input_kernel(
   for (int cc = tr; cc < 64; cc += 4) XT[(int64_t)(c0 + cc) * ldXT + r0 + tc] = to_t<T>(tile[tc][cc]);
 }
 
-// ---- loss: L = mean over valid rows and the n_out columns of (yhat - y_n)^2,
-// y_n = (y - mean) / std.  Writes dL/dyhat (and its transpose), per-tile column
-// sums of it (the output bias gradient) and per-block partial losses.  Block:
-// 64 rows x 64 columns.
-template <class T>
-__global__ __launch_bounds__(256) void loss_kernel(
-    const float* __restrict__ yhat, int64_t ldyh, const float* __restrict__ y, int64_t ldy,
-    const int* __restrict__ rows, int batch, int n_out, const float* __restrict__ y_mean,
-    const float* __restrict__ y_inv_std, float grad_scale, T* dY, int64_t lddy, T* dYT,
-    int64_t lddyt, float* colsum, int ncols, double* partial, Noise nz) {
-  __shared__ float tile[64][65];
-  __shared__ double lsum[256];
-  const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
-  const int tc = threadIdx.x & 63, tr = threadIdx.x >> 6;
-  const int c = c0 + tc;
-  const bool cok = c < n_out;
-  const bool noisy = nz.v && c >= nz.c0 && c < nz.c0 + nz.n;
-  // as in the input packing: all gathers and loads issued before first use
-  constexpr int RPT = 16;
-  int64_t src[RPT];
-  float yr[RPT], yh[RPT];
-#pragma unroll
-  for (int i = 0; i < RPT; ++i) {
-    const int r = r0 + tr + 4 * i;
-    src[i] = r < batch ? (rows ? (int64_t)rows[r] : (int64_t)r) : -1;
-  }
-#pragma unroll
-  for (int i = 0; i < RPT; ++i) {
-    const int r = r0 + tr + 4 * i;
-    const bool ok = src[i] >= 0 && cok;
-    yr[i] = ok ? y[src[i] * ldy + c] : 0.f;
-    yh[i] = ok ? yhat[(int64_t)r * ldyh + c] : 0.f;
-    if (noisy && src[i] >= 0) yr[i] -= nz.v[(int64_t)r * nz.ld + (c - nz.c0)];
-  }
-  const float mu = cok ? y_mean[c] : 0.f, is = cok ? y_inv_std[c] : 0.f;
-  double l2 = 0.0;
-#pragma unroll
-  for (int i = 0; i < RPT; ++i) {
-    const int rr = tr + 4 * i;
-    float d = 0.f;
-    if (src[i] >= 0 && cok) {
-      const float e = yh[i] - (yr[i] - mu) * is;
-      l2 += (double)e * e;
-      d = grad_scale * e;
-    }
-    tile[rr][tc] = d;
-    dY[(int64_t)(r0 + rr) * lddy + c] = to_t<T>(d);
-  }
-  lsum[threadIdx.x] = l2;
-  __syncthreads();
-  for (int cc = tr; cc < 64; cc += 4) dYT[(int64_t)(c0 + cc) * lddyt + r0 + tc] = to_t<T>(tile[tc][cc]);
-  if (threadIdx.x < 64) {
-    float sum = 0.f;
-    for (int rr = 0; rr < 64; ++rr) sum += tile[rr][threadIdx.x];
-    colsum[(int64_t)blockIdx.x * ncols + c0 + threadIdx.x] = sum;
-  }
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) lsum[threadIdx.x] += lsum[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = lsum[0];
-}
-
+// ---- the loss's partial sums (the output layer's epilogue writes one per block)
 __global__ void loss_final_kernel(const double* partial, int n, double inv_count, float* out) {
   __shared__ double s[256];
   double a = 0.0;
@@ -803,10 +858,25 @@ __global__ void adam_kernel(LayerTable t, int update, float* P, const float* G, 
 // grad_reduce_kernel sums it (same order, so the same bits), kept in G, then
 // Adam as adam_kernel takes it (c1 = 1 - b1^t, c2 = 1 - b2^t), then the
 // operand copies.
+// Block 0 also sums the loss kernel's partial losses (`n_part` of them, the
+// same order as loss_final_kernel) into loss_out[0] when loss_out is set.
 template <class T>
-__global__ void reduce_adam_kernel(LayerTable t, float* G, float* P, float* Mom, float* Vel,
-                                   float lr, float b1, float b2, float eps, float c1, float c2,
-                                   T* Wc, T* WTc) {
+__global__ __launch_bounds__(256) void reduce_adam_kernel(
+    LayerTable t, float* G, float* P, float* Mom, float* Vel, float lr, float b1, float b2,
+    float eps, float c1, float c2, T* Wc, T* WTc, const double* loss_part, int n_part,
+    double inv_count, float* loss_out) {
+  if (blockIdx.x == 0 && loss_out) {
+    __shared__ double s[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n_part; i += 256) acc += loss_part[i];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) loss_out[0] = (float)(s[0] * inv_count);
+  }
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= t.off[t.n_layers]) return;
   const int l = layer_of(t, p);
@@ -914,7 +984,6 @@ struct npx_sur {
   void* X0T = nullptr;
   std::vector<void*> H, HT;
   std::vector<void*> Z;  // pre-activations, in the operand type
-  float* Yhat = nullptr;
   void *dA = nullptr, *dAT = nullptr, *dB = nullptr, *dBT = nullptr;
   std::vector<float*> dwp, dbp;
   double* loss_part = nullptr;
@@ -976,6 +1045,22 @@ hipError_t launch_gemm(const GemmArgs<T>& g, int slices, hipStream_t st) {
   return hipGetLastError();
 }
 
+// The input-gradient product `dx` (one slice) and the weight-gradient product
+// `dw` (in `slices` K slices) of one backward layer, as one launch.
+template <class T>
+hipError_t launch_gemm_pair(const GemmArgs<T>& dx, const GemmArgs<T>& dw, int slices,
+                            hipStream_t st) {
+  auto ok = [](const GemmArgs<T>& g, int sl) {
+    return !(g.M % TILE || g.N % TILE || g.K % KSTEP || g.k_split % KSTEP ||
+             (int64_t)g.k_split * sl < g.K);
+  };
+  if (!ok(dx, 1) || !ok(dw, slices) || dx.k_split < dx.K) return hipErrorInvalidValue;
+  const int n_dx = (dx.M / TILE) * (dx.N / TILE), dw_tiles = (dw.M / TILE) * (dw.N / TILE);
+  hipLaunchKernelGGL((gemm_pair_kernel<T>), dim3(n_dx + dw_tiles * slices), dim3(256), 0, st, dx,
+                     dw, n_dx, dw_tiles);
+  return hipGetLastError();
+}
+
 template <class T>
 GemmArgs<T> gemm_args(const void* A, int64_t lda, const void* B, int64_t ldb, int M, int N, int K) {
   GemmArgs<T> g{};
@@ -1003,7 +1088,8 @@ inline const float* bias(const npx_sur* s, int l) {
 }
 
 // Forward pass over `batch` gathered rows.  final_out == nullptr: training
-// pass (pre-activations, transposed copies, normalised output in Yhat); else
+// pass through the hidden layers (pre-activations and transposed copies; the
+// training pass runs the output layer with the loss in its epilogue); else
 // the de-normalised prediction goes to final_out.
 template <class T>
 npx_status forward_packed_t(npx_sur* s, int batch, float* final_out, int64_t ld_out,
@@ -1080,23 +1166,17 @@ npx_status forward_packed_t(npx_sur* s, int batch, float* final_out, int64_t ld_
     prev = s->H[l];
     ld_prev = s->hp;
   }
+  if (train) return NPX_OK;  // the training pass runs the output layer with its loss
   const int L = s->n_layers - 1;
   GemmArgs<T> g = gemm_args<T>(prev, ld_prev, wc<T>(s, L), s->tab.in_p[L], Mp, s->out_p,
                                s->tab.in_p[L]);
   g.bias = bias(s, L);
-  if (train) {
-    g.C = s->Yhat;
-    g.ldc = s->out_p;
-    g.n_valid = s->out_p;
-    g.m_valid = Mp;
-  } else {
-    g.C = final_out;
-    g.ldc = ld_out;
-    g.n_valid = s->n_out;
-    g.m_valid = batch;
-    g.scale = s->y_std;
-    g.shift = s->y_mean;
-  }
+  g.C = final_out;
+  g.ldc = ld_out;
+  g.n_valid = s->n_out;
+  g.m_valid = batch;
+  g.scale = s->y_std;
+  g.shift = s->y_mean;
   HIP_TRY((launch_gemm<T, EPI_OUT>(g, 1, st)));
   return NPX_OK;
 }
@@ -1113,16 +1193,38 @@ npx_status backward_t(npx_sur* s, const float* x, int64_t ldx, const float* y, i
   const int tiles_m = Mp / TILE;
   const int L = s->n_layers - 1;
   {
-    const float scale = 2.0f / ((float)batch * (float)s->n_out);
-    hipLaunchKernelGGL((loss_kernel<T>), dim3(tiles_m, s->out_p / TILE), dim3(256), 0, st, s->Yhat,
-                       (int64_t)s->out_p, y, ldy, rows, batch, s->n_out, s->y_mean, s->y_inv,
-                       scale, static_cast<T*>(s->dA), (int64_t)s->out_p, static_cast<T*>(s->dAT),
-                       (int64_t)Mp, s->dbp[L], s->out_p, s->loss_part, s->noise);
-    HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, st, s->loss_part,
-                       tiles_m * (s->out_p / TILE),
-                       1.0 / ((double)batch * s->n_out), loss_out ? loss_out : s->loss_tmp);
-    HIP_TRY(hipGetLastError());
+    // the output layer with the loss in its epilogue: dL/dyhat (and its
+    // transpose), the output bias gradient's tile sums, the partial losses
+    const void* hin = s->n_hl > 0 ? s->H[s->n_hl - 1] : s->X0;
+    const int64_t ld_in = s->n_hl > 0 ? s->hp : s->in_p0;
+    GemmArgs<T> g = gemm_args<T>(hin, ld_in, wc<T>(s, L), s->tab.in_p[L], Mp, s->out_p,
+                                 s->tab.in_p[L]);
+    g.bias = bias(s, L);
+    LossArgs<T>& q = g.loss;
+    q.y = y;
+    q.ldy = ldy;
+    q.rows = rows;
+    q.batch = batch;
+    q.n_out = s->n_out;
+    q.y_mean = s->y_mean;
+    q.y_inv_std = s->y_inv;
+    q.grad_scale = 2.0f / ((float)batch * (float)s->n_out);
+    q.dY = static_cast<T*>(s->dA);
+    q.lddy = s->out_p;
+    q.dYT = static_cast<T*>(s->dAT);
+    q.lddyt = Mp;
+    q.colsum = s->dbp[L];
+    q.ncols = s->out_p;
+    q.partial = s->loss_part;
+    q.nz = s->noise;
+    HIP_TRY((launch_gemm<T, EPI_LOSS>(g, 1, st)));
+    // the training step sums the partial losses inside its update
+    if (reduce) {
+      hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, st, s->loss_part,
+                         tiles_m * (s->out_p / TILE), 1.0 / ((double)batch * s->n_out),
+                         loss_out ? loss_out : s->loss_tmp);
+      HIP_TRY(hipGetLastError());
+    }
   }
   void *cur = s->dA, *curT = s->dAT, *nxt = s->dB, *nxtT = s->dBT;
   for (int l = L; l >= 0; --l) {
@@ -1136,10 +1238,12 @@ npx_status backward_t(npx_sur* s, const float* x, int64_t ldx, const float* y, i
     const int used = (Mp + gw.k_split - 1) / gw.k_split;
     gw.C = s->dwp[l];
     gw.ldc = in_p;
-    HIP_TRY((launch_gemm<T, EPI_DW>(gw, used, st)));
     s->tab.dw_slices[l] = used;
-    if (l == 0) break;
-    // dZ_{l-1} = (dZ_l * W_l) . silu'(Z_{l-1})
+    if (l == 0) {
+      HIP_TRY((launch_gemm<T, EPI_DW>(gw, used, st)));
+      break;
+    }
+    // dZ_{l-1} = (dZ_l * W_l) . silu'(Z_{l-1}), in the same launch as dW_l
     GemmArgs<T> gx = gemm_args<T>(cur, out_p, wtc<T>(s, l), out_p, Mp, in_p, out_p);
     gx.Zin = static_cast<const T*>(s->Z[l - 1]);
     gx.ldz = s->hp;
@@ -1148,7 +1252,7 @@ npx_status backward_t(npx_sur* s, const float* x, int64_t ldx, const float* y, i
     gx.HT = static_cast<T*>(nxtT);
     gx.ldht = Mp;
     gx.colsum = s->dbp[l - 1];
-    HIP_TRY((launch_gemm<T, EPI_DX>(gx, 1, st)));
+    HIP_TRY((launch_gemm_pair<T>(gx, gw, used, st)));
     std::swap(cur, nxt);
     std::swap(curT, nxtT);
   }
@@ -1314,7 +1418,6 @@ npx_status npx_sur_create(const npx_sur_desc* d, npx_sur** out) {
       A(&s->HT[l], Mp * s->hp * s->esz);
       A(&s->Z[l], Mp * s->hp * s->esz);
     }
-    A(&s->Yhat, Mp * s->out_p * 4);
     A(&s->dA, Mp * wmax * s->esz);
     A(&s->dAT, Mp * wmax * s->esz);
     A(&s->dB, Mp * wmax * s->esz);
@@ -1481,15 +1584,19 @@ npx_status npx_sur_train_step(npx_sur* s, const float* x, int64_t ldx, const flo
   const float c1 = (float)(1.0 - std::pow(s->b1, s->step));
   const float c2 = (float)(1.0 - std::pow(s->b2, s->step));
   const int blocks = (int)((s->n_pad + 255) / 256);
+  const int n_part = (round_up((int)batch, TILE) / TILE) * (s->out_p / TILE);
+  const double inv_count = 1.0 / ((double)batch * s->n_out);
+  float* lo = loss ? loss : s->loss_tmp;
   if (s->precision == NPX_SUR_FP32)
     hipLaunchKernelGGL((reduce_adam_kernel<float>), dim3(blocks), dim3(256), 0, st, s->tab, s->G,
                        s->P, s->Mom, s->Vel, (float)lr, (float)s->b1, (float)s->b2, (float)s->eps,
-                       c1, c2, static_cast<float*>(s->Wc), static_cast<float*>(s->WTc));
+                       c1, c2, static_cast<float*>(s->Wc), static_cast<float*>(s->WTc),
+                       s->loss_part, n_part, inv_count, lo);
   else
     hipLaunchKernelGGL((reduce_adam_kernel<__bf16>), dim3(blocks), dim3(256), 0, st, s->tab,
                        s->G, s->P, s->Mom, s->Vel, (float)lr, (float)s->b1, (float)s->b2,
                        (float)s->eps, c1, c2, static_cast<__bf16*>(s->Wc),
-                       static_cast<__bf16*>(s->WTc));
+                       static_cast<__bf16*>(s->WTc), s->loss_part, n_part, inv_count, lo);
   HIP_TRY(hipGetLastError());
   return NPX_OK;
 }
