@@ -90,6 +90,15 @@ int npx_create_point(npx_morph* m, double x, double y, double z, double mass);
 /* 8 corner points; w along x, h along z, d along y, centre (x, y, z). */
 int npx_create_box(npx_morph* m, double w, double h, double d, double x, double y, double z,
                    double mass);
+/* The same box with its two faces normal to z (bottom and top) each carrying a
+ * grid_nx x grid_ny lattice of points that spans the face, corners included
+ * (2 * grid_nx * grid_ny points, the mass spread equally). Contact is found at
+ * mass points only (Sec. III-A), so a box resting on uneven ground with its 8
+ * corners alone is held at the corners; the lattice lets the face between them
+ * touch. grid 0, 0 is npx_create_box; otherwise both counts must lie in
+ * [2, 64] (else NPX_EINVAL). Returns the body id or a negative status. */
+int npx_create_box_grid(npx_morph* m, double w, double h, double d, double x, double y, double z,
+                        double mass, int grid_nx, int grid_ny);
 /* ring_pts points on each end cap ring of radius rr (mode 0). */
 int npx_create_cylinder(npx_morph* m, double x1, double y1, double z1, double x2, double y2,
                         double z2, double rr, double mass, int ring_pts);

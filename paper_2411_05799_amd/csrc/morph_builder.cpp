@@ -185,6 +185,24 @@ int npx_create_box(npx_morph* m, double w, double h, double d, double x, double 
   return add_body(m, b);
 }
 
+int npx_create_box_grid(npx_morph* m, double w, double h, double d, double x, double y, double z,
+                        double mass, int grid_nx, int grid_ny) {
+  if (grid_nx == 0 && grid_ny == 0) return npx_create_box(m, w, h, d, x, y, z, mass);
+  if (!m || !(w >= 0 && h >= 0 && d >= 0 && mass >= 0) || grid_nx < 2 || grid_ny < 2 ||
+      grid_nx > 64 || grid_ny > 64)
+    return bad(NPX_EINVAL, "bad box grid (0, 0 or both in [2, 64])");
+  Body b;
+  b.ref = {x, y, z};
+  b.orient = M3::eye();
+  for (int sz = -1; sz <= 1; sz += 2)
+    for (int j = 0; j < grid_ny; ++j)
+      for (int i = 0; i < grid_nx; ++i)
+        b.local.push_back({w * ((double)i / (grid_nx - 1) - 0.5),
+                           d * ((double)j / (grid_ny - 1) - 0.5), sz * h / 2});
+  b.mass = mass;
+  return add_body(m, b);
+}
+
 int npx_create_cylinder(npx_morph* m, double x1, double y1, double z1, double x2, double y2,
                         double z2, double rr, double mass, int ring_pts) {
   if (!m || !(rr >= 0 && mass >= 0) || ring_pts < 1) return bad(NPX_EINVAL, "bad cylinder");

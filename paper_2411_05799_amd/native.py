@@ -111,6 +111,7 @@ def lib():
         L.npx_simplify_mode.argtypes = [vp, C.c_int]
         L.npx_create_point.argtypes = [vp, d, d, d, d]
         L.npx_create_box.argtypes = [vp, d, d, d, d, d, d, d]
+        L.npx_create_box_grid.argtypes = [vp, d, d, d, d, d, d, d, C.c_int, C.c_int]
         L.npx_create_cylinder.argtypes = [vp, d, d, d, d, d, d, d, d, C.c_int]
         L.npx_create_sphere.argtypes = [vp, d, d, d, d, d]
         L.npx_create_ray.argtypes = [vp, d, d, d, d, d, d]
@@ -135,7 +136,7 @@ def lib():
         L.npx_gp_run.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int32, C.c_int32, C.c_float, vp]
         L.npx_gp_run.restype = C.c_int
         for name in ("npx_morph_new", "npx_simplify_mode", "npx_create_point", "npx_create_box",
-                     "npx_create_cylinder", "npx_create_sphere", "npx_create_ray",
+                     "npx_create_box_grid", "npx_create_cylinder", "npx_create_sphere", "npx_create_ray",
                      "npx_connect_bodies", "npx_create_joint", "npx_set_joint_limits",
                      "npx_move_body", "npx_rotate_body", "npx_get_max_body_id",
                      "npx_finalize_construction", "npx_morph_get_tables", "npx_morph_joint_index"):
@@ -488,7 +489,10 @@ class MorphBuilder:
     def create_point(self, x, y, z, m):
         return self._call(lib().npx_create_point(self.h, x, y, z, m))
 
-    def create_box(self, w, h, d, x, y, z, m):
+    def create_box(self, w, h, d, x, y, z, m, grid_nx=0, grid_ny=0):
+        if grid_nx or grid_ny:
+            return self._call(lib().npx_create_box_grid(self.h, w, h, d, x, y, z, m,
+                                                        int(grid_nx), int(grid_ny)))
         return self._call(lib().npx_create_box(self.h, w, h, d, x, y, z, m))
 
     def create_cylinder(self, x1, y1, z1, x2, y2, z2, rr, m, ring_pts=8):

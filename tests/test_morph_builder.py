@@ -26,6 +26,43 @@ def test_box_corners_and_mass():
     np.testing.assert_allclose(t.points[:, 3], 0.1, atol=1e-7)
 
 
+def test_box_grid_lattice_faces_and_mass():
+    b = N.MorphBuilder()
+    i = b.create_box(0.3, 0.04, 0.2, 1.0, 2.0, 3.0, 1.2, grid_nx=4, grid_ny=3)
+    assert i == 0
+    b.finalize_construction()
+    t = b.tables()
+    assert t.n_points == 2 * 4 * 3 and t.n_links == 1
+    p = t.points[:, :3].astype(np.float64)
+    np.testing.assert_allclose(np.sort(np.unique(np.round(p[:, 0], 6))),
+                               1.0 + np.linspace(-0.15, 0.15, 4), atol=1e-6)
+    np.testing.assert_allclose(np.sort(np.unique(np.round(p[:, 1], 6))),
+                               2.0 + np.linspace(-0.1, 0.1, 3), atol=1e-6)
+    np.testing.assert_allclose(np.sort(np.unique(np.round(p[:, 2], 6))), [2.98, 3.02], atol=1e-6)
+    assert (np.abs(p[:, 2] - 2.98) < 1e-6).sum() == 12     # bottom face lattice
+    np.testing.assert_allclose(t.points[:, 3], 1.2 / 24, atol=1e-7)
+    # the eight corners of the plain box are among the lattice's points
+    b0 = N.MorphBuilder()
+    b0.create_box(0.3, 0.04, 0.2, 1.0, 2.0, 3.0, 1.2)
+    b0.finalize_construction()
+    corners = b0.tables().points[:, :3].astype(np.float64)
+    for c in corners:
+        assert np.min(np.abs(p - c).max(axis=1)) < 1e-6
+
+
+def test_box_grid_zero_is_the_plain_box_and_bad_grids_fail():
+    b1, b2 = N.MorphBuilder(), N.MorphBuilder()
+    b1.create_box(0.2, 0.05, 0.1, 0.5, 0.0, 0.1, 0.8)
+    assert N.lib().npx_create_box_grid(b2.h, 0.2, 0.05, 0.1, 0.5, 0.0, 0.1, 0.8, 0, 0) == 0
+    b1.finalize_construction()
+    b2.finalize_construction()
+    np.testing.assert_array_equal(b1.tables().points, b2.tables().points)
+    b3 = N.MorphBuilder()
+    for nx, ny in ((1, 3), (3, 1), (0, 4), (65, 2), (-2, -2)):
+        with pytest.raises(N.NpxError):
+            b3.create_box(0.2, 0.05, 0.1, 0, 0, 0, 1.0, grid_nx=nx, grid_ny=ny)
+
+
 def test_rotate_is_fixed_axis_rpy_about_reference_and_move_places_it():
     a, be, g = 0.3, -0.7, 1.1
     b = N.MorphBuilder()
