@@ -194,6 +194,27 @@ typedef struct {
                                       (when the force sits on points along one
                                       line, a point of near-zero force would
                                       decide the roll about it), are rejected */
+  void* ext_device_buffers[4];     /* optional caller-owned device memory (a torch
+                                      tensor's storage, say) that holds the world's
+                                      state in place of its own allocation, so the
+                                      caller reads it with no copy; a NULL entry is
+                                      allocated by the world:
+                                      [0] float [13 + 2 J_max][n_instances]: CoG,
+                                          quaternion, velocity, angular velocity,
+                                          joint angles, joint angles before the last
+                                          update (NPX_F_BODY, NPX_F_JOINT,
+                                          NPX_F_JOINT_PREV one after the other);
+                                      [1] int32 [n_instances] frame counters;
+                                      [2] int32 [n_instances] health flags;
+                                      [3] double [4][n_instances] telemetry sums.
+                                      Each must be device memory of the current
+                                      device, 16-byte aligned, inside one
+                                      allocation that holds the bytes named (else
+                                      NPX_EINVAL). The caller keeps it alive and
+                                      unmoved until npx_destroy_world, which does
+                                      not free it. npx_create_world writes the
+                                      start state into it; after an npx_step_n has
+                                      completed on its stream it holds that state. */
 } npx_world_desc;
 
 typedef struct npx_world npx_world;

@@ -62,7 +62,8 @@ struct npx_world {
   double dt = 0, mu = 0;
   int K = 1;
 
-  // device buffers
+  // device buffers (st, step, flags, tele may be the caller's: ext_state)
+  bool ext_state[4] = {false, false, false, false};
   float* st = nullptr;
   int* step = nullptr;
   int* flags = nullptr;
@@ -514,10 +515,36 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
 #define ALLOC(p, n)                                                                    \
   if (dalloc(&(p), (n)) != hipSuccess)                                                 \
     return cleanup_fail(fail(NPX_ENOMEM, "device allocation of %s failed", #p));
-  ALLOC(w->st, rows * I);
-  ALLOC(w->step, I);
-  ALLOC(w->flags, I);
-  ALLOC(w->tele, I * npx::TELE_N);
+  // the state buffers: the caller's device memory where given, else the world's
+  {
+    const size_t need[4] = {rows * I * sizeof(float), I * sizeof(int), I * sizeof(int),
+                            I * npx::TELE_N * sizeof(double)};
+    void** dst[4] = {reinterpret_cast<void**>(&w->st), reinterpret_cast<void**>(&w->step),
+                     reinterpret_cast<void**>(&w->flags), reinterpret_cast<void**>(&w->tele)};
+    for (int k = 0; k < 4; ++k) {
+      void* p = d->ext_device_buffers[k];
+      if (!p) continue;
+      hipPointerAttribute_t at{};
+      void* base = nullptr;
+      size_t size = 0;
+      if ((reinterpret_cast<uintptr_t>(p) & 15u) != 0 ||
+          hipPointerGetAttributes(&at, p) != hipSuccess || at.type != hipMemoryTypeDevice ||
+          at.device != w->device || hipMemGetAddressRange(&base, &size, p) != hipSuccess ||
+          static_cast<char*>(p) + need[k] > static_cast<char*>(base) + size) {
+        (void)hipGetLastError();
+        return cleanup_fail(fail(NPX_EINVAL,
+                                 "ext_device_buffers[%d]: not 16-byte aligned device memory of "
+                                 "this device holding %zu bytes",
+                                 k, need[k]));
+      }
+      *dst[k] = p;
+      w->ext_state[k] = true;
+    }
+  }
+  if (!w->ext_state[0]) ALLOC(w->st, rows * I);
+  if (!w->ext_state[1]) ALLOC(w->step, I);
+  if (!w->ext_state[2]) ALLOC(w->flags, I);
+  if (!w->ext_state[3]) ALLOC(w->tele, I * npx::TELE_N);
   ALLOC(w->inst_morph_d, I);
   ALLOC(w->morph_info, info.size());
   ALLOC(w->morph_mass, mass.size());
@@ -663,6 +690,10 @@ void npx_destroy_world(npx_world* w) {
   if (w->has_last_stream) (void)hipStreamSynchronize(w->last_stream);
   w->drop_graphs();
   if (w->capture_stream) (void)hipStreamDestroy(w->capture_stream);
+  if (w->ext_state[0]) w->st = nullptr;  // the caller's memory
+  if (w->ext_state[1]) w->step = nullptr;
+  if (w->ext_state[2]) w->flags = nullptr;
+  if (w->ext_state[3]) w->tele = nullptr;
   void* bufs[] = {w->st, w->step, w->flags, w->tele, w->inst_morph_d, w->morph_info,
                   w->morph_mass, w->pts, w->pt_link, w->pt_orig, w->links, w->link_parent,
                   w->fk_task, w->fk_info, w->ctrl, w->hf, w->order, w->queue, w->lp_off,

@@ -44,7 +44,7 @@ class _WorldDesc(C.Structure):
                 ("instance_morph", C.POINTER(C.c_int32)), ("init_pose", C.POINTER(C.c_float)),
                 ("ctrl", C.POINTER(C.c_float)), ("friction_weighting", C.c_int32),
                 ("hf_bilinear", C.c_int32), ("max_joint_rate", C.c_double),
-                ("friction_6dof", C.c_int32)]
+                ("friction_6dof", C.c_int32), ("ext_device_buffers", C.c_void_p * 4)]
 
 
 class Launch(C.Structure):
@@ -209,9 +209,15 @@ def pack_ctrl(ctrl_list, j_max):
 class World:
     """A world on the current HIP device (npx_create_world ... npx_destroy_world)."""
 
-    def __init__(self, w: W.Workload):
+    def __init__(self, w: W.Workload, ext=None):
+        """ext: optional [state, step, flags, tele] torch device tensors (None
+        entries allowed) that hold the world's state in place of its own
+        buffers (npx_world_desc.ext_device_buffers): float32 with
+        (13 + 2 J_max) x I elements, int32 with I, int32 with I and float64
+        with 4 x I, contiguous; kept referenced for the world's life."""
         self.workload = w
         self._keep = []
+        self._ext = None
         morphs = (_MorphTables * len(w.morphs))()
         for i, m in enumerate(w.morphs):
             arrs = (_f32(m.points), _i32(m.pt_link), _i32(m.parent), _f32(m.joint))
@@ -239,6 +245,20 @@ class World:
                           int(getattr(p, "hf_bilinear", 0)),
                           float(getattr(p, "max_joint_rate", 0.0)),
                           int(getattr(p, "friction_6dof", 0)))
+        if ext is not None:
+            I = int(w.n_instances)
+            want = [("float32", (13 + 2 * self.j_max_expected) * I), ("int32", I),
+                    ("int32", I), ("float64", 4 * I)]
+            ext = list(ext) + [None] * (4 - len(ext))
+            for k, (t, (dt, n)) in enumerate(zip(ext[:4], want)):
+                if t is None:
+                    continue
+                if (str(t.dtype) != "torch." + dt or t.numel() != n or not t.is_contiguous()
+                        or t.device.type != "cuda"):
+                    raise ValueError(f"ext[{k}]: need a contiguous {dt} device tensor of {n} "
+                                     f"elements")
+                desc.ext_device_buffers[k] = t.data_ptr()
+            self._ext = ext[:4]
         h = C.c_void_p()
         check(lib().npx_create_world(C.byref(desc), C.byref(h)))
         self.h = h
