@@ -513,6 +513,24 @@ npx_status npx_sur_rollout(npx_sur* net, npx_world* w, float* s, int64_t lds, in
                            int32_t n_calls, float* x_work, int64_t ldx, float* y_work,
                            int64_t ldy, float* tau_acc, void* stream);
 
+/* The controller search's selection step (Sec. V, the surrogate screen): the
+ * fitness of each of n candidates, f_i = (p1_i - p0_i) . h_i - torque_weight *
+ * tau_i / n_calls, where p0_i and p1_i are columns 0 and 1 (the CoG's ground
+ * position) of row i of s0 and s1 (row stride lds floats, >= 2), h_i the unit
+ * start heading (heading [n][2]) and tau_i the torque proxy summed over
+ * n_calls calls; f_i = -inf where flags[i] != 0 (flags may be NULL) or f_i is
+ * not finite, and -0 counts as +0. fitness [n] receives every f_i; top [n_top]
+ * the indices of the n_top largest, best first, equal values by the lower
+ * index (n_top = 0: fitness only). All pointers are device memory; the call is
+ * asynchronous on `stream` and takes its sort's scratch from the stream-
+ * ordered allocator (freed on the stream). Errors: NPX_EINVAL for n < 0,
+ * n > 2^31 - 1, n_top outside [0, n], n_calls < 1, lds < 2 or a NULL buffer
+ * that is needed; NPX_ENOMEM, NPX_EHIP. */
+npx_status npx_sur_screen_select(const float* s0, const float* s1, int64_t lds,
+                                 const float* heading, const float* tau, int32_t n_calls,
+                                 float torque_weight, const int32_t* flags, int64_t n,
+                                 int32_t n_top, float* fitness, int32_t* top, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,7 +16,8 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libnpx.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["step_kernel.hip", "world.hip", "morph_builder.cpp", "mlp.hip", "surrogate.hip", "sensors.hip"]
+SOURCES = ["step_kernel.hip", "world.hip", "morph_builder.cpp", "mlp.hip", "surrogate.hip", "sensors.hip",
+           "screen.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 ARCH = os.environ.get("NPX_OFFLOAD_ARCH", "gfx950")

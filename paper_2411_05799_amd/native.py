@@ -165,6 +165,9 @@ def lib():
         L.npx_sur_advance.argtypes = [vp, vp, i64, vp, i64, i64, vp]
         L.npx_sur_torque.argtypes = [vp, vp, i64, vp, C.c_int, vp]
         L.npx_sur_rollout.argtypes = [vp, vp, vp, i64, i64, C.c_int32, vp, i64, vp, i64, vp, vp]
+        L.npx_sur_screen_select.argtypes = [vp, vp, i64, vp, vp, C.c_int32, C.c_float, vp, i64,
+                                            C.c_int32, vp, vp, vp]
+        L.npx_sur_screen_select.restype = C.c_int
         for name in ("npx_sur_widths", "npx_world_rows", "npx_sur_features", "npx_sur_delta",
                      "npx_sur_advance", "npx_sur_torque", "npx_sur_rollout"):
             getattr(L, name).restype = C.c_int
@@ -677,6 +680,27 @@ class Surrogate:
         check(lib().npx_sur_train_step(self.h, _ptr(x), x.stride(0), _ptr(y), y.stride(0),
                                        _ptr(rows), b, float(lr), _ptr(loss),
                                        C.c_void_p(_stream_handle(stream))))
+
+
+def screen_select(s0, s1, heading, tau, n_calls, torque_weight, flags=None, n_top=0,
+                  stream=None):
+    """Fitness of every candidate and the indices of the n_top best
+    (npx_sur_screen_select): s0, s1 [n, >= 2] state rows (CoG x, y first),
+    heading [n, 2], tau [n] summed torque proxy, flags [n] int32 or None; all
+    device tensors. Returns (fitness [n] float32, top [n_top] int32) tensors."""
+    import torch
+    n = s0.shape[0]
+    if s1.stride(0) != s0.stride(0) or s0.stride(1) != 1 or s1.stride(1) != 1:
+        raise ValueError("s0 and s1 need the same row stride and contiguous rows")
+    fit = torch.empty(n, dtype=torch.float32, device=s0.device)
+    top = torch.empty(max(1, n_top), dtype=torch.int32, device=s0.device)
+    heading = heading.contiguous()
+    tau = tau.contiguous()
+    check(lib().npx_sur_screen_select(_ptr(s0), _ptr(s1), s0.stride(0), _ptr(heading), _ptr(tau),
+                                      int(n_calls), float(torque_weight), _ptr(flags), n,
+                                      int(n_top), _ptr(fit), _ptr(top),
+                                      C.c_void_p(_stream_handle(stream))))
+    return fit, top[:n_top]
 
 
 def norm_stats(x, cols=None, stream=None):
