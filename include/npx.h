@@ -349,7 +349,9 @@ typedef struct {
   int32_t lanes_per_instance; /* 16, 32 or 64 lanes of a wave per robot */
   int32_t persistent;         /* 1: resident grid pulling tasks from a queue */
   int32_t chunk_steps;        /* frames per kernel launch (state stays in registers) */
-  int32_t use_graph;          /* 1: replay chunk launches from cached hipGraphs */
+  int32_t use_graph;          /* 1: replay the launches of a persistent chunk (queue
+                                 reset, then the step) from cached hipGraphs; a chunk
+                                 of one kernel is always launched directly */
   int32_t waves_per_cu;       /* resident waves per CU in persistent mode */
 } npx_launch;
 

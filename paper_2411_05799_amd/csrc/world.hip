@@ -203,7 +203,10 @@ npx_status run_steps(npx_world* w, int64_t n, hipStream_t s) {
   int64_t left = n;
   while (left > 0) {
     const int c = (int)std::min<int64_t>(left, chunk);
-    if (w->launch.use_graph) {
+    // A persistent chunk is two launches (queue reset, step) and is replayed
+    // from a cached graph; a chunk of one kernel is launched directly: as a
+    // one-node graph it took about 10 us more per launch.
+    if (w->launch.use_graph && w->launch.persistent) {
       auto it = w->graphs.find(c);
       if (it == w->graphs.end()) {
         hipGraph_t g = nullptr;
