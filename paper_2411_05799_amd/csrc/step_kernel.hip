@@ -209,13 +209,16 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
   const int I = a.n_inst;
   const int task = tb * IPW + seg;
   const bool valid = task < a.n_tasks;
-  const int inst = valid ? a.order[task] : 0;
-  const int mi = valid ? a.inst_morph[inst] : 0;
-  const int4 info = a.morph_info[mi];
-  const int N = valid ? info.y : 0;
-  const int L = valid ? info.w : 1;
-  const int pt_off = info.x, lk_off = info.z;
-  const float M = a.morph_mass[mi];
+  // the task's instance, morphology offsets, sizes and mass in one load pair
+  // (a past-the-end task reads task 0's and steps nothing)
+  const int4 ta = a.task_info[2 * (valid ? task : 0)];
+  const int4 tc = a.task_info[2 * (valid ? task : 0) + 1];
+  const int inst = valid ? ta.x : 0;
+  const int mi = ta.y;
+  const int N = valid ? tc.x : 0;
+  const int L = valid ? tc.y : 1;
+  const int pt_off = ta.z, lk_off = ta.w;
+  const float M = __int_as_float(tc.z);
   const float invM = rcp(M);
   const float* st = a.st;
 

@@ -81,6 +81,7 @@ struct npx_world {
   float* ctrl = nullptr;
   float* hf = nullptr;
   int* order = nullptr;
+  int4* task_info = nullptr;  // [I][2], see StepArgs::task_info
   int* queue = nullptr;
   int* lp_off = nullptr;   // [total links + 1] point range of each link in lp_idx
   int* lp_idx = nullptr;   // [total points] point indices grouped by link
@@ -562,6 +563,7 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   ALLOC(w->ctrl, I * w->j_max * 3);
   ALLOC(w->hf, (size_t)d->hf_nx * d->hf_ny);
   ALLOC(w->order, I);
+  ALLOC(w->task_info, 2 * I);
   ALLOC(w->queue, 1);
   ALLOC(w->lp_off, lpo.size());
   ALLOC(w->lp_idx, lpi.size());
@@ -593,6 +595,20 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   std::vector<int> ord = task_order(w);
   H2D(w->order, ord.data(), I * sizeof(int));
   {
+    // what the step kernel needs of a task at the start of a launch, in one
+    // place: the instance, its morphology's table offsets and sizes, its mass
+    std::vector<int4> ti(2 * I);
+    for (size_t t = 0; t < I; ++t) {
+      const int inst = ord[t], mi = d->instance_morph[inst];
+      float m = mass[mi];
+      int mb;
+      std::memcpy(&mb, &m, sizeof(int));
+      ti[2 * t] = make_int4(inst, mi, info[mi].x, info[mi].z);
+      ti[2 * t + 1] = make_int4(info[mi].y, info[mi].w, mb, 0);
+    }
+    H2D(w->task_info, ti.data(), ti.size() * sizeof(int4));
+  }
+  {
     std::vector<float> zero(I * w->j_max * 3, 0.f);
     H2D(w->ctrl, d->ctrl ? d->ctrl : zero.data(), zero.size() * sizeof(float));
     std::vector<int> zi(I, 0);
@@ -607,6 +623,7 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   a.n_inst = w->n_inst;
   a.n_tasks = w->n_inst;
   a.order = w->order;
+  a.task_info = w->task_info;
   a.j_max = w->j_max;
   a.max_depth = w->max_depth;
   a.inst_morph = w->inst_morph_d;
@@ -699,7 +716,8 @@ void npx_destroy_world(npx_world* w) {
   if (w->ext_state[3]) w->tele = nullptr;
   void* bufs[] = {w->st, w->step, w->flags, w->tele, w->inst_morph_d, w->morph_info,
                   w->morph_mass, w->pts, w->pt_link, w->pt_orig, w->links, w->link_parent,
-                  w->fk_task, w->fk_info, w->ctrl, w->hf, w->order, w->queue, w->lp_off,
+                  w->fk_task, w->fk_info, w->ctrl, w->hf, w->order, w->task_info, w->queue,
+                  w->lp_off,
                   w->lp_idx, w->sub_mask, w->rays, w->ray_link, w->ray_info,
                   w->foot_pairs, w->foot_info};
   for (void* b : bufs)
