@@ -222,6 +222,24 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
   const float invM = rcp(M);
   const float* st = a.st;
 
+  // ---- per-robot state (same value in every lane of the segment), loaded
+  // first: these loads depend on nothing but the instance, so they are in
+  // flight while the link tables below are read
+  float c[3], Q[4], v[3], w[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    c[i] = st[(size_t)i * I + inst];
+    v[i] = st[(size_t)(7 + i) * I + inst];
+    w[i] = st[(size_t)(10 + i) * I + inst];
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) Q[i] = st[(size_t)(3 + i) * I + inst];
+  int n = a.step[inst];
+  int fl = a.flags[inst];
+  double tele[TELE_N];
+#pragma unroll
+  for (int i = 0; i < TELE_N; ++i) tele[i] = a.tele[(size_t)i * I + inst];
+
   // ---- links of this lane: table row and joint angles (the rest of the link
   // data is read from the cache-resident tables where it is used)
   int lrow[LPL];
@@ -233,9 +251,11 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
     lv[l] = li < L;
     lj[l] = lv[l] && li >= 1;
     lrow[l] = lk_off + (lv[l] ? li : 0);
-    const int j = lj[l] ? li - 1 : 0;
-    q[l] = lj[l] ? st[(size_t)(BODY_ROWS + j) * I + inst] : 0.f;
-    qp[l] = lj[l] ? st[(size_t)(BODY_ROWS + a.j_max + j) * I + inst] : 0.f;
+    const int j = lj[l] ? li - 1 : 0;  // (row 0 of the joints when this lane has none)
+    const float qv = st[(size_t)(BODY_ROWS + j) * I + inst];
+    const float qpv = st[(size_t)(BODY_ROWS + a.j_max + j) * I + inst];
+    q[l] = lj[l] ? qv : 0.f;
+    qp[l] = lj[l] ? qpv : 0.f;
   }
 
   // ---- this lane's link constants, staged in LDS once per launch (each lane
@@ -270,33 +290,25 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
   const int* fk_t = a.fk_task + fki.x + sl;
 
   // ---- the link of each of this lane's points (6 bits per slot, five slots
-  // per register), read once per launch
+  // per register), read once per launch. Every slot's load is issued (a slot
+  // past the robot's points reads its first point's entry, which every
+  // morphology has, and keeps 0), so the loads travel together instead of
+  // one guarded round trip per slot.
   constexpr int PACKW = (PPL + 4) / 5;
   unsigned plk[PACKW];
 #pragma unroll
   for (int w = 0; w < PACKW; ++w) plk[w] = 0u;
+  unsigned lkp[PPL];
 #pragma unroll
   for (int p = 0; p < PPL; ++p) {
     const int k = sl + p * G;
-    const unsigned lk = k < N ? (unsigned)a.pt_link[pt_off + k] : 0u;
+    lkp[p] = (unsigned)a.pt_link[pt_off + (k < N ? k : 0)];
+  }
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) {
+    const unsigned lk = sl + p * G < N ? lkp[p] : 0u;
     plk[p / 5] |= (lk & 63u) << (6 * (p % 5));
   }
-
-  // ---- per-robot state (same value in every lane of the segment)
-  float c[3], Q[4], v[3], w[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    c[i] = st[(size_t)i * I + inst];
-    v[i] = st[(size_t)(7 + i) * I + inst];
-    w[i] = st[(size_t)(10 + i) * I + inst];
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) Q[i] = st[(size_t)(3 + i) * I + inst];
-  int n = a.step[inst];
-  int fl = a.flags[inst];
-  double tele[TELE_N];
-#pragma unroll
-  for (int i = 0; i < TELE_N; ++i) tele[i] = a.tele[(size_t)i * I + inst];
 
   // ---- mass properties and their increments; body points about the CoG are
   // not kept: a point is rebuilt from its construction-frame position and its
