@@ -29,9 +29,9 @@ struct StepArgs {
   int n_inst;             // instances in the world (SoA stride)
   int n_tasks;            // instances stepped by this launch
   int n_blocks;           // ceil(n_tasks / instances per wave)
-  const int* order;       // [n_tasks] instance of each task
   const int4* task_info;  // [n_tasks][2] (instance, morphology, point offset, link offset),
-                          //   (points, links, mass bits, 0) of each task
+                          //   (points, links, mass bits, 0) of each task, costlier
+                          //   robots first
   int j_max;              // joint stride of ctrl and q
   int max_depth;          // deepest link over all morphologies
   const int* inst_morph;  // [n_inst]

@@ -80,7 +80,6 @@ struct npx_world {
   int2* fk_info = nullptr;  // [morphs][3] (first entry, passes) for segments of 16, 32, 64 lanes
   float* ctrl = nullptr;
   float* hf = nullptr;
-  int* order = nullptr;
   int4* task_info = nullptr;  // [I][2], see StepArgs::task_info
   int* queue = nullptr;
   int* lp_off = nullptr;   // [total links + 1] point range of each link in lp_idx
@@ -562,7 +561,6 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   ALLOC(w->fk_info, fki.size());
   ALLOC(w->ctrl, I * w->j_max * 3);
   ALLOC(w->hf, (size_t)d->hf_nx * d->hf_ny);
-  ALLOC(w->order, I);
   ALLOC(w->task_info, 2 * I);
   ALLOC(w->queue, 1);
   ALLOC(w->lp_off, lpo.size());
@@ -593,7 +591,6 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   H2D(w->sub_mask, subm.data(), subm.size() * sizeof(unsigned long long));
   H2D(w->hf, d->hf_heights, (size_t)d->hf_nx * d->hf_ny * sizeof(float));
   std::vector<int> ord = task_order(w);
-  H2D(w->order, ord.data(), I * sizeof(int));
   {
     // what the step kernel needs of a task at the start of a launch, in one
     // place: the instance, its morphology's table offsets and sizes, its mass
@@ -622,7 +619,6 @@ npx_status npx_create_world(const npx_world_desc* d, npx_world** out) {
   npx::StepArgs& a = w->args;
   a.n_inst = w->n_inst;
   a.n_tasks = w->n_inst;
-  a.order = w->order;
   a.task_info = w->task_info;
   a.j_max = w->j_max;
   a.max_depth = w->max_depth;
@@ -716,7 +712,7 @@ void npx_destroy_world(npx_world* w) {
   if (w->ext_state[3]) w->tele = nullptr;
   void* bufs[] = {w->st, w->step, w->flags, w->tele, w->inst_morph_d, w->morph_info,
                   w->morph_mass, w->pts, w->pt_link, w->pt_orig, w->links, w->link_parent,
-                  w->fk_task, w->fk_info, w->ctrl, w->hf, w->order, w->task_info, w->queue,
+                  w->fk_task, w->fk_info, w->ctrl, w->hf, w->task_info, w->queue,
                   w->lp_off,
                   w->lp_idx, w->sub_mask, w->rays, w->ray_link, w->ray_info,
                   w->foot_pairs, w->foot_info};
