@@ -309,6 +309,19 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
     const unsigned lk = sl + p * G < N ? lkp[p] : 0u;
     plk[p / 5] |= (lk & 63u) << (6 * (p % 5));
   }
+  // the construction-frame positions of the first slots' points (the leaf
+  // links' points, which the point order puts first and which are the ones
+  // the detection usually tests), held for the launch
+  constexpr int NRC = PPL < 3 ? PPL : 3;
+  float rc[NRC][3];
+#pragma unroll
+  for (int p = 0; p < NRC; ++p) {
+    const int k = sl + p * G;
+    const float4 r4 = a.pts[pt_off + (k < N ? k : 0)];
+    rc[p][0] = r4.x;
+    rc[p][1] = r4.y;
+    rc[p][2] = r4.z;
+  }
 
   // ---- mass properties and their increments; body points about the CoG are
   // not kept: a point is rebuilt from its construction-frame position and its
@@ -944,7 +957,13 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
       const int lk = (int)((plk[p / 5] >> (6 * (p % 5))) & 63u);
       bool hit = false;
       if (ok && touch[lk]) {
-        const float4 rho = a.pts[kk];
+        float4 rho;
+        if (p < NRC) {
+          const int q = p < NRC ? p : 0;  // (p < NRC here; keeps the index in range)
+          rho = make_float4(rc[q][0], rc[q][1], rc[q][2], 0.f);
+        } else {
+          rho = a.pts[kk];
+        }
         const float4 r0 = T[lk][0], r1 = T[lk][1], r2 = T[lk][2];
         const float rx = r0.x * rho.x + r0.y * rho.y + r0.z * rho.z + r0.w - gb[0];
         const float ry = r1.x * rho.x + r1.y * rho.y + r1.z * rho.z + r1.w - gb[1];
