@@ -949,21 +949,53 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
     tx = 0.f;
     ty = 0.f;
     nc = 0.f;
+    // The first NRC slots (the leaf links' points, whose points are in
+    // registers) are tested without branches: every lane's point is placed
+    // and looked up, and only those of links that may touch count. Their
+    // look-ups then travel together instead of one guarded chain per slot.
+    {
+      float dd[NRC], uxs[NRC], uys[NRC];
+      bool need[NRC];
 #pragma unroll
-    for (int p = 0; p < PPL; ++p) {
+      for (int p = 0; p < NRC; ++p) {
+        const int lk = (int)((plk[p / 5] >> (6 * (p % 5))) & 63u);
+        need[p] = sl + p * G < N && touch[lk] != 0;
+        const float4 r0 = T[lk][0], r1 = T[lk][1], r2 = T[lk][2];
+        const float rx = r0.x * rc[p][0] + r0.y * rc[p][1] + r0.z * rc[p][2] + r0.w - gb[0];
+        const float ry = r1.x * rc[p][0] + r1.y * rc[p][1] + r1.z * rc[p][2] + r1.w - gb[1];
+        const float rz = r2.x * rc[p][0] + r2.y * rc[p][1] + r2.z * rc[p][2] + r2.w - gb[2];
+        const float ux = R[0] * rx + R[1] * ry + R[2] * rz;
+        const float uy = R[3] * rx + R[4] * ry + R[5] * rz;
+        const float uz = R[6] * rx + R[7] * ry + R[8] * rz;
+        const float Px = c[0] + ux, Py = c[1] + uy, Pz = c[2] + uz;
+        dd[p] = hf_at<BIL>(a, Px, Py) - Pz;
+        uxs[p] = ux;
+        uys[p] = uy;
+      }
+#pragma unroll
+      for (int p = 0; p < NRC; ++p) {
+        const bool hit = need[p] && dd[p] > 0.f;
+        if (hit) {
+          kap |= 1u << p;
+          const float vz = v[2] + (w[0] * uys[p] - w[1] * uxs[p]);
+          const float f = fmaxf(a.kn * dd[p] * (1.f - a.zeta * vz), 0.f);
+          F += f;
+          tx += uys[p] * f;
+          ty -= uxs[p] * f;
+          nc += 1.f;
+        }
+        if (__ballot(hit) != 0ull) kap_slots |= 1u << p;
+      }
+    }
+#pragma unroll
+    for (int p = NRC; p < PPL; ++p) {
       const int k = sl + p * G;
       const bool ok = k < N;
       const int kk = pt_off + (ok ? k : 0);
       const int lk = (int)((plk[p / 5] >> (6 * (p % 5))) & 63u);
       bool hit = false;
       if (ok && touch[lk]) {
-        float4 rho;
-        if (p < NRC) {
-          const int q = p < NRC ? p : 0;  // (p < NRC here; keeps the index in range)
-          rho = make_float4(rc[q][0], rc[q][1], rc[q][2], 0.f);
-        } else {
-          rho = a.pts[kk];
-        }
+        const float4 rho = a.pts[kk];
         const float4 r0 = T[lk][0], r1 = T[lk][1], r2 = T[lk][2];
         const float rx = r0.x * rho.x + r0.y * rho.y + r0.z * rho.z + r0.w - gb[0];
         const float ry = r1.x * rho.x + r1.y * rho.y + r1.z * rho.z + r1.w - gb[1];
