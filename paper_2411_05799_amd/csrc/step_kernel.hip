@@ -203,7 +203,7 @@ struct LinkConst {
 
 template <int G, int PPL, int LPL, int MODE, bool BIL, bool SIX>
 __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT, int* cand,
-                                          int* touch, LinkConst* LK, int tb, int seg,
+                                          LinkConst* LK, int tb, int seg,
                                           int sl) {
   constexpr int IPW = 64 / G;
   const int I = a.n_inst;
@@ -924,9 +924,12 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
     // tested (they would add exactly nothing); a point slot no lane of the
     // wave needs is skipped as a whole. The box's lowest world height is its
     // centre's minus sum_j |w_j| e_j, w = the world z row of the link's axes.
+    // The verdicts go round the wave as ballots, one bit per link lane.
+    unsigned long long tmask[LPL];
 #pragma unroll
     for (int l = 0; l < LPL; ++l) {
       const int li = sl + l * G;
+      bool tl = false;
       if (lv[l]) {
         const float4 r0 = T[li][0], r1 = T[li][1], r2 = T[li][2];
         const float4 b0 = LK[li].box0, b1 = LK[li].I1_box;
@@ -939,10 +942,18 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
         const float wy = R[6] * r0.y + R[7] * r1.y + R[8] * r2.y;
         const float wz = R[6] * r0.z + R[7] * r1.z + R[8] * r2.z;
         const float ez = fabsf(wx) * bx[3] + fabsf(wy) * bx[4] + fabsf(wz) * bx[5];
-        touch[li] = (zc - ez <= a.hf_max + 1e-3f) ? 1 : 0;
+        tl = zc - ez <= a.hf_max + 1e-3f;
       }
+      tmask[l] = __ballot(tl);
     }
-    __builtin_amdgcn_wave_barrier();
+    // whether link lk of this lane's robot may touch: its lane's bit
+    auto touches = [&](int lk) __attribute__((always_inline)) {
+      const int l = LPL == 1 ? 0 : lk / G;
+      unsigned long long m = tmask[0];
+#pragma unroll
+      for (int q = 1; q < LPL; ++q) m = l == q ? tmask[q] : m;
+      return ((m >> (seg * G + (lk - l * G))) & 1ull) != 0ull;
+    };
     kap = 0u;
     kap_slots = 0u;
     F = 0.f;
@@ -959,7 +970,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
 #pragma unroll
       for (int p = 0; p < NRC; ++p) {
         const int lk = (int)((plk[p / 5] >> (6 * (p % 5))) & 63u);
-        need[p] = sl + p * G < N && touch[lk] != 0;
+        need[p] = sl + p * G < N && touches(lk);
         const float4 r0 = T[lk][0], r1 = T[lk][1], r2 = T[lk][2];
         const float rx = r0.x * rc[p][0] + r0.y * rc[p][1] + r0.z * rc[p][2] + r0.w - gb[0];
         const float ry = r1.x * rc[p][0] + r1.y * rc[p][1] + r1.z * rc[p][2] + r1.w - gb[1];
@@ -994,7 +1005,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
       const int kk = pt_off + (ok ? k : 0);
       const int lk = (int)((plk[p / 5] >> (6 * (p % 5))) & 63u);
       bool hit = false;
-      if (ok && touch[lk]) {
+      if (ok && touches(lk)) {
         const float4 rho = a.pts[kk];
         const float4 r0 = T[lk][0], r1 = T[lk][1], r2 = T[lk][2];
         const float rx = r0.x * rho.x + r0.y * rho.y + r0.z * rho.z + r0.w - gb[0];
@@ -1121,7 +1132,6 @@ void step_kernel(const StepArgs a) {
   __shared__ LinkT T[IPW][LMAX];
   __shared__ LinkT dT[IPW][LMAX];
   __shared__ int cand[IPW][G * PPL];  // contact points of a frame, compacted
-  __shared__ int touch[IPW][LMAX];    // links that may reach the ground this frame
   __shared__ LinkConst LK[IPW][LMAX]; // constants of every link of the robot
   const int lane = threadIdx.x;
   const int seg = lane / G;
@@ -1145,7 +1155,7 @@ void step_kernel(const StepArgs a) {
       tb = x * q + (x < r ? x : r) + (int)(blockIdx.x / kXcds);
     }
     if (tb >= a.n_blocks) break;
-    run_block<G, PPL, LPL, MODE, BIL, SIX>(a, T[seg], dT[seg], cand[seg], touch[seg], LK[seg], tb,
+    run_block<G, PPL, LPL, MODE, BIL, SIX>(a, T[seg], dT[seg], cand[seg], LK[seg], tb,
                                       seg, sl);
     __syncthreads();
   }
