@@ -288,6 +288,9 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
   const int2 fki = a.fk_info[mi * 3 + (G == 16 ? 0 : (G == 32 ? 1 : 2))];
   const int fk_np = valid ? fki.y : 0;
   const int* fk_t = a.fk_task + fki.x + sl;
+  // the first pass's task of this lane, held for the launch (the later
+  // passes' are loaded one pass ahead)
+  const int fk_r0 = fk_np > 0 ? fk_t[0] : -1;
 
   // ---- the link of each of this lane's points (6 bits per slot, five slots
   // per register), read once per launch. Every slot's load is issued (a slot
@@ -398,7 +401,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
     // and the next pass reads what this one wrote, so program order within the
     // wave is the only ordering needed.
     __builtin_amdgcn_wave_barrier();
-    int fk_next = fk_np > 0 ? fk_t[0] : -1;
+    int fk_next = fk_r0;
     for (int p = 0; __any(p < fk_np); ++p) {
       const int task = fk_next;
       fk_next = p + 1 < fk_np ? fk_t[(p + 1) * G] : -1;
