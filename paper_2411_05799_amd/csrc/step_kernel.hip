@@ -312,10 +312,43 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
     const unsigned lk = sl + p * G < N ? lkp[p] : 0u;
     plk[p / 5] |= (lk & 63u) << (6 * (p % 5));
   }
-  // the construction-frame positions of the first slots' points (the leaf
-  // links' points, which the point order puts first and which are the ones
-  // the detection usually tests), held for the launch
+  // Which of the slots past the first NRC hold points of which links, for
+  // the detection's skip test. First, per link (gathered in the candidate
+  // list's LDS, which no frame has used yet), the slots that hold one of its
+  // points in some lane of the segment; then, transposed by one ballot per
+  // slot, lanes p and 32 + p of the wave hold in smask[l] the low and high
+  // halves of the link lanes (bit layout of the broad phase's ballot
+  // tmask[l]) whose links have points in slot p. A frame's broad-phase
+  // verdicts then decide every slot at once: slot p is tested when a half of
+  // its mask meets the links that may touch.
   constexpr int NRC = PPL < 3 ? PPL : 3;
+  static_assert(PPL <= 32, "slot masks take lanes p and 32 + p");
+  const bool hi_half = threadIdx.x >= 32;
+  unsigned smask[LPL];
+  if constexpr (MODE == kStep) {
+    unsigned* ls = reinterpret_cast<unsigned*>(cand);
+#pragma unroll
+    for (int l = 0; l < LPL; ++l) ls[sl + l * G] = 0u;
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int p = NRC; p < PPL; ++p)
+      if (sl + p * G < N) atomicOr(&ls[lkp[p]], 1u << p);
+    __builtin_amdgcn_wave_barrier();
+    unsigned lsl[LPL];
+#pragma unroll
+    for (int l = 0; l < LPL; ++l) lsl[l] = ls[sl + l * G];
+    __builtin_amdgcn_wave_barrier();
+    const int slot = (int)(threadIdx.x & 31u);
+#pragma unroll
+    for (int l = 0; l < LPL; ++l) {
+      smask[l] = 0u;
+#pragma unroll
+      for (int p = NRC; p < PPL; ++p) {
+        const unsigned long long b = __ballot((lsl[l] >> p) & 1u);
+        smask[l] = slot == p ? (unsigned)(hi_half ? b >> 32 : b) : smask[l];
+      }
+    }
+  }
   float rc[NRC][3];
 #pragma unroll
   for (int p = 0; p < NRC; ++p) {
@@ -949,6 +982,15 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
       }
       tmask[l] = __ballot(tl);
     }
+    // the slots past the first NRC that some lane must test (bit p: slot p)
+    unsigned act;
+    {
+      unsigned meet = 0u;
+#pragma unroll
+      for (int l = 0; l < LPL; ++l) meet |= (unsigned)(hi_half ? tmask[l] >> 32 : tmask[l]) & smask[l];
+      const unsigned long long b = __ballot(meet != 0u);
+      act = (unsigned)b | (unsigned)(b >> 32);
+    }
     // whether link lk of this lane's robot may touch: its lane's bit
     auto touches = [&](int lk) __attribute__((always_inline)) {
       const int l = LPL == 1 ? 0 : lk / G;
@@ -1003,6 +1045,7 @@ __device__ __forceinline__ void run_block(const StepArgs& a, LinkT* T, LinkT* dT
     }
 #pragma unroll
     for (int p = NRC; p < PPL; ++p) {
+      if (!((act >> p) & 1u)) continue;
       const int k = sl + p * G;
       const bool ok = k < N;
       const int kk = pt_off + (ok ? k : 0);
