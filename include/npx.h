@@ -361,8 +361,9 @@ npx_status npx_set_launch(npx_world* w, const npx_launch* cfg);
 
 /* Times `steps` frames of each candidate launch shape on a scratch copy of the
  * state (the world's state is untouched), applies the fastest and writes it to
- * best. times_ms (may be NULL) receives one time per candidate tried, at most
- * max_results; n_tried receives the count. */
+ * best; a persistent shape counts as fastest only when it is more than 3%
+ * faster than every direct one. times_ms (may be NULL) receives one time per
+ * candidate tried, at most max_results; n_tried receives the count. */
 npx_status npx_autotune(npx_world* w, int32_t steps, void* hip_stream, npx_launch* best,
                         npx_launch* tried, float* times_ms, int32_t max_results,
                         int32_t* n_tried);
